@@ -1,0 +1,66 @@
+"""Closed-form solutions that pin the walk (not from any implementation).
+
+All on the unit square [0,1]^2 unless stated; standard Brownian motion with
+generator Laplace/2, so E solves Laplace E = i alpha E (TE mode).
+"""
+import numpy as np
+
+
+def plane_wave(alpha, z):
+    """exp(-sqrt(i alpha) z): the 1-D decaying TE wave; principal root."""
+    return np.exp(-np.sqrt(1j * alpha) * np.asarray(z))
+
+
+def cosh_model(alpha, y, z):
+    """(z + 1) cosh(sqrt(i alpha) (y - 1/2)): the analytic test model of
+    Sec. 4.1 (Eq. 15b) with equal kappa on both sides, shifted to the unit
+    square; Laplace u = i alpha u."""
+    return (np.asarray(z) + 1.0) * np.cosh(np.sqrt(1j * alpha) * (np.asarray(y) - 0.5))
+
+
+def _odd(K):
+    return np.arange(1, K + 1, 2, dtype=np.float64)
+
+
+def g1_const_alpha(alpha, y, z, K=801):
+    """u = 1 on the boundary, Laplace u = i alpha u inside:
+    u = 1 - sum_{m,n odd} 16 i alpha / (pi^2 m n (pi^2 (m^2+n^2) + i alpha))
+              sin(m pi y) sin(n pi z)."""
+    m = _odd(K)[:, None]
+    n = _odd(K)[None, :]
+    coef = 16j * alpha / (np.pi ** 2 * m * n * (np.pi ** 2 * (m ** 2 + n ** 2) + 1j * alpha))
+    y = np.atleast_1d(np.asarray(y, dtype=np.float64))
+    z = np.atleast_1d(np.asarray(z, dtype=np.float64))
+    out = np.empty(y.shape, dtype=np.complex128)
+    for i in range(y.size):
+        out.flat[i] = 1.0 - np.sum(coef * np.sin(m * np.pi * y.flat[i]) * np.sin(n * np.pi * z.flat[i]))
+    return out
+
+
+def mean_exit_time(y, z, K=801):
+    """E[tau] for standard BM leaving the unit square: (1/2) Laplace u = -1,
+    u = sum_{m,n odd} 32 / (pi^4 m n (m^2 + n^2)) sin(m pi y) sin(n pi z)."""
+    m = _odd(K)[:, None]
+    n = _odd(K)[None, :]
+    coef = 32.0 / (np.pi ** 4 * m * n * (m ** 2 + n ** 2))
+    y = np.atleast_1d(np.asarray(y, dtype=np.float64))
+    z = np.atleast_1d(np.asarray(z, dtype=np.float64))
+    out = np.empty(y.shape)
+    for i in range(y.size):
+        out.flat[i] = np.sum(coef * np.sin(m * np.pi * y.flat[i]) * np.sin(n * np.pi * z.flat[i]))
+    return out
+
+
+def halfspace_e0(alpha, z_top):
+    """Air (linear) over a uniform half-space (exp(-k z)), normalised to 1 at
+    z_top < 0: E(z) = E0 exp(-k z) below 0, E0 (1 - k z) above, E0 = 1/(1 - k z_top)."""
+    k = np.sqrt(1j * alpha)
+    return 1.0 / (1.0 - k * z_top)
+
+
+def zscores(mean, exact, se_re, se_im, bias=0.0):
+    """Component z-scores with a stated bias allowance subtracted first."""
+    d = np.asarray(mean) - np.asarray(exact)
+    zr = np.maximum(np.abs(d.real) - bias, 0.0) / np.asarray(se_re)
+    zi = np.maximum(np.abs(d.imag) - bias, 0.0) / np.asarray(se_im)
+    return np.concatenate([np.atleast_1d(zr), np.atleast_1d(zi)])
