@@ -1,0 +1,229 @@
+"""Throughput benchmark of the TE Feynman-Kac interface solver on one MI355X.
+
+One step = one complete interface solve of the quarter-space workload
+(512 interface nodes x 65536 paths, dt = 4e-4, FP32-mixed walk, FP64
+reduction) through the C ABI: table/node upload, persistent walker, per-node
+reduction, results back on the host.  Prints ONE JSON line.
+
+Legs besides the timed workload (each bounded, each can be switched off):
+  --plain   the plain FP64 one-launch-per-node form and the FP64 persistent
+            walker on a node subset (the comparison form);
+  --served  a short Poisson stream of mixed requests through the served
+            mode, for p50/p99 latency;
+  cpu       the FP64 CPU oracle on a bounded sample of the same workload
+            (rank 0 only), as a baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "walk-steps/s + interface nodes/s at 1e-3 rel. MC error; p50/p99 request latency"
+
+# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = non-packed 32-bit VALU
+# lane-operations per second (the issue peak of a VALU-bound kernel).
+CUS, SIMDS, LANES, CLOCK = 256, 4, 16, 2.4e9
+VALU_PEAK = CUS * SIMDS * LANES * CLOCK
+
+# Algorithmic VALU work of one FP32-mixed walk step on the quarter-space
+# model, in full-rate lane-operation slots (quarter-rate ops count 4):
+#   Philox4x32-10, half a call per step: 10 rounds x (2 32x32->64 products at
+#     quarter rate = 8, 2 three-input xors = 2) / 2                      = 50
+#   two uniforms (shift, convert, fma)                                     =  6
+#   Box-Muller (log2, sqrt, sin, cos at quarter rate = 16; 3 multiplies)  = 19
+#   Euler-Maruyama position update (2 fma)                                 =  2
+#   nearer-wall exit test, both axes (~12 compare/select/sub each)         = 24
+#   region lookup, 2 half-planes (2 compares, 2 selects)                   =  4
+#   compensated phase add (TwoSum)                                         =  6
+OPS_PER_STEP = 50 + 6 + 19 + 2 + 24 + 4 + 6   # = 111
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("sdd_kernels.hip", "sdd_device.h"):
+        with open(os.path.join(ROOT, "paper_1603_09311_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload: str):
+    """HBM bytes per walk launch from the committed rocprofv3 counter runs,
+    valid only for the kernel source they were taken with."""
+    path = os.path.join(ROOT, "profiles", f"walk_persist_{workload}_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+def nodes_per_s_at(res, steps_per_s: float, rel_se: float, gnorm: float) -> float:
+    """Interface nodes per second at SE <= rel_se |g|inf: each node needs
+    N = (s / (rel_se |g|inf))^2 paths (s^2 = var_re + var_im) of its measured
+    mean length."""
+    s2 = res["var_re"] + res["var_im"]
+    n_need = np.maximum(s2 / (rel_se * gnorm) ** 2, 1.0)
+    steps_per_path = res["steps"] / np.maximum(res["paths_done"] + res["unfinished"], 1)
+    total_steps = float(np.sum(n_need * steps_per_path))
+    return res["mean"].size / (total_steps / steps_per_s)
+
+
+def cpu_baseline(p, budget_s: float = 15.0):
+    """The FP64 oracle on a bounded sample (a node subset, fewer paths), sized
+    to about budget_s seconds from a short calibration run."""
+    from oracle import oracle as O
+    O.build(force=False)
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    idx = np.arange(0, p.n_nodes, max(1, p.n_nodes // 16))[:16]
+    cal = p.subset(idx).with_paths(8)
+    t0 = time.perf_counter()
+    r, _ = O.solve(cal, threads=threads)
+    t_cal = time.perf_counter() - t0
+    paths = int(max(8, min(65536, 8 * budget_s / max(t_cal, 1e-3))))
+    sample = p.subset(idx).with_paths(paths)
+    t0 = time.perf_counter()
+    r, _ = O.solve(sample, threads=threads)
+    dt = time.perf_counter() - t0
+    steps = float(r["steps"].sum())
+    return {"value": steps / dt, "unit": "walk-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(idx)} of {p.n_nodes} nodes x {paths} paths ({steps:.3e} steps, {dt:.1f} s), FP64"}
+
+
+def served_leg(ctx, n_requests: int, rate_hz: float, paths: int):
+    from paper_1603_09311_amd import workloads as W
+    trace = W.served_trace(n_requests, rate_hz, seed=1, paths_override=paths)
+    lat = []
+    t0 = time.perf_counter()
+    pending = []
+    for t_arr, p in trace:
+        now = time.perf_counter() - t0
+        if t_arr > now:
+            time.sleep(t_arr - now)
+        pending.append((time.perf_counter(), ctx.submit(p)))
+    steps = 0
+    for t_sub, tk in pending:
+        r = ctx.wait(tk, timeout_s=600)
+        lat.append(time.perf_counter() - t_sub)
+        steps += int(r["steps"].sum())
+    wall = time.perf_counter() - t0
+    lat = np.array(lat)
+    return {"requests": n_requests, "rate_hz": rate_hz, "paths_per_node": paths,
+            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "walk_steps_per_s": steps / wall}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--paths", type=int, default=65536, help="paths per node of the timed workload")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--served-requests", type=int, default=24)
+    ap.add_argument("--served-rate", type=float, default=8.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the walk shards by node and path "
+              "tile across GPUs by design, but this build measures one MI355X.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1603_09311_amd import sdd
+    from paper_1603_09311_amd import workloads as W
+
+    prec = W.FP32_MIXED if args.precision == "fp32" else W.FP64
+    p = W.quarter_space(paths=args.paths, precision=prec)
+    ctx = sdd.Context(0, workspace_bytes=64 << 30)
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+
+    for i in range(args.warmup):
+        ctx.solve(p)
+        log(f"warmup {i} done")
+    torch.cuda.synchronize()
+    times, kms, res = [], [], None
+    t_all = time.perf_counter()
+    for i in range(args.steps):
+        t0 = time.perf_counter()
+        res = ctx.solve(p)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        kms.append(ctx.stats()["last_walk_ms"])
+        log(f"step {i}: {times[-1]:.3f} s (walk kernel {kms[-1]:.1f} ms)")
+    elapsed = time.perf_counter() - t_all
+    steps_per_solve = float(res["steps"].sum())
+    ms_per_step = elapsed / args.steps * 1e3
+    value = steps_per_solve / (elapsed / args.steps)
+    walk_ms = float(np.mean(kms))
+    achieved = OPS_PER_STEP * steps_per_solve / (walk_ms * 1e-3)
+    gnorm = p.g_norm
+    nodes_s = nodes_per_s_at(res, value, 1e-3, gnorm)
+    out = {
+        "metric": METRIC, "value": value, "unit": "walk-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if prec == W.FP32_MIXED else "f64", "data": "synthetic",
+        "config": {"workload": "quarter_space_te", "nodes": p.n_nodes, "paths_per_node": args.paths,
+                   "dt": p.dt, "domain": [p.y_lo, p.y_hi, p.z_lo, p.z_hi], "freq_hz": p.freq_hz,
+                   "precision": "fp32_mixed_walk_fp64_reduce" if prec == W.FP32_MIXED else "fp64",
+                   "walk_steps_per_solve": steps_per_solve},
+        "interface_nodes_per_s_at_1e-3": nodes_s,
+        "interface_nodes_per_s_as_run": p.n_nodes / (elapsed / args.steps),
+        "max_rel_se_as_run": float(np.max(res["se"]) / gnorm),
+        "walk_kernel_ms": walk_ms,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
+                     "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK,
+                     "traffic": load_traffic("quarter_space"),
+                     "ops_per_step": OPS_PER_STEP},
+    }
+    st = ctx.stats()
+    out["launch"] = {"blocks": st["last_blocks"], "threads": st["last_threads"]}
+
+    if not args.no_plain:
+        sub = W.quarter_space(paths=args.paths, precision=W.FP64).subset(np.arange(0, 512, 16))
+        r = ctx.solve_plain(sub)
+        t_plain = ctx.stats()["last_walk_ms"]
+        s_plain = float(r["steps"].sum())
+        r64 = ctx.solve(sub)
+        t_p64 = ctx.stats()["last_walk_ms"]
+        sub32 = sub.replace(precision=W.FP32_MIXED)
+        ctx.solve(sub32)
+        t_p32 = ctx.stats()["last_walk_ms"]
+        out["comparison"] = {
+            "subset": f"{sub.n_nodes} nodes x {args.paths} paths",
+            "plain_fp64_walk_steps_per_s": s_plain / (t_plain * 1e-3),
+            "persistent_fp64_walk_steps_per_s": s_plain / (t_p64 * 1e-3),
+            "persistent_fp32_walk_steps_per_s": s_plain / (t_p32 * 1e-3),
+            "fp64_persistent_equals_plain": bool(np.array_equal(r["mean"], r64["mean"])),
+        }
+        log(f"comparison: {out['comparison']}")
+
+    if not args.no_served:
+        out["served"] = served_leg(ctx, args.served_requests, args.served_rate, 4096)
+        log(f"served: {out['served']}")
+        out["p50_ms"] = out["served"]["p50_ms"]
+        out["p99_ms"] = out["served"]["p99_ms"]
+
+    if not args.no_cpu:
+        cb = cpu_baseline(p)
+        out["cpu_baseline"] = cb
+        log(f"cpu baseline: {cb}")
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

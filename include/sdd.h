@@ -1,0 +1,209 @@
+/*
+ * sdd.h -- C ABI of the MI355X (gfx950) Monte-Carlo interface solver for the
+ * 2-D TE magnetotelluric equation.
+ *
+ * Method (Bihlo, Farquharson, Haynes, Loredo-Osti, arXiv:1603.09311):
+ *   TE mode of the quasi-static Maxwell equations (Sec. 2.1, Eq. 1) in model
+ *   length units L:  Laplace(E) = i alpha(y, z) E,  alpha = omega mu0 sigma L^2,
+ *   with Dirichlet data g on the rectangle Omega (Sec. 2.1).  At each
+ *   interface node x the library evaluates the Feynman-Kac representation
+ *   (Sec. 2.2, Eqs. 5a/5b, 7-8)
+ *       E(x) = Exp[ g(X_tau) exp(-i S) ],  S = (1/2) int_0^tau alpha(X_s) ds,
+ *   by Monte-Carlo over Euler-Maruyama Brownian walks (Sec. 3.1, Eq. 13) that
+ *   stop at the first exit from Omega, detected with the Brownian-bridge
+ *   hitting test (Sec. 3.1, Eq. 14, applied to the outer boundary), and
+ *   reduces each node's samples to the MC estimate (Sec. 3.1, estimator) with
+ *   its variance and standard error.
+ *
+ * Conventions: y to the right, z downward; walls are named top (z = z_lo),
+ * right (y = y_hi), bottom (z = z_hi), left (y = y_lo).
+ *
+ * Every call returns an sdd_status; no exception crosses the ABI; a failing
+ * call leaves a thread-local message readable with sdd_last_error().
+ * Ownership: the caller owns every host buffer; inputs are copied before a
+ * call returns; result buffers passed to sdd_submit must stay valid until
+ * sdd_wait/sdd_poll report completion (or cancellation).  Device memory is
+ * the caller's workspace given to sdd_create: the library never allocates
+ * device memory itself, and its HBM admission budget is that workspace.
+ */
+#ifndef SDD_H
+#define SDD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sdd_ctx *sdd_ctx_t;
+typedef uint32_t sdd_model_t;
+typedef uint64_t sdd_ticket_t;
+
+typedef enum {
+    SDD_OK = 0,
+    SDD_E_INVALID = -1,    /* bad argument; see sdd_last_error() */
+    SDD_E_NOMEM = -2,      /* the request does not fit in the workspace */
+    SDD_E_DEVICE = -3,     /* a HIP call failed */
+    SDD_E_BUSY = -4,       /* model in use / ticket not finished */
+    SDD_E_NOTFOUND = -5,   /* unknown model or ticket */
+    SDD_E_TIMEOUT = -6,    /* sdd_wait timed out */
+    SDD_E_CANCELLED = -7   /* the ticket was cancelled */
+} sdd_status;
+
+/* Arithmetic of the walk.  SDD_FP64: every step in FP64 (the plain form,
+ * identical decisions to an FP64 reference on the same streams).
+ * SDD_FP32_MIXED: positions, normals, exit test and region lookup in FP32,
+ * the phase integral in compensated FP32 (hi + lo), the per-path weight and
+ * the per-node reduction in FP64. */
+typedef enum { SDD_FP64 = 0, SDD_FP32_MIXED = 1 } sdd_precision;
+
+/* Conductivity primitives (Sec. 2.2: piecewise-constant sub-domains).
+ * A model is an ordered list; a point belongs to the first primitive that
+ * contains it, else to the background.
+ *   SDD_HALF_Z_LT : z < v[0]                         (e.g. air above z = 0)
+ *   SDD_HALF_Y_LT : y < v[0]
+ *   SDD_BOX       : v[0] <= y < v[1] and v[2] <= z < v[3]
+ *   SDD_TRIANGLE  : closed triangle (v[0],v[1]), (v[2],v[3]), (v[4],v[5]) */
+typedef enum { SDD_HALF_Z_LT = 0, SDD_HALF_Y_LT = 1, SDD_BOX = 2, SDD_TRIANGLE = 3 } sdd_region_kind;
+
+#define SDD_MAX_REGIONS 16
+
+typedef struct {
+    int32_t kind;          /* sdd_region_kind */
+    int32_t reserved;      /* 0 */
+    double v[6];           /* geometry, model length units */
+    double sigma;          /* conductivity, S/m (>= 0; 0 = air) */
+} sdd_region;
+
+/* A conductivity model on Omega = [y_lo, y_hi] x [z_lo, z_hi]. */
+typedef struct {
+    double y_lo, y_hi, z_lo, z_hi;
+    double length_unit_m;      /* metres per model length unit (> 0) */
+    double sigma_background;   /* S/m, >= 0 */
+    uint32_t n_regions;        /* <= SDD_MAX_REGIONS */
+    const sdd_region *regions; /* copied by sdd_model_create */
+} sdd_model_desc;
+
+/* One interface solve: the paper's problem statement (model, frequency,
+ * boundary data, nodes, paths per node, time step) plus the random streams.
+ *   alpha_r = (2 pi freq_hz) mu0 sigma_r L^2 with mu0 = 4 pi 1e-7 H/m, or,
+ *   when freq_hz == 0, alpha_r = alpha_direct * sigma_r (non-dimensional).
+ * Random numbers: Philox4x32-10 keyed by `seed`; the normal pair of step n of
+ * path p at node j comes from the call with counter (n/2, p, j, 2 stream)
+ * (words 0,1 for even n, 2,3 for odd n); the bridge uniforms of step n from
+ * counter (n, p, j, 2 stream + 1).  A node's paths are therefore the same
+ * realisations in every batch, mix, precision and kernel. */
+typedef struct {
+    sdd_model_t model;
+    int32_t precision;          /* sdd_precision */
+    double freq_hz;
+    double alpha_direct;
+    /* Dirichlet data: 4 walls (top, right, bottom, left) x g_samples x
+     * (re, im), each wall sampled at g_samples equispaced points from its
+     * low to its high end (top/bottom along y, left/right along z);
+     * linear interpolation in between. */
+    const double *g_tables;
+    uint32_t g_samples;         /* >= 2 */
+    uint32_t n_nodes;
+    const double *nodes_yz;     /* n_nodes x (y, z), strictly inside Omega */
+    const uint32_t *path_begin; /* nullable: first path index per node (default 0) */
+    const uint32_t *path_count; /* nullable: paths per node (default paths_uniform) */
+    uint32_t paths_uniform;
+    double dt;                  /* Euler-Maruyama step; 7 sqrt(dt) < half the shorter side */
+    uint64_t seed;
+    uint32_t stream;            /* < 2^31 */
+    uint32_t max_steps;         /* proposals per path before it counts as unfinished; 0 = 2e9 */
+    uint32_t flags;             /* 0 */
+    uint32_t reserved;          /* 0 */
+    double target_rel_se;       /* 0: fixed paths.  > 0: a 4096-path pilot per node, then
+                                   extended on the same streams to N = ceil((s/(target*|g|inf))^2)
+                                   (capped at 2^20), s^2 = var_re + var_im of the pilot */
+} sdd_request;
+
+/* Per-path record (node-major, path order), for inspection and tests. */
+typedef struct {
+    double w_re, w_im;   /* g(X_tau) exp(-i S) */
+    double tau;          /* exit-time estimate (n + f) dt; -1 if unfinished */
+    uint32_t steps;      /* proposals drawn */
+    int32_t wall;        /* 0 top, 1 right, 2 bottom, 3 left; -1 unfinished */
+} sdd_path_record;
+
+/* Results per node (arrays of n_nodes rows; every pointer but `mean` is nullable). */
+typedef struct {
+    double *mean;            /* n x 2: re, im */
+    double *var;             /* n x 3: var_re, var_im, cov (divisor N - 1) */
+    double *se;              /* n x 3: se_re, se_im, se = sqrt((var_re + var_im)/N) */
+    uint64_t *paths_done;    /* n: finished paths N */
+    uint64_t *steps;         /* n: proposals drawn, all paths */
+    uint64_t *unfinished;    /* n: paths that reached max_steps */
+    double *mean_exit_time;  /* n */
+    sdd_path_record *path_records; /* sum of path counts; fixed-path requests only */
+} sdd_result;
+
+/* Launch shape of the persistent walker (0 = automatic). */
+typedef struct {
+    uint32_t block_threads;   /* multiple of 64, <= 1024 */
+    uint32_t blocks_per_cu;
+    uint32_t tile_paths;      /* paths per tile (work unit claimed by a wave) */
+    uint32_t slice_iters;     /* served mode: iterations (2 steps) per wave per slice */
+} sdd_tuning;
+
+/* Context on device `device` (HIP ordinal) with a caller-owned device
+ * workspace of workspace_bytes (256-byte aligned) and a HIP stream
+ * (hipStream_t, may be NULL for the default stream). */
+sdd_status sdd_create(int device, void *workspace_dev, size_t workspace_bytes, void *hip_stream,
+                      sdd_ctx_t *out);
+sdd_status sdd_destroy(sdd_ctx_t ctx);
+
+/* Copy a conductivity model into the workspace, where it stays resident
+ * until sdd_model_destroy (SDD_E_BUSY while a submitted request uses it). */
+sdd_status sdd_model_create(sdd_ctx_t ctx, const sdd_model_desc *desc, sdd_model_t *out);
+sdd_status sdd_model_destroy(sdd_ctx_t ctx, sdd_model_t model);
+
+/* Blocking solve of one request by the persistent walker. */
+sdd_status sdd_solve(sdd_ctx_t ctx, const sdd_request *req, sdd_result *res);
+
+/* Blocking solve of n requests with uneven node counts, path counts,
+ * frequencies, models and precisions in one persistent launch. */
+sdd_status sdd_solve_batch(sdd_ctx_t ctx, uint32_t n, const sdd_request *reqs, sdd_result *res);
+
+/* The plain form: FP64, one kernel launch per node, one thread per path,
+ * no refill (req->precision is ignored).  Same streams, same records. */
+sdd_status sdd_solve_plain(sdd_ctx_t ctx, const sdd_request *req, sdd_result *res);
+
+/* Served mode: requests are queued, admitted while the workspace has room,
+ * and walked together in time slices of the persistent kernel (continuous
+ * batching); a request that arrives while others run joins at the next
+ * slice. */
+sdd_status sdd_submit(sdd_ctx_t ctx, const sdd_request *req, sdd_result *res, sdd_ticket_t *out);
+sdd_status sdd_poll(sdd_ctx_t ctx, sdd_ticket_t t, int *done);
+sdd_status sdd_wait(sdd_ctx_t ctx, sdd_ticket_t t, int64_t timeout_ns);   /* < 0: forever */
+sdd_status sdd_cancel(sdd_ctx_t ctx, sdd_ticket_t t);
+
+sdd_status sdd_set_tuning(sdd_ctx_t ctx, const sdd_tuning *t);
+sdd_status sdd_get_tuning(sdd_ctx_t ctx, sdd_tuning *t);
+
+/* Timing of the most recent walk launch on this context, measured with HIP
+ * events on the context's stream around the walk kernel alone. */
+typedef struct {
+    double last_walk_ms;          /* duration of the last walk kernel (persistent or plain) */
+    double last_reduce_ms;        /* duration of the last reduction kernel */
+    uint64_t last_walk_steps;     /* proposals drawn by that walk launch */
+    uint64_t last_walk_paths;     /* paths walked by that launch */
+    uint32_t last_blocks, last_threads;  /* launch shape of the last persistent walk */
+    uint64_t launches;            /* walk launches since sdd_create */
+} sdd_stats;
+
+sdd_status sdd_get_stats(sdd_ctx_t ctx, sdd_stats *out);
+
+/* Bytes of workspace a request needs (tables, nodes, tiles, records). */
+sdd_status sdd_request_footprint(sdd_ctx_t ctx, const sdd_request *req, uint64_t *bytes);
+
+const char *sdd_status_string(sdd_status s);
+const char *sdd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SDD_H */

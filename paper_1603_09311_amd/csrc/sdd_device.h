@@ -1,0 +1,96 @@
+// Device-side data layout shared by the kernels and the host runtime.
+//
+// Everything a wave needs for one request lives in a DevReq that the wave
+// reads with scalar loads (the request index is wave-uniform), so the model,
+// the step size, the phase increments and the Philox key sit in SGPRs and the
+// 64 lanes hold only their walkers' state in VGPRs.
+#pragma once
+#include <stdint.h>
+
+namespace sdd {
+
+constexpr int kMaxPrims = 16;                 // conductivity primitives per model
+constexpr int kMaxRegions = kMaxPrims + 1;    // + background
+constexpr uint32_t kNoRequest = 0xFFFFFFFFu;
+
+enum PrimKind : int32_t { kHalfZ = 0, kHalfY = 1, kBox = 2, kTriangle = 3 };
+
+// Resident conductivity model (workspace copy made by sdd_model_create).
+struct DevModel {
+  int32_t nprims;
+  int32_t pad0[3];
+  int32_t kind[kMaxPrims];
+  double pd[kMaxPrims][6];    // FP64 geometry
+  float pf[kMaxPrims][8];     // FP32 geometry (FP32-mixed walks), padded to 8
+  double sigma[kMaxRegions];  // per region, background last
+  double y_lo, y_hi, z_lo, z_hi, length_unit_m, pad1[3];
+};
+
+// A work unit claimed by a wave: `count` consecutive paths of one node.
+struct DevTile {
+  uint32_t node;
+  uint32_t p0;        // first path index
+  uint32_t count;
+  uint32_t pad;
+  uint64_t rec0;      // record slot of path p0 (request-relative)
+  uint64_t pad1;
+};
+
+// Per-path record, 32 bytes.
+struct PathRec {
+  double w_re, w_im;
+  double tau;          // (n + f) dt, or -1 when unfinished
+  uint32_t steps;      // proposals drawn
+  int32_t wall;        // 0 top, 1 right, 2 bottom, 3 left, -1 unfinished
+};
+
+// Per-node reduction output, 96 bytes.
+struct NodeOut {
+  double mean_re, mean_im, var_re, var_im, cov, se_re, se_im, se, mean_exit_time;
+  uint64_t paths_done, steps, unfinished;
+};
+
+// One node's records for the reduction kernel: up to two segments (the
+// pilot and the extension of a target-SE request), reduced in that order.
+struct NodeJob {
+  const PathRec *recs0;
+  uint64_t count0;
+  const PathRec *recs1;
+  uint64_t count1;
+  NodeOut *out;
+  uint64_t pad;
+};
+
+// Per-request device descriptor.
+struct DevReq {
+  // FP64 numerics
+  double y_lo, y_hi, z_lo, z_hi;
+  double s;            // sqrt(dt)
+  double dt;
+  double thr;          // bridge pre-filter: draw U only if 2 d0 d1 <= thr
+  double pad0;
+  double c[kMaxRegions + 1];   // phase per full step: alpha_r dt / 2 (background at [nprims])
+  // FP32 copies for the mixed walk
+  float fy_lo, fy_hi, fz_lo, fz_hi, fs, fdt, fthr, fpad;
+  float fc[kMaxRegions + 3];
+  // streams and limits
+  uint32_t key0, key1;  // Philox key (seed low, high)
+  uint32_t ctr3;        // 2 * stream
+  uint32_t max_steps;
+  uint32_t precision;   // 0 FP64, 1 FP32-mixed
+  uint32_t n_tiles;
+  uint32_t M;           // g_samples - 1
+  uint32_t nprims;
+  int32_t kind[kMaxPrims];
+  double pd[kMaxPrims][6];    // FP64 geometry of the model's primitives
+  float pf[kMaxPrims][8];     // FP32 geometry, padded to 8 for one scalar load
+  const DevModel *model;      // resident model the primitives were taken from
+  const double *nodes;  // n x (y, z)
+  const double *g;      // 4 x (M + 1) x (re, im)
+  const DevTile *tiles;
+  PathRec *recs;
+  uint32_t *tile_counter;           // next tile to claim
+  unsigned long long *done_counter; // paths completed (finished or capped)
+};
+
+}  // namespace sdd

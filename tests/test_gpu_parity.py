@@ -1,0 +1,292 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Bars:
+  * FP64 walk: identical per-path decisions (steps, exit wall) and weights
+    equal to ~1e-12; per node |E_gpu - E_oracle| <= 1e-9 max(|E_oracle|, SE).
+  * FP32-mixed walk: per node within 4.5 SE of the oracle per component plus
+    a chi-square gate over all components; paired with the FP64 walk on the
+    same streams, the difference is far below SE.
+  * Scheduling never changes a bit: plain == persistent, alone == in a batch,
+    any tile/block shape, served == blocking.
+"""
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from paper_1603_09311_amd import sdd
+from paper_1603_09311_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-9
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    c = sdd.Context(0, workspace_bytes=24 << 30)
+    yield c
+    c.close()
+
+
+def oracle_solve(orc, p, records=False):
+    res, recs = orc.solve(p, records=records)
+    return res, recs
+
+
+def assert_fp64_parity(g, o, tol=TOL_FP64):
+    e_o = o["mean_re"] + 1j * o["mean_im"]
+    scale = np.maximum(np.abs(e_o), o["se"])
+    d = np.abs(g["mean"] - e_o)
+    assert np.all(d <= tol * scale), (d / scale).max()
+    assert np.array_equal(g["paths_done"], o["paths_done"])
+    assert np.array_equal(g["steps"], o["steps"])
+    assert np.array_equal(g["unfinished"], o["unfinished"])
+    for k in ("var_re", "var_im", "cov", "se"):
+        ok = np.isfinite(o[k])
+        assert np.allclose(g[k][ok], o[k][ok], rtol=1e-9, atol=1e-300), k
+    assert np.allclose(g["mean_exit_time"], o["mean_exit_time"], rtol=1e-12)
+
+
+def assert_within_se(g, o, zmax=4.5):
+    e_o = o["mean_re"] + 1j * o["mean_im"]
+    d = g["mean"] - e_o
+    z = np.concatenate([np.abs(d.real) / o["se_re"], np.abs(d.imag) / o["se_im"]])
+    assert z.max() <= zmax, z.max()
+    assert np.sum(z ** 2) <= stats.chi2.ppf(0.999, z.size)
+
+
+def assert_records_match(grec, orec):
+    assert grec.shape == orec.shape
+    assert np.array_equal(grec["steps"], orec["steps"])
+    assert np.array_equal(grec["wall"], orec["wall"])
+    for f in ("w_re", "w_im", "tau"):
+        assert np.allclose(grec[f], orec[f], rtol=1e-11, atol=1e-13), f
+
+
+def small_mixed_model():
+    regions = [W.Region(W.HALF_Z_LT, (0.3,), 0.0), W.Region(W.BOX, (0.5, 0.8, 0.4, 0.7), 5.0),
+               W.Region(W.TRIANGLE, (0.1, 0.5, 0.1, 0.95, 0.45, 0.95), 2.0)]
+    p = W.unit_square(alpha=30.0, g_fn=lambda y, z: np.exp(1j * y) * (1 + z), M=64, dt=1e-3,
+                      nodes=np.array([[0.5, 0.5], [0.02, 0.5], [0.97, 0.03], [0.3, 0.8], [0.6, 0.45],
+                                      [0.2, 0.6], [0.7, 0.35], [0.45, 0.9]]),
+                      paths=200, seed=0x123456789, stream=3)
+    return p.replace(regions=regions, sigma_background=1.0)
+
+
+# ---------------------------------------------------------------------------
+
+def test_records_fp64_match_oracle_path_by_path(ctx, orc):
+    p = small_mixed_model()
+    log(f"records fp64: nodes={p.n_nodes} paths={p.total_paths}")
+    g = ctx.solve(p, precision=sdd.SDD_FP64, records=True)
+    o, orec = oracle_solve(orc, p, records=True)
+    assert_records_match(g["records"], orec)
+    assert_fp64_parity(g, o)
+
+
+def test_plain_equals_persistent_fp64_bitwise(ctx):
+    p = small_mixed_model().with_paths(333)
+    a = ctx.solve(p, precision=sdd.SDD_FP64, records=True)
+    b = ctx.solve_plain(p, records=True)
+    assert a["records"].tobytes() == b["records"].tobytes()
+    assert np.array_equal(a["mean"], b["mean"])
+
+
+def test_unit_square_fp64_parity(ctx, orc):
+    """The homogeneous toy at full size: 8 nodes x 4096 paths, dt = 1e-4."""
+    p = W.unit_square(paths=4096, precision=W.FP64)
+    log("unit square fp64 full size")
+    g = ctx.solve(p)
+    o, _ = oracle_solve(orc, p)
+    assert_fp64_parity(g, o)
+    exact = -0.0021278355286973 - 0.2057296574127508j
+    z = np.abs(g["mean"] - exact) / g["se"]
+    assert z.max() < 4.5
+
+
+def test_unit_square_fp32_within_se(ctx, orc):
+    p = W.unit_square(paths=4096, precision=W.FP32_MIXED)
+    g = ctx.solve(p)
+    o, _ = oracle_solve(orc, p)
+    assert_within_se(g, o)
+    # paired with the FP64 walk on the same streams
+    g64 = ctx.solve(p, precision=sdd.SDD_FP64)
+    assert np.all(np.abs(g["mean"] - g64["mean"]) < 0.2 * g64["se"])
+
+
+def test_g_one_alpha_zero_exact_both_precisions(ctx):
+    p = W.unit_square(alpha=0.0, g_fn=lambda y, z: np.ones_like(y) + 0j, paths=1000, dt=4e-4)
+    for prec in (sdd.SDD_FP64, sdd.SDD_FP32_MIXED):
+        g = ctx.solve(p, precision=prec)
+        assert np.all(g["mean"] == 1.0) and np.all(g["var_re"] == 0.0)
+
+
+def test_quarter_space_subset_fp64_parity(ctx, orc):
+    """Quarter-space geometry (lengths in skin depths, air, two half-spaces),
+    a node subset with fewer paths so the oracle finishes in seconds."""
+    p = W.quarter_space(paths=96, precision=W.FP64, M=4096).subset([0, 37, 128, 255, 256, 300, 383, 511])
+    p = p.replace(path_count=np.array([96, 17, 64, 65, 96, 1, 130, 33], np.uint32))
+    log(f"quarter space subset fp64: {p.total_paths} paths")
+    g = ctx.solve(p, records=True)
+    o, orec = oracle_solve(orc, p, records=True)
+    assert_records_match(g["records"], orec)
+    assert_fp64_parity(g, o)
+
+
+def test_quarter_space_subset_fp32_within_se(ctx, orc):
+    p = W.quarter_space(paths=2048, precision=W.FP32_MIXED, M=4096).subset([10, 100, 200, 260, 400, 500])
+    log(f"quarter space subset fp32: {p.total_paths} paths")
+    g = ctx.solve(p)
+    o, _ = oracle_solve(orc, p)
+    assert_within_se(g, o)
+
+
+def test_block_and_triangle_fp64_parity(ctx, orc):
+    blk = W.block_in_half_space(10.0, paths=64, precision=W.FP64, M=2048).subset([0, 130, 260, 400, 600, 1000])
+    tri = W.triangle_request(5, precision=W.FP64, M=2048)
+    tri = tri.subset(np.arange(0, tri.n_nodes, max(1, tri.n_nodes // 6))[:6]).with_paths(48)
+    for p in (blk, tri):
+        g = ctx.solve(p, records=True)
+        o, orec = oracle_solve(orc, p, records=True)
+        assert_records_match(g["records"], orec)
+        assert_fp64_parity(g, o)
+
+
+def test_batch_equals_alone_bitwise(ctx):
+    """Uneven node counts, path counts, frequencies, models and precisions in
+    one persistent launch: each result is bitwise the one it gets alone."""
+    a = small_mixed_model()
+    b = W.quarter_space(paths=40, precision=W.FP32_MIXED, M=1024).subset(np.arange(0, 512, 37))
+    c = W.block_in_half_space(1.0, paths=24, precision=W.FP64, M=1024).subset(np.arange(0, 1024, 101))
+    d = W.unit_square(paths=777, precision=W.FP32_MIXED, seed=9)
+    batch = ctx.solve_batch([a, b, c, d], records=True)
+    for p, got in zip([a, b, c, d], batch):
+        alone = ctx.solve(p, records=True)
+        assert got["records"].tobytes() == alone["records"].tobytes()
+        assert np.array_equal(got["mean"], alone["mean"]) and np.array_equal(got["se"], alone["se"])
+
+
+def test_launch_shape_does_not_change_a_bit(ctx):
+    p = W.unit_square(paths=1500, precision=W.FP32_MIXED, seed=4)
+    ref = ctx.solve(p, records=True)
+    try:
+        for bt, bpc, tile in [(64, 1, 1), (128, 2, 64), (512, 1, 4096), (256, 3, 100)]:
+            ctx.set_tuning(block_threads=bt, blocks_per_cu=bpc, tile_paths=tile)
+            got = ctx.solve(p, records=True)
+            assert got["records"].tobytes() == ref["records"].tobytes(), (bt, bpc, tile)
+            assert np.array_equal(got["mean"], ref["mean"])
+    finally:
+        ctx.set_tuning()
+
+
+def test_edge_cases(ctx, orc):
+    # no nodes
+    p0 = W.unit_square(paths=4).subset([])
+    g = ctx.solve(p0)
+    assert g["mean"].size == 0
+    # one path: variance undefined (NaN), mean is the path's weight
+    p1 = W.unit_square(paths=1, precision=W.FP64, nodes=np.array([[0.5, 0.5]]))
+    g = ctx.solve(p1, records=True)
+    assert g["paths_done"][0] == 1 and np.isnan(g["var_re"][0])
+    assert g["mean"][0] == complex(g["records"]["w_re"][0], g["records"]["w_im"][0])
+    # ragged path counts and begins (not multiples of 64 or of the tile)
+    pr = W.unit_square(paths=1, precision=W.FP64).replace(
+        path_begin=np.array([0, 5, 1000, 7, 0, 3, 64, 1], np.uint32),
+        path_count=np.array([1, 63, 65, 127, 129, 513, 2, 1000], np.uint32))
+    g = ctx.solve(pr, records=True)
+    o, orec = oracle_solve(orc, pr, records=True)
+    assert_records_match(g["records"], orec)
+    assert_fp64_parity(g, o)
+    # a tiny step cap: unfinished paths counted and left out of the estimate
+    pc = W.unit_square(paths=300, precision=W.FP64, dt=4e-4).replace(max_steps=25)
+    g = ctx.solve(pc, records=True)
+    o, orec = oracle_solve(orc, pc, records=True)
+    assert g["unfinished"].sum() > 0 and np.array_equal(g["unfinished"], o["unfinished"])
+    assert_records_match(g["records"], orec)
+    for prec in (sdd.SDD_FP32_MIXED,):
+        g32 = ctx.solve(pc, precision=prec)
+        assert np.all(g32["paths_done"] + g32["unfinished"] == 300)
+
+
+def test_invalid_requests_rejected(ctx):
+    p = W.unit_square(paths=8)
+    bad = [p.replace(dt=0.0), p.replace(dt=0.02), p.replace(nodes=np.array([[0.0, 0.5]] * 8)),
+           p.replace(nodes=np.array([[0.5, 1.0]] * 8)), p.replace(path_count=np.zeros(8, np.uint32)),
+           p.replace(stream=2 ** 31)]
+    for b in bad:
+        with pytest.raises(sdd.SddError) as e:
+            ctx.solve(b)
+        assert e.value.status == sdd.SDD_E_INVALID
+    with pytest.raises(sdd.SddError) as e:
+        ctx.solve(p, precision=7)
+    assert e.value.status == sdd.SDD_E_INVALID
+
+
+def test_workspace_exhaustion_is_reported():
+    import torch
+    c = sdd.Context(0, workspace_bytes=1 << 20)
+    try:
+        p = W.unit_square(paths=100000)
+        with pytest.raises(sdd.SddError) as e:
+            c.solve(p)
+        assert e.value.status == sdd.SDD_E_NOMEM
+        g = c.solve(W.unit_square(paths=64))   # still usable
+        assert g["paths_done"].sum() == 8 * 64
+    finally:
+        c.close()
+    torch.cuda.synchronize()
+
+
+def test_target_rel_se_pilot_and_extension(ctx, orc):
+    """Pilot of 4096 paths, then N = ceil((s / (target |g|inf))^2) on the same
+    streams; the oracle decides N from its own pilot."""
+    p = W.unit_square(paths=1, precision=W.FP64, dt=4e-4, n_nodes=4)
+    target = 4e-3
+    g = ctx.solve(p, target_rel_se=target)
+    pil = p.with_paths(4096)
+    o1, _ = oracle_solve(orc, pil)
+    gnorm = p.g_norm
+    want = np.ceil((o1["var_re"] + o1["var_im"]) / (target * gnorm) ** 2)
+    want = np.clip(want, 4096, 1 << 20).astype(np.uint32)
+    assert np.array_equal(g["paths_done"], want)
+    full = p.replace(path_begin=np.zeros(4, np.uint32), path_count=want)
+    o2, _ = oracle_solve(orc, full)
+    assert_fp64_parity(g, o2)
+    assert np.all(g["se"] <= target * gnorm * 1.25)
+
+
+def test_served_results_equal_blocking(ctx):
+    ps = [small_mixed_model(), W.unit_square(paths=500, precision=W.FP32_MIXED, seed=3),
+          W.quarter_space(paths=16, precision=W.FP32_MIXED, M=1024).subset(np.arange(0, 512, 64)),
+          W.unit_square(paths=300, precision=W.FP64, seed=8)]
+    tickets = [ctx.submit(p, records=True) for p in ps]
+    got = [ctx.wait(t, timeout_s=120) for t in tickets]
+    for p, r in zip(ps, got):
+        alone = ctx.solve(p, records=True)
+        assert r["records"].tobytes() == alone["records"].tobytes()
+        assert np.array_equal(r["mean"], alone["mean"])
+    # cancel: either it is cancelled (wait reports it) or it had finished
+    t = ctx.submit(W.unit_square(paths=64))
+    st = ctx.cancel(t)
+    if st == sdd.SDD_OK:
+        with pytest.raises(sdd.SddError) as e:
+            ctx.wait(t, timeout_s=60)
+        assert e.value.status == sdd.SDD_E_CANCELLED
+    else:
+        assert st == sdd.SDD_E_BUSY
+        assert ctx.wait(t, timeout_s=60)["paths_done"].sum() == 8 * 64
+    with pytest.raises(sdd.SddError) as e:
+        ctx.poll(987654321)
+    assert e.value.status == sdd.SDD_E_NOTFOUND
