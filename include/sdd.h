@@ -143,7 +143,7 @@ typedef struct {
 
 /* Launch shape of the persistent walker (0 = automatic). */
 typedef struct {
-    uint32_t block_threads;   /* multiple of 64, <= 1024 */
+    uint32_t block_threads;   /* multiple of 64, <= 256 */
     uint32_t blocks_per_cu;
     uint32_t tile_paths;      /* paths per tile (work unit claimed by a wave) */
     uint32_t slice_iters;     /* served mode: iterations (2 steps) per wave per slice */

@@ -63,15 +63,19 @@ struct NodeJob {
 
 // Per-request device descriptor.
 struct DevReq {
-  // FP64 numerics
+  // FP64 walk (absolute coordinates, the same arithmetic as a plain FP64 reference)
   double y_lo, y_hi, z_lo, z_hi;
   double s;            // sqrt(dt)
   double dt;
   double thr;          // bridge pre-filter: draw U only if 2 d0 d1 <= thr
-  double pad0;
+  double ymid, zmid;   // centre of the domain (origin of the FP32 walk)
   double c[kMaxRegions + 1];   // phase per full step: alpha_r dt / 2 (background at [nprims])
-  // FP32 copies for the mixed walk
-  float fy_lo, fy_hi, fz_lo, fz_hi, fs, fdt, fthr, fpad;
+  // FP32-mixed walk: coordinates relative to (ymid, zmid), walls at +-h
+  float fhy, fhz;      // half-widths
+  float fs, fdt;       // sqrt(dt), dt
+  float fthr;          // 22.9 dt, compared with 2 d0 d1
+  float fscr;          // fthr / 2, compared with d0 d1' in the per-step screen
+  float fpad[2];
   float fc[kMaxRegions + 3];
   // streams and limits
   uint32_t key0, key1;  // Philox key (seed low, high)
@@ -83,7 +87,7 @@ struct DevReq {
   uint32_t nprims;
   int32_t kind[kMaxPrims];
   double pd[kMaxPrims][6];    // FP64 geometry of the model's primitives
-  float pf[kMaxPrims][8];     // FP32 geometry, padded to 8 for one scalar load
+  float pf[kMaxPrims][8];     // FP32 geometry relative to the centre, padded to 8
   const DevModel *model;      // resident model the primitives were taken from
   const double *nodes;  // n x (y, z)
   const double *g;      // 4 x (M + 1) x (re, im)

@@ -1,15 +1,21 @@
 // HIP kernels for gfx950: the Feynman-Kac walk of the 2-D TE equation at
 // interface nodes and the per-node reduction.
 //
-//   walk_plain     FP64, one thread per path, one launch per node (the plain
-//                  form): a wave waits for its longest path.
-//   walk_persist   persistent walker, FP64 or FP32-mixed: each wave owns one
-//                  request at a time, claims tiles of paths with one atomic,
-//                  and refills every lane whose path has exited (ballot +
-//                  mbcnt rank), so lanes stay busy until the request's tiles
-//                  run out.
-//   reduce_nodes   deterministic FP64 reduction of each node's path records
-//                  to the MC estimate, variance, covariance and SE.
+//   walk_plain        FP64, one thread per path, one launch per node (the
+//                     plain form): a wave waits for its longest path.
+//   walk_persist_f64  persistent walker, FP64: identical arithmetic to a
+//                     plain FP64 reference on the same streams.
+//   walk_persist_f32  persistent walker, FP32-mixed: coordinates relative to
+//                     the domain centre, a conservative 6-operation exit
+//                     screen per step, compensated FP32 phase; weight and
+//                     reduction in FP64.
+//   reduce_nodes      deterministic FP64 reduction of each node's path records
+//                     to the MC estimate, variance, covariance and SE.
+//
+// Persistent walkers: each wave owns one request at a time, claims tiles of
+// paths with one atomic and refills every lane whose path has exited (ballot
+// + mbcnt rank), so lanes stay busy until the request's tiles run out; the
+// request data sit in SGPRs (scalar loads), walker state in VGPRs.
 //
 // The arithmetic of one path is a pure function of (seed, stream, node, path)
 // and the request's data, and every path writes its own record, so results
@@ -33,106 +39,86 @@ namespace sdd {
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64-bit
-// products; the key schedule depends only on the (wave-uniform) key, so it
-// runs on the scalar unit.
+// products with a Weyl key schedule (the key is wave-uniform, so the
+// schedule runs on the scalar unit).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                          uint32_t k0, uint32_t k1) {
+constexpr uint32_t kM0 = 0xD2511F53u, kM1 = 0xCD9E8D57u;
+constexpr uint32_t kW0 = 0x9E3779B9u, kW1 = 0xBB67AE85u;
+
+__device__ __forceinline__ void philox_round(uint32_t &c0, uint32_t &c1, uint32_t &c2, uint32_t &c3, uint32_t k0,
+                                             uint32_t k1) {
+  const uint64_t p0 = (uint64_t)kM0 * (uint64_t)c0;
+  const uint64_t p1 = (uint64_t)kM1 * (uint64_t)c2;
+  const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+  const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+  c1 = (uint32_t)p1;
+  c3 = (uint32_t)p0;
+  c0 = n0;
+  c2 = n2;
+}
+
+// Every counter this walk uses has the form (c0, path, node, c3): words 1 and
+// 2 are fixed for a path.  Round 1 then depends on c0 only through M0*c0, and
+// round 2 multiplies a word that is fixed for the path; both products are made
+// once per path.
+struct PhiloxPath {
+  uint32_t x1;   // lo(M1 node)             (round-1 output word 1)
+  uint32_t hb;   // hi(M0 x0), x0 = hi(M1 node) ^ path ^ k0 (round-1 word 0)
+  uint32_t lb;   // lo(M0 x0)
+};
+
+__device__ __forceinline__ PhiloxPath philox_path(uint32_t path, uint32_t node, uint32_t k0) {
+  const uint64_t A = (uint64_t)kM1 * (uint64_t)node;
+  const uint32_t x0 = (uint32_t)(A >> 32) ^ path ^ k0;
+  const uint64_t B = (uint64_t)kM0 * (uint64_t)x0;
+  PhiloxPath pp;
+  pp.x1 = (uint32_t)A;
+  pp.hb = (uint32_t)(B >> 32);
+  pp.lb = (uint32_t)B;
+  return pp;
+}
+
+// Philox4x32-10 of the counter (c0, path, node, c3) given P0 = M0 * c0.
+__device__ __forceinline__ uint4 philox_pp(uint64_t P0, uint32_t c3, const PhiloxPath &pp, uint32_t k0,
+                                           uint32_t k1) {
+  // round 1 gives (x0, x1, hi(P0) ^ c3 ^ k1, lo(P0)); round 2 (key + W):
+  const uint32_t r1w2 = (uint32_t)(P0 >> 32) ^ c3 ^ k1;
+  const uint32_t r1w3 = (uint32_t)P0;
+  const uint64_t p1 = (uint64_t)kM1 * (uint64_t)r1w2;
+  uint32_t w0 = (uint32_t)(p1 >> 32) ^ pp.x1 ^ (k0 + kW0);
+  uint32_t w1 = (uint32_t)p1;
+  uint32_t w2 = pp.hb ^ r1w3 ^ (k1 + kW1);
+  uint32_t w3 = pp.lb;
 #pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
-    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
-    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
-    c1 = (uint32_t)p1;
-    c3 = (uint32_t)p0;
-    c0 = n0;
-    c2 = n2;
-    k0 += 0x9E3779B9u;
-    k1 += 0xBB67AE85u;
-  }
-  return make_uint4(c0, c1, c2, c3);
+  for (uint32_t r = 2; r < 10; ++r) philox_round(w0, w1, w2, w3, k0 + r * kW0, k1 + r * kW1);
+  return make_uint4(w0, w1, w2, w3);
 }
 
 // ---------------------------------------------------------------------------
-// Precision policies.
+// Helpers shared by both precisions.
 // ---------------------------------------------------------------------------
-template <class R> struct Arith;
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// FP64: the uniform (w + 1/2) 2^-32 is exact; library log/sqrt/sin/cos.
-template <> struct Arith<double> {
-  static __device__ __forceinline__ double u01(uint32_t w) {
-    return ((double)w + 0.5) * (1.0 / 4294967296.0);
-  }
-  static __device__ __forceinline__ void normals(uint32_t a, uint32_t b, double &n0, double &n1) {
-    const double two_pi = 6.283185307179586476925286766559;
-    const double r = sqrt(-2.0 * log(u01(a)));
-    const double th = two_pi * u01(b);
-    n0 = r * cos(th);
-    n1 = r * sin(th);
-  }
-  static __device__ __forceinline__ double neglog_u(uint32_t w) { return -log(u01(w)); }
-  static __device__ __forceinline__ double mad(double a, double b, double c) { return c + a * b; }
+template <class R> struct ExitInfo {
+  R f, t;     // fraction of the last step; tangential coordinate of the exit
+  int wall;   // 0 top, 1 right, 2 bottom, 3 left
 };
-
-// FP32: the uniform ((w >> 8) + 1/2) 2^-24 is exact in FP32; hardware
-// transcendentals: v_log_f32 (log2), v_sqrt_f32, and v_sin/v_cos_f32 whose
-// argument is in revolutions, so the angle 2 pi u needs no multiply.
-template <> struct Arith<float> {
-  static __device__ __forceinline__ float u01(uint32_t w) {
-    return __builtin_fmaf((float)(w >> 8), 0x1p-24f, 0x1p-25f);
-  }
-  static __device__ __forceinline__ void normals(uint32_t a, uint32_t b, float &n0, float &n1) {
-    const float m2ln2 = -1.3862943611198906f;  // -2 ln 2
-    const float r = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u01(a)));
-    const float ub = u01(b);
-    n0 = r * __builtin_amdgcn_cosf(ub);
-    n1 = r * __builtin_amdgcn_sinf(ub);
-  }
-  static __device__ __forceinline__ float neglog_u(uint32_t w) {
-    return -0.69314718055994531f * __builtin_amdgcn_logf(u01(w));
-  }
-  static __device__ __forceinline__ float mad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-};
-
-// Wave-uniform request data in registers.
-template <class R> struct Uni;
-template <> struct Uni<double> {
-  double ylo, yhi, zlo, zhi, s, dt, thr;
-  __device__ __forceinline__ void load(const DevReq &Q) {
-    ylo = Q.y_lo; yhi = Q.y_hi; zlo = Q.z_lo; zhi = Q.z_hi; s = Q.s; dt = Q.dt; thr = Q.thr;
-  }
-};
-template <> struct Uni<float> {
-  float ylo, yhi, zlo, zhi, s, dt, thr;
-  __device__ __forceinline__ void load(const DevReq &Q) {
-    ylo = Q.fy_lo; yhi = Q.fy_hi; zlo = Q.fz_lo; zhi = Q.fz_hi; s = Q.fs; dt = Q.fdt; thr = Q.fthr;
-  }
-};
-
-template <class R> __device__ __forceinline__ R creg(const DevReq &Q, int k);
-template <> __device__ __forceinline__ double creg<double>(const DevReq &Q, int k) { return Q.c[k]; }
-template <> __device__ __forceinline__ float creg<float>(const DevReq &Q, int k) { return Q.fc[k]; }
-template <class R> __device__ __forceinline__ const R *prm(const DevReq &Q, int k);
-template <> __device__ __forceinline__ const double *prm<double>(const DevReq &Q, int k) { return Q.pd[k]; }
-template <> __device__ __forceinline__ const float *prm<float>(const DevReq &Q, int k) { return Q.pf[k]; }
 
 // Phase increment of the region containing (y, z): primitives in list order,
-// the first match wins, else the background (index nprims).  The loop is
-// wave-uniform (scalar loads of the model); only the tests are per lane.
-template <class R>
-__device__ __forceinline__ R region_c(const DevReq &Q, R y, R z) {
-  const int np = (int)Q.nprims;
-  R c = creg<R>(Q, np);
+// the first match wins, else the background (index nprims).  The loop and the
+// primitive kinds are wave-uniform; only the tests are per lane.
+template <class R, int STRIDE>
+__device__ __forceinline__ R region_c_impl(int np, const int32_t *kind, const R *prm, const R *cv, R y, R z) {
+  R c = cv[np];
   for (int k = np - 1; k >= 0; --k) {
-    const int kind = Q.kind[k];
-    const R *v = prm<R>(Q, k);
+    const int kd = kind[k];
+    const R *v = prm + k * STRIDE;
     bool in;
-    if (kind == kHalfZ) {
+    if (kd == kHalfZ) {
       in = z < v[0];
-    } else if (kind == kHalfY) {
+    } else if (kd == kHalfY) {
       in = y < v[0];
-    } else if (kind == kBox) {
+    } else if (kd == kBox) {
       in = (y >= v[0]) && (y < v[1]) && (z >= v[2]) && (z < v[3]);
     } else {
       const R e0 = (v[2] - v[0]) * (z - v[1]) - (v[3] - v[1]) * (y - v[0]);
@@ -142,123 +128,27 @@ __device__ __forceinline__ R region_c(const DevReq &Q, R y, R z) {
       const bool np_ = (e0 <= R(0)) && (e1 <= R(0)) && (e2 <= R(0));
       in = nn || np_;
     }
-    c = in ? creg<R>(Q, k) : c;
+    c = in ? cv[k] : c;
   }
   return c;
 }
 
-// Walker state of one lane.
-template <class R> struct Walker {
-  R y, z;
-  R shi, slo;   // phase S = shi + slo (slo stays 0 in FP64)
-  R cc;         // phase increment of the region of the current point
-  uint32_t n;   // index of the next step
-  uint32_t path, node;
-  uint64_t rec;
-};
-
-template <class R> __device__ __forceinline__ void add_phase(Walker<R> &W, R c);
-template <> __device__ __forceinline__ void add_phase<double>(Walker<double> &W, double c) {
-  W.shi = W.shi + c;
+__device__ __forceinline__ double region_c64(const DevReq &Q, double y, double z) {
+  return region_c_impl<double, 6>((int)Q.nprims, Q.kind, &Q.pd[0][0], Q.c, y, z);
 }
-// Compensated FP32 (Knuth's TwoSum): shi + slo carries S to ~2^-48 relative.
-template <> __device__ __forceinline__ void add_phase<float>(Walker<float> &W, float c) {
-  const float s = W.shi + c;
-  const float bb = s - W.shi;
-  const float e = (W.shi - (s - bb)) + (c - bb);
-  W.shi = s;
-  W.slo = W.slo + e;
+__device__ __forceinline__ float region_c32(const DevReq &Q, float a, float b) {
+  return region_c_impl<float, 8>((int)Q.nprims, Q.kind, &Q.pf[0][0], Q.fc, a, b);
 }
 
-template <class R> struct ExitInfo {
-  R f, t;
-  int wall;
-};
-
-// One step of the walk.  Returns true when the step reaches the outer
-// boundary (ExitInfo filled, walker state left at the last inside point);
-// otherwise the proposal is accepted and its region's phase added.
-template <class R>
-__device__ __forceinline__ bool walk_step(const DevReq &Q, const Uni<R> &U, uint32_t k0, uint32_t k1,
-                                          uint32_t ctr3, Walker<R> &W, R n0, R n1, ExitInfo<R> &X) {
-  const R yn = Arith<R>::mad(U.s, n0, W.y);
-  const R zn = Arith<R>::mad(U.s, n1, W.z);
-  // nearer wall per axis; a tie goes to the lower wall
-  const R dly = W.y - U.ylo, dhy = U.yhi - W.y;
-  const bool upy = !(dly <= dhy);
-  const R d0y = upy ? dhy : dly;
-  const R d1y = upy ? (U.yhi - yn) : (yn - U.ylo);
-  const R dlz = W.z - U.zlo, dhz = U.zhi - W.z;
-  const bool upz = !(dlz <= dhz);
-  const R d0z = upz ? dhz : dlz;
-  const R d1z = upz ? (U.zhi - zn) : (zn - U.zlo);
-  const bool cy = d1y <= R(0);
-  const bool cz = d1z <= R(0);
-  const R qy = (R(2) * d0y) * d1y;
-  const R qz = (R(2) * d0z) * d1z;
-  bool hy = cy, hz = cz;
-  R fy = R(0), fz = R(0);
-  // Same side: the bridge can only have hit when 2 d0 d1 <= dt (-log U) and
-  // -log U <= 22.87 for every U this generator makes, so U is drawn only
-  // below the threshold thr = 22.9 dt.
-  const bool ny = !cy && (qy <= U.thr);
-  const bool nz = !cz && (qz <= U.thr);
-  if (ny || nz) {
-    const uint4 b = philox10(W.n, W.path, W.node, ctr3 + 1u, k0, k1);
-    if (ny) {
-      const R L = Arith<R>::neglog_u(b.x);
-      if (qy <= U.dt * L) { hy = true; fy = qy / (U.dt * L); }
-    }
-    if (nz) {
-      const R L = Arith<R>::neglog_u(b.y);
-      if (qz <= U.dt * L) { hz = true; fz = qz / (U.dt * L); }
-    }
-  }
-  if (hy || hz) {
-    if (cy) fy = d0y / (d0y - d1y);
-    if (cz) fz = d0z / (d0z - d1z);
-    const bool usey = hy && (!hz || fy <= fz);
-    if (usey) {
-      X.f = fy;
-      X.wall = upy ? 1 : 3;
-      R t = W.z + fy * (zn - W.z);
-      t = t < U.zlo ? U.zlo : t;
-      t = t > U.zhi ? U.zhi : t;
-      X.t = t;
-    } else {
-      X.f = fz;
-      X.wall = upz ? 2 : 0;
-      R t = W.y + fz * (yn - W.y);
-      t = t < U.ylo ? U.ylo : t;
-      t = t > U.yhi ? U.yhi : t;
-      X.t = t;
-    }
-    return true;
-  }
-  const R c = region_c<R>(Q, yn, zn);
-  add_phase<R>(W, c);
-  W.cc = c;
-  W.y = yn;
-  W.z = zn;
-  return false;
-}
-
-// The weight g(X_tau) exp(-i S) of a finished path, in FP64.
-template <class R>
-__device__ __forceinline__ PathRec finish_path(const DevReq &Q, const Walker<R> &W, const ExitInfo<R> &X) {
-  double S;
-  if constexpr (sizeof(R) == 8) {
-    S = (double)W.shi + (double)(W.cc * X.f);
-  } else {
-    S = ((double)W.shi + (double)W.slo) + (double)(W.cc * X.f);
-  }
-  const int wall = X.wall;
+// The weight g(X_tau) exp(-i S) of a finished path, in FP64, from the exit
+// wall, the tangential coordinate t (absolute) and the phase S.
+__device__ __forceinline__ void weight(const DevReq &Q, int wall, double t, double S, double &wre, double &wim) {
   const bool along_y = (wall == 0) || (wall == 2);
   const double t0 = along_y ? Q.y_lo : Q.z_lo;
   const double t1 = along_y ? Q.y_hi : Q.z_hi;
   const int M = (int)Q.M;
   const double h = (t1 - t0) / (double)M;
-  const double u = ((double)X.t - t0) / h;
+  const double u = (t - t0) / h;
   int i = (int)floor(u);
   i = i < 0 ? 0 : i;
   i = i > M - 1 ? M - 1 : i;
@@ -269,13 +159,8 @@ __device__ __forceinline__ PathRec finish_path(const DevReq &Q, const Walker<R> 
   const double gre = (1.0 - lam) * ga.x + lam * gb.x;
   const double gim = (1.0 - lam) * ga.y + lam * gb.y;
   const double cs = cos(S), sn = sin(S);
-  PathRec r;
-  r.w_re = gre * cs + gim * sn;
-  r.w_im = gim * cs - gre * sn;
-  r.tau = ((double)W.n + (double)X.f) * Q.dt;
-  r.steps = W.n + 1u;
-  r.wall = wall;
-  return r;
+  wre = gre * cs + gim * sn;
+  wim = gim * cs - gre * sn;
 }
 
 __device__ __forceinline__ PathRec unfinished_rec(uint32_t steps) {
@@ -288,20 +173,328 @@ __device__ __forceinline__ PathRec unfinished_rec(uint32_t steps) {
   return r;
 }
 
-template <class R>
-__device__ __forceinline__ void start_walker(const DevReq &Q, Walker<R> &W, uint32_t node, uint32_t path,
-                                             uint64_t rec) {
+// ===========================================================================
+// FP64 walk: absolute coordinates, every decision exactly as the plain
+// definition takes it.
+// ===========================================================================
+struct W64 {
+  double y, z, S, cc;   // position, phase, phase rate of the current region
+  uint32_t n, path, node;
+  uint64_t rec;
+  uint64_t P;           // M0 * (n / 2): counter product of the next normal pair
+  PhiloxPath pp;
+};
+
+struct U64 {
+  double ylo, yhi, zlo, zhi, s, dt, thr;
+  uint32_t k0, k1, ctr3, max_steps;
+  __device__ __forceinline__ void load(const DevReq &Q) {
+    ylo = Q.y_lo; yhi = Q.y_hi; zlo = Q.z_lo; zhi = Q.z_hi; s = Q.s; dt = Q.dt; thr = Q.thr;
+    k0 = Q.key0; k1 = Q.key1; ctr3 = Q.ctr3; max_steps = Q.max_steps;
+  }
+};
+
+__device__ __forceinline__ void start64(const DevReq &Q, const U64 &U, W64 &W, uint32_t node, uint32_t path,
+                                        uint64_t rec) {
   const double2 p = *reinterpret_cast<const double2 *>(Q.nodes + 2 * (size_t)node);
-  W.y = (R)p.x;
-  W.z = (R)p.y;
-  W.shi = R(0);
-  W.slo = R(0);
+  W.y = p.x;
+  W.z = p.y;
+  W.S = 0.0;
   W.n = 0;
   W.path = path;
   W.node = node;
   W.rec = rec;
-  W.cc = region_c<R>(Q, W.y, W.z);
+  W.P = 0;
+  W.pp = philox_path(path, node, U.k0);
+  W.cc = region_c64(Q, W.y, W.z);
 }
+
+__device__ __forceinline__ double u01_64(uint32_t w) { return ((double)w + 0.5) * (1.0 / 4294967296.0); }
+
+__device__ __forceinline__ void normals64(uint32_t a, uint32_t b, double &n0, double &n1) {
+  const double two_pi = 6.283185307179586476925286766559;
+  const double r = sqrt(-2.0 * log(u01_64(a)));
+  const double th = two_pi * u01_64(b);
+  n0 = r * cos(th);
+  n1 = r * sin(th);
+}
+
+// One FP64 step.  Returns true when the step reaches the outer boundary.
+__device__ __forceinline__ bool step64(const DevReq &Q, const U64 &U, W64 &W, double n0, double n1,
+                                       ExitInfo<double> &X) {
+  const double yn = W.y + U.s * n0;
+  const double zn = W.z + U.s * n1;
+  // nearer wall per axis; a tie goes to the lower wall
+  const double dly = W.y - U.ylo, dhy = U.yhi - W.y;
+  const bool upy = !(dly <= dhy);
+  const double d0y = upy ? dhy : dly;
+  const double d1y = upy ? (U.yhi - yn) : (yn - U.ylo);
+  const double dlz = W.z - U.zlo, dhz = U.zhi - W.z;
+  const bool upz = !(dlz <= dhz);
+  const double d0z = upz ? dhz : dlz;
+  const double d1z = upz ? (U.zhi - zn) : (zn - U.zlo);
+  const bool cy = d1y <= 0.0;
+  const bool cz = d1z <= 0.0;
+  const double qy = (2.0 * d0y) * d1y;
+  const double qz = (2.0 * d0z) * d1z;
+  bool hy = cy, hz = cz;
+  double fy = 0.0, fz = 0.0;
+  // Same side: the bridge can only have hit when 2 d0 d1 <= dt (-log U) and
+  // -log U <= 22.87 for every U made here, so U is drawn only when
+  // 2 d0 d1 <= 22.9 dt.
+  const bool ny = !cy && (qy <= U.thr);
+  const bool nz = !cz && (qz <= U.thr);
+  if (ny || nz) {
+    const uint64_t Pn = (W.P << 1) + ((W.n & 1u) ? (uint64_t)kM0 : 0ull);   // M0 * n
+    const uint4 b = philox_pp(Pn, U.ctr3 + 1u, W.pp, U.k0, U.k1);
+    if (ny) {
+      const double L = -log(u01_64(b.x));
+      if (qy <= U.dt * L) { hy = true; fy = qy / (U.dt * L); }
+    }
+    if (nz) {
+      const double L = -log(u01_64(b.y));
+      if (qz <= U.dt * L) { hz = true; fz = qz / (U.dt * L); }
+    }
+  }
+  if (hy || hz) {
+    if (cy) fy = d0y / (d0y - d1y);
+    if (cz) fz = d0z / (d0z - d1z);
+    if (hy && (!hz || fy <= fz)) {
+      X.f = fy;
+      X.wall = upy ? 1 : 3;
+      double t = W.z + fy * (zn - W.z);
+      t = t < U.zlo ? U.zlo : t;
+      X.t = t > U.zhi ? U.zhi : t;
+    } else {
+      X.f = fz;
+      X.wall = upz ? 2 : 0;
+      double t = W.y + fz * (yn - W.y);
+      t = t < U.ylo ? U.ylo : t;
+      X.t = t > U.yhi ? U.yhi : t;
+    }
+    return true;
+  }
+  const double c = region_c64(Q, yn, zn);
+  W.S = W.S + c;
+  W.cc = c;
+  W.y = yn;
+  W.z = zn;
+  return false;
+}
+
+__device__ __forceinline__ PathRec finish64(const DevReq &Q, const W64 &W, const ExitInfo<double> &X) {
+  const double S = W.S + W.cc * X.f;
+  PathRec r;
+  weight(Q, X.wall, X.t, S, r.w_re, r.w_im);
+  r.tau = ((double)W.n + X.f) * Q.dt;
+  r.steps = W.n + 1u;
+  r.wall = X.wall;
+  return r;
+}
+
+// Two steps (one Philox call).  Returns 0 running, 1 exited, 2 step cap.
+__device__ __forceinline__ int iterate64(const DevReq &Q, const U64 &U, W64 &W, ExitInfo<double> &X) {
+  const uint4 w = philox_pp(W.P, U.ctr3, W.pp, U.k0, U.k1);
+  double a0, a1, b0, b1;
+  normals64(w.x, w.y, a0, a1);
+  normals64(w.z, w.w, b0, b1);
+  if (step64(Q, U, W, a0, a1, X)) return 1;
+  W.n += 1u;
+  if (W.n >= U.max_steps) return 2;
+  if (step64(Q, U, W, b0, b1, X)) return 1;
+  W.n += 1u;
+  W.P += (uint64_t)kM0;
+  return W.n >= U.max_steps ? 2 : 0;
+}
+
+// ===========================================================================
+// FP32-mixed walk: coordinates (a, b) relative to the domain centre, walls
+// at +-h.  The distance of the current point to its nearer wall, d0 = h - |a|,
+// is carried from step to step.  A proposal can only reach a wall, or need a
+// bridge uniform, if d0 d1 <= 11.45 dt on some axis, where d1 is the distance
+// of the proposal to the wall nearer to the current point; d1' = h - |a'|
+// (distance to the wall nearer to the proposal) satisfies d1' <= d1, so the
+// screen min(d0y d1y', d0z d1z') <= 11.45 dt never misses one.
+// ===========================================================================
+struct W32 {
+  float a, b;       // y - ymid, z - zmid
+  float d0y, d0z;   // h - |a|, h - |b|
+  float shi, slo;   // phase S = shi + slo (compensated)
+  float cc;         // phase rate of the current region
+  uint32_t n, path, node;
+  uint64_t rec;
+  uint64_t P;
+  PhiloxPath pp;
+};
+
+struct U32 {
+  float hy, hz, s, dt, thr, scr;
+  uint32_t k0, k1, ctr3, max_steps;
+  __device__ __forceinline__ void load(const DevReq &Q) {
+    hy = Q.fhy; hz = Q.fhz; s = Q.fs; dt = Q.fdt; thr = Q.fthr; scr = Q.fscr;
+    k0 = Q.key0; k1 = Q.key1; ctr3 = Q.ctr3; max_steps = Q.max_steps;
+  }
+};
+
+// ((w >> 8) + 1/2) 2^-24: exact in FP32, never 0 or 1.
+__device__ __forceinline__ float u01_32(uint32_t w) { return __builtin_fmaf((float)(w >> 8), 0x1p-24f, 0x1p-25f); }
+
+// Box-Muller with the hardware transcendentals: v_log_f32 (log2), v_sqrt_f32,
+// and v_sin/v_cos_f32, whose argument is in revolutions (no 2 pi multiply).
+__device__ __forceinline__ void normals32(uint32_t a, uint32_t b, float &n0, float &n1) {
+  const float m2ln2 = -1.3862943611198906f;  // -2 ln 2
+  const float r = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u01_32(a)));
+  const float ub = u01_32(b);
+  n0 = r * __builtin_amdgcn_cosf(ub);
+  n1 = r * __builtin_amdgcn_sinf(ub);
+}
+
+__device__ __forceinline__ float neglog32(uint32_t w) {
+  return -0.69314718055994531f * __builtin_amdgcn_logf(u01_32(w));
+}
+
+__device__ __forceinline__ void start32(const DevReq &Q, const U32 &U, W32 &W, uint32_t node, uint32_t path,
+                                        uint64_t rec) {
+  const double2 p = *reinterpret_cast<const double2 *>(Q.nodes + 2 * (size_t)node);
+  W.a = (float)(p.x - Q.ymid);
+  W.b = (float)(p.y - Q.zmid);
+  W.d0y = U.hy - fabsf(W.a);
+  W.d0z = U.hz - fabsf(W.b);
+  W.shi = 0.f;
+  W.slo = 0.f;
+  W.n = 0;
+  W.path = path;
+  W.node = node;
+  W.rec = rec;
+  W.P = 0;
+  W.pp = philox_path(path, node, U.k0);
+  W.cc = region_c32(Q, W.a, W.b);
+}
+
+// Exact exit logic for a lane the screen flagged.
+__device__ __forceinline__ bool exit32(const U32 &U, const W32 &W, float an, float bn,
+                                                 ExitInfo<float> &X) {
+  const bool upy = W.a > 0.f;   // a tie (a = 0) goes to the lower wall
+  const bool upz = W.b > 0.f;
+  const float d0y = W.d0y, d0z = W.d0z;
+  const float d1y = upy ? (U.hy - an) : (U.hy + an);
+  const float d1z = upz ? (U.hz - bn) : (U.hz + bn);
+  const bool cy = d1y <= 0.f, cz = d1z <= 0.f;
+  const float qy = (2.f * d0y) * d1y, qz = (2.f * d0z) * d1z;
+  bool hy = cy, hz = cz;
+  float fy = 0.f, fz = 0.f;
+  const bool ny = !cy && (qy <= U.thr);
+  const bool nz = !cz && (qz <= U.thr);
+  if (ny || nz) {
+    const uint64_t Pn = (W.P << 1) + ((W.n & 1u) ? (uint64_t)kM0 : 0ull);
+    const uint4 u = philox_pp(Pn, U.ctr3 + 1u, W.pp, U.k0, U.k1);
+    if (ny) {
+      const float L = neglog32(u.x);
+      if (qy <= U.dt * L) { hy = true; fy = qy / (U.dt * L); }
+    }
+    if (nz) {
+      const float L = neglog32(u.y);
+      if (qz <= U.dt * L) { hz = true; fz = qz / (U.dt * L); }
+    }
+  }
+  if (!(hy || hz)) return false;
+  if (cy) fy = d0y / (d0y - d1y);
+  if (cz) fz = d0z / (d0z - d1z);
+  if (hy && (!hz || fy <= fz)) {
+    X.f = fy;
+    X.wall = upy ? 1 : 3;
+    X.t = fminf(fmaxf(__builtin_fmaf(fy, bn - W.b, W.b), -U.hz), U.hz);
+  } else {
+    X.f = fz;
+    X.wall = upz ? 2 : 0;
+    X.t = fminf(fmaxf(__builtin_fmaf(fz, an - W.a, W.a), -U.hy), U.hy);
+  }
+  return true;
+}
+
+// Compensated FP32 accumulation (Knuth's TwoSum): shi + slo carries S.
+__device__ __forceinline__ void add_phase32(W32 &W, float c) {
+  const float s = W.shi + c;
+  const float bb = s - W.shi;
+  const float e = (W.shi - (s - bb)) + (c - bb);
+  W.shi = s;
+  W.slo = W.slo + e;
+}
+
+__device__ __forceinline__ bool step32(const DevReq &Q, const U32 &U, W32 &W, float n0, float n1,
+                                       ExitInfo<float> &X) {
+  const float an = __builtin_fmaf(U.s, n0, W.a);
+  const float bn = __builtin_fmaf(U.s, n1, W.b);
+  const float e1y = U.hy - fabsf(an);
+  const float e1z = U.hz - fabsf(bn);
+  if (fminf(W.d0y * e1y, W.d0z * e1z) <= U.scr) {
+    if (exit32(U, W, an, bn, X)) return true;
+  }
+  const float c = region_c32(Q, an, bn);
+  add_phase32(W, c);
+  W.cc = c;
+  W.a = an;
+  W.b = bn;
+  W.d0y = e1y;
+  W.d0z = e1z;
+  return false;
+}
+
+__device__ __forceinline__ PathRec finish32(const DevReq &Q, const W32 &W, const ExitInfo<float> &X) {
+  const double S = ((double)W.shi + (double)W.slo) + (double)(W.cc * X.f);
+  const bool along_y = (X.wall == 0) || (X.wall == 2);
+  double t = (double)X.t + (along_y ? Q.ymid : Q.zmid);
+  const double lo = along_y ? Q.y_lo : Q.z_lo, hi = along_y ? Q.y_hi : Q.z_hi;
+  t = t < lo ? lo : (t > hi ? hi : t);
+  PathRec r;
+  weight(Q, X.wall, t, S, r.w_re, r.w_im);
+  r.tau = ((double)W.n + (double)X.f) * Q.dt;
+  r.steps = W.n + 1u;
+  r.wall = X.wall;
+  return r;
+}
+
+__device__ __forceinline__ int iterate32(const DevReq &Q, const U32 &U, W32 &W, ExitInfo<float> &X) {
+  const uint4 w = philox_pp(W.P, U.ctr3, W.pp, U.k0, U.k1);
+  float a0, a1, b0, b1;
+  normals32(w.x, w.y, a0, a1);
+  normals32(w.z, w.w, b0, b1);
+  if (step32(Q, U, W, a0, a1, X)) return 1;
+  W.n += 1u;
+  if (W.n >= U.max_steps) return 2;
+  if (step32(Q, U, W, b0, b1, X)) return 1;
+  W.n += 1u;
+  W.P += (uint64_t)kM0;
+  return W.n >= U.max_steps ? 2 : 0;
+}
+
+// Precision traits for the persistent loop.
+struct F64 {
+  using Walker = W64;
+  using Uni = U64;
+  using Exit = ExitInfo<double>;
+  static __device__ __forceinline__ void start(const DevReq &Q, const Uni &U, Walker &W, uint32_t node,
+                                               uint32_t path, uint64_t rec) { start64(Q, U, W, node, path, rec); }
+  static __device__ __forceinline__ int iterate(const DevReq &Q, const Uni &U, Walker &W, Exit &X) {
+    return iterate64(Q, U, W, X);
+  }
+  static __device__ __forceinline__ PathRec finish(const DevReq &Q, const Walker &W, const Exit &X) {
+    return finish64(Q, W, X);
+  }
+};
+struct F32 {
+  using Walker = W32;
+  using Uni = U32;
+  using Exit = ExitInfo<float>;
+  static __device__ __forceinline__ void start(const DevReq &Q, const Uni &U, Walker &W, uint32_t node,
+                                               uint32_t path, uint64_t rec) { start32(Q, U, W, node, path, rec); }
+  static __device__ __forceinline__ int iterate(const DevReq &Q, const Uni &U, Walker &W, Exit &X) {
+    return iterate32(Q, U, W, X);
+  }
+  static __device__ __forceinline__ PathRec finish(const DevReq &Q, const Walker &W, const Exit &X) {
+    return finish32(Q, W, X);
+  }
+};
 
 // ---------------------------------------------------------------------------
 // Plain FP64 walker: one thread walks one path to its end.
@@ -311,37 +504,19 @@ __global__ void __launch_bounds__(256) walk_plain(const DevReq *__restrict__ req
   const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
   if (tid >= count) return;
   const DevReq &Q = reqs[0];
-  Uni<double> U;
+  U64 U;
   U.load(Q);
-  const uint32_t k0 = Q.key0, k1 = Q.key1, ctr3 = Q.ctr3, max_steps = Q.max_steps;
-  Walker<double> W;
-  start_walker<double>(Q, W, node, p0 + tid, rec0 + tid);
+  W64 W;
+  start64(Q, U, W, node, p0 + tid, rec0 + tid);
   ExitInfo<double> X;
-  while (W.n < max_steps) {
-    const uint4 w = philox10(W.n >> 1, W.path, W.node, ctr3, k0, k1);
-    double a0, a1, b0, b1;
-    Arith<double>::normals(w.x, w.y, a0, a1);
-    Arith<double>::normals(w.z, w.w, b0, b1);
-    if (walk_step<double>(Q, U, k0, k1, ctr3, W, a0, a1, X)) {
-      Q.recs[W.rec] = finish_path<double>(Q, W, X);
-      return;
-    }
-    W.n += 1u;
-    if (W.n >= max_steps) break;
-    if (walk_step<double>(Q, U, k0, k1, ctr3, W, b0, b1, X)) {
-      Q.recs[W.rec] = finish_path<double>(Q, W, X);
-      return;
-    }
-    W.n += 1u;
-  }
-  Q.recs[W.rec] = unfinished_rec(max_steps);
+  int st = W.n >= U.max_steps ? 2 : 0;
+  while (st == 0) st = iterate64(Q, U, W, X);
+  Q.recs[W.rec] = st == 1 ? finish64(Q, W, X) : unfinished_rec(U.max_steps);
 }
 
 // ---------------------------------------------------------------------------
 // Persistent walker.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-
 __device__ __forceinline__ uint32_t pick_request(const DevReq *__restrict__ reqs, uint32_t n_req) {
   // the request with the most unclaimed tiles (ties: lowest index)
   uint32_t best = kNoRequest, best_left = 0;
@@ -354,24 +529,20 @@ __device__ __forceinline__ uint32_t pick_request(const DevReq *__restrict__ reqs
   return best;
 }
 
-template <class R>
+template <class T>
 __device__ __forceinline__ void run_request(const DevReq &Q) {
   const uint32_t lane = __lane_id();
-  Uni<R> U;
+  typename T::Uni U;
   U.load(Q);
-  const uint32_t k0 = Q.key0, k1 = Q.key1, ctr3 = Q.ctr3, max_steps = Q.max_steps;
   const uint32_t n_tiles = Q.n_tiles;
-
-  Walker<R> W;
-  W.n = 0; W.path = 0; W.node = 0; W.rec = 0;
-  W.y = R(0); W.z = R(0); W.shi = R(0); W.slo = R(0); W.cc = R(0);
+  typename T::Walker W;
   bool active = false;
 
   // wave-uniform tile cursor
   uint32_t t_node = 0, t_p0 = 0, t_next = 0, t_end = 0;
   uint64_t t_rec0 = 0;
   bool exhausted = false;
-  uint32_t finished = 0;   // paths this wave completed (wave-uniform)
+  uint32_t finished = 0;   // paths this wave completed
 
   for (;;) {
     // refill free lanes in rank order from the wave's tile, claiming tiles
@@ -387,17 +558,17 @@ __device__ __forceinline__ void run_request(const DevReq &Q) {
           if (lane == 0) t = atomicAdd(Q.tile_counter, 1u);
           t = uni(t);
           if (t >= n_tiles) { exhausted = true; break; }
-          const DevTile T = Q.tiles[t];
-          t_node = uni(T.node);
-          t_p0 = uni(T.p0);
+          const DevTile Tl = Q.tiles[t];
+          t_node = uni(Tl.node);
+          t_p0 = uni(Tl.p0);
           t_next = t_p0;
-          t_end = t_p0 + uni(T.count);
-          t_rec0 = ((uint64_t)uni((uint32_t)(T.rec0 >> 32)) << 32) | uni((uint32_t)T.rec0);
+          t_end = t_p0 + uni(Tl.count);
+          t_rec0 = ((uint64_t)uni((uint32_t)(Tl.rec0 >> 32)) << 32) | uni((uint32_t)Tl.rec0);
         }
         const uint32_t take = min(t_end - t_next, nfree - given);
         if (!active && rank >= given && rank < given + take) {
           const uint32_t p = t_next + (rank - given);
-          start_walker<R>(Q, W, t_node, p, t_rec0 + (p - t_p0));
+          T::start(Q, U, W, t_node, p, t_rec0 + (p - t_p0));
           active = true;
         }
         t_next += take;
@@ -408,25 +579,10 @@ __device__ __forceinline__ void run_request(const DevReq &Q) {
     if (freemask_after_refill == ~0ull) break;
 
     if (active) {
-      // two steps per Philox call: words 0,1 for step n (even), 2,3 for n+1
-      const uint4 w = philox10(W.n >> 1, W.path, W.node, ctr3, k0, k1);
-      R a0, a1, b0, b1;
-      Arith<R>::normals(w.x, w.y, a0, a1);
-      Arith<R>::normals(w.z, w.w, b0, b1);
-      ExitInfo<R> X;
-      bool ex = walk_step<R>(Q, U, k0, k1, ctr3, W, a0, a1, X);
-      if (!ex) {
-        W.n += 1u;
-        if (W.n < max_steps) {
-          ex = walk_step<R>(Q, U, k0, k1, ctr3, W, b0, b1, X);
-          if (!ex) W.n += 1u;
-        }
-      }
-      if (ex) {
-        Q.recs[W.rec] = finish_path<R>(Q, W, X);
-        active = false;
-      } else if (W.n >= max_steps) {
-        Q.recs[W.rec] = unfinished_rec(max_steps);
+      typename T::Exit X;
+      const int st = T::iterate(Q, U, W, X);
+      if (st != 0) {
+        Q.recs[W.rec] = st == 1 ? T::finish(Q, W, X) : unfinished_rec(U.max_steps);
         active = false;
       }
     }
@@ -435,23 +591,33 @@ __device__ __forceinline__ void run_request(const DevReq &Q) {
   if (lane == 0) atomicAdd(Q.done_counter, (unsigned long long)finished);
 }
 
-__global__ void __launch_bounds__(256) walk_persist(const DevReq *__restrict__ reqs, uint32_t n_req,
-                                                    const uint32_t *__restrict__ wave_start) {
+template <class T>
+__device__ __forceinline__ void persist_body(const DevReq *__restrict__ reqs, uint32_t n_req,
+                                             const uint32_t *__restrict__ wave_start) {
   const uint32_t wid = uni((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   // initial request: waves are shared out in proportion to each request's work
   uint32_t r = kNoRequest;
   for (uint32_t i = 0; i < n_req; ++i)
     if (wid >= wave_start[i] && wid < wave_start[i + 1]) r = i;
   r = uni(r);
+  if (r == kNoRequest) r = pick_request(reqs, n_req);
   // Each visit either claims a tile or finds the request's tiles exhausted,
   // after which pick_request never returns it again: the loop ends once every
   // tile of every request has been claimed.
   while (r != kNoRequest) {
-    const DevReq &Q = reqs[r];
-    if (Q.precision == 0u) run_request<double>(Q);
-    else run_request<float>(Q);
+    run_request<T>(reqs[r]);
     r = pick_request(reqs, n_req);
   }
+}
+
+__global__ void __launch_bounds__(256) walk_persist_f64(const DevReq *__restrict__ reqs, uint32_t n_req,
+                                                        const uint32_t *__restrict__ wave_start) {
+  persist_body<F64>(reqs, n_req, wave_start);
+}
+
+__global__ void __launch_bounds__(256) walk_persist_f32(const DevReq *__restrict__ reqs, uint32_t n_req,
+                                                        const uint32_t *__restrict__ wave_start) {
+  persist_body<F32>(reqs, n_req, wave_start);
 }
 
 // ---------------------------------------------------------------------------
@@ -571,22 +737,27 @@ hipError_t launch_walk_plain(const DevReq *req_dev, uint32_t node, uint32_t p0, 
   return hipGetLastError();
 }
 
-hipError_t launch_walk_persist(const DevReq *reqs_dev, uint32_t n_req, const uint32_t *wave_start_dev,
-                               uint32_t blocks, uint32_t threads, hipStream_t st) {
-  hipLaunchKernelGGL(walk_persist, dim3(blocks), dim3(threads), 0, st, reqs_dev, n_req, wave_start_dev);
+hipError_t launch_walk_persist(int precision, const DevReq *reqs_dev, uint32_t n_req,
+                               const uint32_t *wave_start_dev, uint32_t blocks, uint32_t threads, hipStream_t st) {
+  if (precision == 0)
+    hipLaunchKernelGGL(walk_persist_f64, dim3(blocks), dim3(threads), 0, st, reqs_dev, n_req, wave_start_dev);
+  else
+    hipLaunchKernelGGL(walk_persist_f32, dim3(blocks), dim3(threads), 0, st, reqs_dev, n_req, wave_start_dev);
   return hipGetLastError();
+}
+
+int persist_blocks_per_cu(int precision, uint32_t threads) {
+  int nb = 0;
+  const hipError_t e = precision == 0
+      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_persist_f64, (int)threads, 0)
+      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_persist_f32, (int)threads, 0);
+  return e == hipSuccess ? nb : 0;
 }
 
 hipError_t launch_reduce(const NodeJob *jobs_dev, uint32_t n_jobs, hipStream_t st) {
   if (n_jobs == 0) return hipSuccess;
   hipLaunchKernelGGL(reduce_nodes, dim3(n_jobs), dim3(kRedThreads), 0, st, jobs_dev);
   return hipGetLastError();
-}
-
-int persist_blocks_per_cu(uint32_t threads) {
-  int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_persist, (int)threads, 0) != hipSuccess) return 0;
-  return nb;
 }
 
 hipError_t launch_reset(uint32_t *tile_counters, unsigned long long *done, uint32_t n, hipStream_t st) {

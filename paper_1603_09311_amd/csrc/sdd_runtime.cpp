@@ -27,11 +27,11 @@
 namespace sdd {
 hipError_t launch_walk_plain(const DevReq *req_dev, uint32_t node, uint32_t p0, uint32_t count, uint64_t rec0,
                              hipStream_t st);
-hipError_t launch_walk_persist(const DevReq *reqs_dev, uint32_t n_req, const uint32_t *wave_start_dev,
-                               uint32_t blocks, uint32_t threads, hipStream_t st);
+hipError_t launch_walk_persist(int precision, const DevReq *reqs_dev, uint32_t n_req,
+                               const uint32_t *wave_start_dev, uint32_t blocks, uint32_t threads, hipStream_t st);
 hipError_t launch_reduce(const NodeJob *jobs_dev, uint32_t n_jobs, hipStream_t st);
 hipError_t launch_reset(uint32_t *tile_counters, unsigned long long *done, uint32_t n, hipStream_t st);
-int persist_blocks_per_cu(uint32_t threads);
+int persist_blocks_per_cu(int precision, uint32_t threads);
 }  // namespace sdd
 
 using namespace sdd;
@@ -130,7 +130,7 @@ struct HostModel {
   sdd_model_desc desc;
   std::vector<sdd_region> regions;
   char *dev = nullptr;   // resident DevModel in the workspace
-  int in_flight = 0;     // submitted requests referencing it
+  std::atomic<int> in_flight{0};  // prepared requests referencing it
 };
 
 static constexpr uint32_t kPilotPaths = 4096;
@@ -197,11 +197,9 @@ struct sdd_ctx {
   sdd_stats stats{};
 };
 
+// Takes no lock: a Prepared may be destroyed while ctx->mu is held.
 Prepared::~Prepared() {
-  if (owner && model) {
-    std::lock_guard<std::mutex> lk(owner->mu);
-    const_cast<HostModel *>(model)->in_flight -= 1;
-  }
+  if (owner && model) const_cast<HostModel *>(model)->in_flight.fetch_sub(1);
 }
 
 static double alpha_of(const sdd_request &r, const HostModel &m, double sigma) {
@@ -270,21 +268,38 @@ static void fill_devreq(Prepared &P) {
   q.dt = r.dt;
   q.s = std::sqrt(r.dt);
   q.thr = 22.9 * r.dt;
+  // the FP32 walk measures positions from the centre of the domain
+  q.ymid = 0.5 * (q.y_lo + q.y_hi);
+  q.zmid = 0.5 * (q.z_lo + q.z_hi);
   const uint32_t np = (uint32_t)m.regions.size();
   q.nprims = np;
   for (uint32_t k = 0; k < np; ++k) {
     q.c[k] = alpha_of(r, m, m.regions[k].sigma) * r.dt / 2.0;
     q.kind[k] = m.regions[k].kind;
-    for (int i = 0; i < 6; ++i) {
-      q.pd[k][i] = m.regions[k].v[i];
-      q.pf[k][i] = (float)m.regions[k].v[i];
+    const double *v = m.regions[k].v;
+    for (int i = 0; i < 6; ++i) q.pd[k][i] = v[i];
+    // centred FP32 geometry: y-coordinates minus ymid, z-coordinates minus zmid
+    switch (m.regions[k].kind) {
+      case SDD_HALF_Z_LT: q.pf[k][0] = (float)(v[0] - q.zmid); break;
+      case SDD_HALF_Y_LT: q.pf[k][0] = (float)(v[0] - q.ymid); break;
+      case SDD_BOX:
+        q.pf[k][0] = (float)(v[0] - q.ymid); q.pf[k][1] = (float)(v[1] - q.ymid);
+        q.pf[k][2] = (float)(v[2] - q.zmid); q.pf[k][3] = (float)(v[3] - q.zmid);
+        break;
+      default:
+        for (int i = 0; i < 6; i += 2) {
+          q.pf[k][i] = (float)(v[i] - q.ymid);
+          q.pf[k][i + 1] = (float)(v[i + 1] - q.zmid);
+        }
     }
   }
   q.c[np] = alpha_of(r, m, m.desc.sigma_background) * r.dt / 2.0;
-  q.fy_lo = (float)q.y_lo; q.fy_hi = (float)q.y_hi; q.fz_lo = (float)q.z_lo; q.fz_hi = (float)q.z_hi;
+  q.fhy = (float)(0.5 * (q.y_hi - q.y_lo));
+  q.fhz = (float)(0.5 * (q.z_hi - q.z_lo));
   q.fs = (float)q.s;
   q.fdt = (float)q.dt;
   q.fthr = 22.9f * q.fdt;
+  q.fscr = 0.5f * q.fthr;
   for (uint32_t k = 0; k <= np; ++k) q.fc[k] = (float)q.c[k];
   q.key0 = (uint32_t)(r.seed & 0xFFFFFFFFu);
   q.key1 = (uint32_t)(r.seed >> 32);
@@ -302,7 +317,7 @@ static sdd_status prepare(sdd_ctx *ctx, const sdd_request *r, std::unique_ptr<Pr
     std::lock_guard<std::mutex> lk(ctx->mu);
     sdd_status st = validate(ctx, r, &m);
     if (st != SDD_OK) return st;
-    const_cast<HostModel *>(m)->in_flight += 1;   // the model outlives the request
+    const_cast<HostModel *>(m)->in_flight.fetch_add(1);   // the model outlives the request
   }
   auto P = std::make_unique<Prepared>();
   P->owner = ctx;
@@ -416,21 +431,23 @@ struct BatchScratch {
   }
 };
 
-static void launch_shape(sdd_ctx *ctx, uint32_t &blocks, uint32_t &threads) {
+static void launch_shape(sdd_ctx *ctx, int precision, uint32_t &blocks, uint32_t &threads) {
   threads = ctx->tuning.block_threads ? ctx->tuning.block_threads : 256u;
   uint32_t per_cu = ctx->tuning.blocks_per_cu;
   if (!per_cu) {
-    const int occ = persist_blocks_per_cu(threads);
+    const int occ = persist_blocks_per_cu(precision, threads);
     per_cu = occ > 0 ? (uint32_t)occ : 1u;
   }
   blocks = (uint32_t)ctx->cus * per_cu;
 }
 
-static sdd_status run_persistent(sdd_ctx *ctx, std::vector<Prepared *> &passes) {
+// One persistent launch over passes of one precision (the walker kernel is
+// compiled per precision).
+static sdd_status run_group(sdd_ctx *ctx, std::vector<Prepared *> &passes, int precision) {
   const uint32_t n = (uint32_t)passes.size();
   if (n == 0) return SDD_OK;
   uint32_t blocks, threads;
-  launch_shape(ctx, blocks, threads);
+  launch_shape(ctx, precision, blocks, threads);
   const uint32_t waves = blocks * (threads / 64);
   BatchScratch B;
   B.d_reqs = ctx->alloc(n * sizeof(DevReq));
@@ -467,7 +484,7 @@ static sdd_status run_persistent(sdd_ctx *ctx, std::vector<Prepared *> &passes) 
         "reset counters");
   if (st == SDD_OK) check(hipEventRecord(ctx->ev[0], ctx->stream), "event");
   if (st == SDD_OK)
-    check(launch_walk_persist(reinterpret_cast<const DevReq *>(B.d_reqs), n,
+    check(launch_walk_persist(precision, reinterpret_cast<const DevReq *>(B.d_reqs), n,
                               reinterpret_cast<const uint32_t *>(B.d_ws), blocks, threads, ctx->stream),
           "walk_persist");
   if (st == SDD_OK) check(hipEventRecord(ctx->ev[1], ctx->stream), "event");
@@ -479,17 +496,29 @@ static sdd_status run_persistent(sdd_ctx *ctx, std::vector<Prepared *> &passes) 
   B.release(ctx);
   if (st != SDD_OK) return st;
   float ms = 0.f;
-  if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]) == hipSuccess) ctx->stats.last_walk_ms = ms;
+  if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]) == hipSuccess) ctx->stats.last_walk_ms += ms;
   ctx->stats.last_blocks = blocks;
   ctx->stats.last_threads = threads;
   ctx->stats.launches += 1;
-  uint64_t paths = 0;
-  for (auto *P : passes) paths += P->n_paths;
-  ctx->stats.last_walk_paths = paths;
+  for (auto *P : passes) ctx->stats.last_walk_paths += P->n_paths;
   for (uint32_t i = 0; i < n; ++i)
     if (done[i] != passes[i]->n_paths)
       return fail(SDD_E_DEVICE, "request %u: %llu of %llu paths completed", i, done[i],
                   (unsigned long long)passes[i]->n_paths);
+  return SDD_OK;
+}
+
+// The walk of a set of passes: one persistent launch per precision present.
+static sdd_status run_persistent(sdd_ctx *ctx, std::vector<Prepared *> &passes) {
+  ctx->stats.last_walk_ms = 0.0;
+  ctx->stats.last_walk_paths = 0;
+  for (int prec : {SDD_FP32_MIXED, SDD_FP64}) {
+    std::vector<Prepared *> group;
+    for (auto *P : passes)
+      if ((int)P->dreq.precision == prec) group.push_back(P);
+    sdd_status st = run_group(ctx, group, prec);
+    if (st != SDD_OK) return st;
+  }
   return SDD_OK;
 }
 
@@ -885,8 +914,8 @@ sdd_status sdd_model_destroy(sdd_ctx_t ctx, sdd_model_t model) {
   std::lock_guard<std::mutex> lk(ctx->mu);
   auto it = ctx->models.find(model);
   if (it == ctx->models.end()) return fail(SDD_E_NOTFOUND, "unknown model %u", model);
-  if (it->second->in_flight > 0)
-    return fail(SDD_E_BUSY, "model %u is used by %d requests in flight", model, it->second->in_flight);
+  const int busy = it->second->in_flight.load();
+  if (busy > 0) return fail(SDD_E_BUSY, "model %u is used by %d requests in flight", model, busy);
   ctx->arena.release(it->second->dev);
   ctx->models.erase(it);
   return SDD_OK;
@@ -1030,8 +1059,8 @@ sdd_status sdd_request_footprint(sdd_ctx_t ctx, const sdd_request *req, uint64_t
 
 sdd_status sdd_set_tuning(sdd_ctx_t ctx, const sdd_tuning *t) {
   if (!ctx || !t) return fail(SDD_E_INVALID, "NULL argument");
-  if (t->block_threads && (t->block_threads % 64 || t->block_threads > 1024))
-    return fail(SDD_E_INVALID, "block_threads must be a multiple of 64, at most 1024");
+  if (t->block_threads && (t->block_threads % 64 || t->block_threads > 256))
+    return fail(SDD_E_INVALID, "block_threads must be a multiple of 64, at most 256 (the walker's launch bound)");
   if (t->blocks_per_cu > 64) return fail(SDD_E_INVALID, "blocks_per_cu at most 64");
   if (t->tile_paths > (1u << 24)) return fail(SDD_E_INVALID, "tile_paths at most 2^24");
   std::lock_guard<std::mutex> ex(ctx->exec);

@@ -47,7 +47,7 @@ def oracle_solve(orc, p, records=False):
 
 def assert_fp64_parity(g, o, tol=TOL_FP64):
     e_o = o["mean_re"] + 1j * o["mean_im"]
-    scale = np.maximum(np.abs(e_o), o["se"])
+    scale = np.fmax(np.abs(e_o), o["se"])      # SE is NaN for a one-path node
     d = np.abs(g["mean"] - e_o)
     assert np.all(d <= tol * scale), (d / scale).max()
     assert np.array_equal(g["paths_done"], o["paths_done"])
@@ -182,11 +182,14 @@ def test_launch_shape_does_not_change_a_bit(ctx):
     p = W.unit_square(paths=1500, precision=W.FP32_MIXED, seed=4)
     ref = ctx.solve(p, records=True)
     try:
-        for bt, bpc, tile in [(64, 1, 1), (128, 2, 64), (512, 1, 4096), (256, 3, 100)]:
+        for bt, bpc, tile in [(64, 1, 1), (128, 2, 64), (192, 1, 4096), (256, 3, 100)]:
             ctx.set_tuning(block_threads=bt, blocks_per_cu=bpc, tile_paths=tile)
             got = ctx.solve(p, records=True)
             assert got["records"].tobytes() == ref["records"].tobytes(), (bt, bpc, tile)
             assert np.array_equal(got["mean"], ref["mean"])
+        with pytest.raises(sdd.SddError) as e:
+            ctx.set_tuning(block_threads=512)
+        assert e.value.status == sdd.SDD_E_INVALID
     finally:
         ctx.set_tuning()
 
