@@ -36,16 +36,20 @@ CUS, SIMDS, LANES, CLOCK = 256, 4, 16, 2.4e9
 VALU_PEAK = CUS * SIMDS * LANES * CLOCK
 
 # Algorithmic VALU work of one FP32-mixed walk step on the quarter-space
-# model, in full-rate lane-operation slots (quarter-rate ops count 4):
-#   Philox4x32-10, half a call per step: 10 rounds x (2 32x32->64 products at
-#     quarter rate = 8, 2 three-input xors = 2) / 2                      = 50
+# model: every operation the method needs, each in its cheapest gfx950
+# instruction form, one lane-operation slot per instruction (the counters show
+# the walker retiring about one VALU instruction per 4 cycles per SIMD,
+# transcendentals and 32x32->64 products included):
+#   Philox4x32-10, one call per two steps: rounds 3-10 (2 products + 2 3-input
+#     xors each) 32, round 2: 3, round 1: 1, step-pair counter product 2 -> 38/2 = 19
 #   two uniforms (shift, convert, fma)                                     =  6
-#   Box-Muller (log2, sqrt, sin, cos at quarter rate = 16; 3 multiplies)  = 19
+#   Box-Muller (log2, mul, sqrt, sin, cos, 2 mul)                          =  7
 #   Euler-Maruyama position update (2 fma)                                 =  2
-#   nearer-wall exit test, both axes (~12 compare/select/sub each)         = 24
+#   exit screen, both axes (2 sub |.|, 2 mul, min, compare)                =  6
 #   region lookup, 2 half-planes (2 compares, 2 selects)                   =  4
 #   compensated phase add (TwoSum)                                         =  6
-OPS_PER_STEP = 50 + 6 + 19 + 2 + 24 + 4 + 6   # = 111
+#   step counter                                                           =  1
+OPS_PER_STEP = 19 + 6 + 7 + 2 + 6 + 4 + 6 + 1   # = 51
 
 
 def kernel_source_hash() -> str:
@@ -193,7 +197,7 @@ def main():
     out["launch"] = {"blocks": st["last_blocks"], "threads": st["last_threads"]}
 
     if not args.no_plain:
-        sub = W.quarter_space(paths=args.paths, precision=W.FP64).subset(np.arange(0, 512, 16))
+        sub = W.quarter_space(paths=args.paths, precision=W.FP64).subset(np.arange(0, 512, 64))
         r = ctx.solve_plain(sub)
         t_plain = ctx.stats()["last_walk_ms"]
         s_plain = float(r["steps"].sum())

@@ -147,6 +147,7 @@ typedef struct {
     uint32_t blocks_per_cu;
     uint32_t tile_paths;      /* paths per tile (work unit claimed by a wave) */
     uint32_t slice_iters;     /* served mode: iterations (2 steps) per wave per slice */
+    uint32_t refill_every;    /* refill idle lanes every k iterations (power of 2, <= 64) */
 } sdd_tuning;
 
 /* Context on device `device` (HIP ordinal) with a caller-owned device
@@ -181,8 +182,38 @@ sdd_status sdd_poll(sdd_ctx_t ctx, sdd_ticket_t t, int *done);
 sdd_status sdd_wait(sdd_ctx_t ctx, sdd_ticket_t t, int64_t timeout_ns);   /* < 0: forever */
 sdd_status sdd_cancel(sdd_ctx_t ctx, sdd_ticket_t t);
 
+/* Set or read the context's tuning.  set: block_threads not a multiple of
+ * 64 or above 256, blocks_per_cu above 64, tile_paths above 2^24 or
+ * refill_every not a power of 2 up to 64 give SDD_E_INVALID; zeros select
+ * the defaults (256, occupancy, 512, 4096, 1).  Waits for the running launch
+ * sequence; served requests pick the new tuning up at their next slice. */
 sdd_status sdd_set_tuning(sdd_ctx_t ctx, const sdd_tuning *t);
 sdd_status sdd_get_tuning(sdd_ctx_t ctx, sdd_tuning *t);
+
+/* One timed trial of sdd_autotune. */
+typedef struct {
+    sdd_tuning tuning;
+    double walk_ms;            /* walk kernel duration (HIP events) */
+    double walk_steps_per_s;   /* proposals drawn / walk_ms */
+} sdd_tune_trial;
+
+/* Autotuner: times the persistent walker on a sample of *req (the request's
+ * nodes, at most sample_paths paths each; 0 = enough paths to occupy every
+ * resident lane about four times) under a sequence of tunings and keeps the
+ * fastest.  Starting from the context's tuning it sweeps block_threads
+ * {256, 128, 64}, then tile_paths {128, 512, 2048, 8192}, then refill_every
+ * {1, 2, 4, 8}, each with the others held at the best so far.  Results of
+ * every solve are bitwise the same under any tuning (a path's random numbers
+ * are indexed by seed, stream, node, path and step, its record has a fixed
+ * slot, and each node is reduced in path order), so tuning changes speed
+ * only.  On success the context keeps the chosen tuning and copies it to
+ * *chosen (may be NULL); slice_iters is not touched.  Up to max_trials
+ * trials are written to trials (may be NULL when max_trials is 0) and their
+ * count to *n_trials (may be NULL).  On failure the previous tuning is
+ * restored.  Blocks the calling thread for the trials (each about one
+ * sample solve). */
+sdd_status sdd_autotune(sdd_ctx_t ctx, const sdd_request *req, uint32_t sample_paths, sdd_tuning *chosen,
+                        sdd_tune_trial *trials, uint32_t max_trials, uint32_t *n_trials);
 
 /* Timing of the most recent walk launch on this context, measured with HIP
  * events on the context's stream around the walk kernel alone. */
@@ -196,6 +227,19 @@ typedef struct {
 } sdd_stats;
 
 sdd_status sdd_get_stats(sdd_ctx_t ctx, sdd_stats *out);
+
+/* A prepared batch: the requests' inputs stay resident in the workspace and
+ * the launch sequence (counter reset, one persistent walk per precision, the
+ * per-node reduction, the copy of the results to pinned host memory) is
+ * captured once into a HIP graph; sdd_batch_run replays it on the context's
+ * stream and blocks until the results are in `res` (one sdd_result per
+ * request, as for sdd_solve_batch).  Fixed-path requests only.  The batch
+ * holds its workspace until sdd_batch_destroy.  Every replay gives bitwise
+ * the results of sdd_solve_batch on the same requests. */
+typedef struct sdd_batch *sdd_batch_t;
+sdd_status sdd_batch_create(sdd_ctx_t ctx, uint32_t n, const sdd_request *reqs, sdd_batch_t *out);
+sdd_status sdd_batch_run(sdd_batch_t batch, sdd_result *res);
+sdd_status sdd_batch_destroy(sdd_batch_t batch);
 
 /* Bytes of workspace a request needs (tables, nodes, tiles, records). */
 sdd_status sdd_request_footprint(sdd_ctx_t ctx, const sdd_request *req, uint64_t *bytes);

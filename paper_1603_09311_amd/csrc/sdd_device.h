@@ -15,6 +15,10 @@ constexpr uint32_t kNoRequest = 0xFFFFFFFFu;
 
 enum PrimKind : int32_t { kHalfZ = 0, kHalfY = 1, kBox = 2, kTriangle = 3 };
 
+// Model signatures with a specialised, branch-free region lookup; any other
+// model uses the generic loop over its primitives.
+enum ModelSig : int32_t { kSigNone = 0, kSigZ = 1, kSigZY = 2, kSigZBox = 3, kSigZTri = 4, kSigGeneric = 5 };
+
 // Resident conductivity model (workspace copy made by sdd_model_create).
 struct DevModel {
   int32_t nprims;
@@ -35,6 +39,20 @@ struct DevTile {
   uint64_t rec0;      // record slot of path p0 (request-relative)
   uint64_t pad1;
 };
+
+// A walker suspended at the end of a time slice (served mode), 64 bytes.
+// Positions and phase are stored exactly (FP32 values widen losslessly);
+// everything else a walker holds is recomputed from these on resume.
+struct SuspRec {
+  double x, y;         // FP64 walk: (y, z); FP32 walk: centred (a, b)
+  double s_hi, s_lo;   // phase
+  uint64_t rec;        // record slot
+  uint32_t n, path, node, pad;
+  uint64_t pad1;
+};
+
+// Per-request slice control words: claim cursors and append counts.
+enum SliceCtl : int { kPoolCursor = 0, kPoolOut = 1, kExtraCursor = 2, kExtraOut = 3 };
 
 // Per-path record, 32 bytes.
 struct PathRec {
@@ -77,6 +95,15 @@ struct DevReq {
   float fscr;          // fthr / 2, compared with d0 d1' in the per-step screen
   float fpad[2];
   float fc[kMaxRegions + 3];
+  // model signature (which specialised region lookup the walkers use) and its
+  // FP32 parameters in centred coordinates:
+  //   kSigZ:    [z0]                      air above z0
+  //   kSigZY:   [z0, y1]                  + half-space y < y1
+  //   kSigZBox: [z0, y0, y1, zb0, zb1]    + box
+  //   kSigZTri: [z0, A0,B0,C0, A1,B1,C1, A2,B2,C2]  + triangle, edges A a + B b + C
+  int32_t sig;
+  int32_t sig_pad[3];
+  float sigp[12];
   // streams and limits
   uint32_t key0, key1;  // Philox key (seed low, high)
   uint32_t ctr3;        // 2 * stream
@@ -95,6 +122,16 @@ struct DevReq {
   PathRec *recs;
   uint32_t *tile_counter;           // next tile to claim
   unsigned long long *done_counter; // paths completed (finished or capped)
+  // served mode: walkers suspended by the previous slice (pool_in, resumed
+  // first), tile remainders it left (extra_in, claimed before new tiles),
+  // and where this slice suspends its own (pool_out, extra_out).
+  const SuspRec *pool_in;
+  SuspRec *pool_out;
+  const DevTile *extra_in;
+  DevTile *extra_out;
+  uint32_t pool_in_n, extra_in_n;
+  uint32_t pool_cap, extra_cap;     // capacity of pool_out / extra_out
+  uint32_t *slice_ctl;              // SliceCtl words
 };
 
 }  // namespace sdd

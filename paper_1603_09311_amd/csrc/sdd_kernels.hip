@@ -14,8 +14,10 @@
 //
 // Persistent walkers: each wave owns one request at a time, claims tiles of
 // paths with one atomic and refills every lane whose path has exited (ballot
-// + mbcnt rank), so lanes stay busy until the request's tiles run out; the
-// request data sit in SGPRs (scalar loads), walker state in VGPRs.
+// + mbcnt rank), so lanes stay busy until the request's tiles run out.  The
+// request data sit in SGPRs, walker state in VGPRs.  The region lookup is
+// specialised per model signature (a wave-uniform dispatch), with the
+// model's parameters hoisted into registers once per request.
 //
 // The arithmetic of one path is a pure function of (seed, stream, node, path)
 // and the request's data, and every path writes its own record, so results
@@ -40,17 +42,22 @@ namespace sdd {
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64-bit
 // products with a Weyl key schedule (the key is wave-uniform, so the
-// schedule runs on the scalar unit).
+// schedule runs on the scalar unit).  Each output word's double XOR is one
+// gfx950 three-input bit operation (truth table 0x96 = a ^ b ^ c).
 // ---------------------------------------------------------------------------
 constexpr uint32_t kM0 = 0xD2511F53u, kM1 = 0xCD9E8D57u;
 constexpr uint32_t kW0 = 0x9E3779B9u, kW1 = 0xBB67AE85u;
+
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
 
 __device__ __forceinline__ void philox_round(uint32_t &c0, uint32_t &c1, uint32_t &c2, uint32_t &c3, uint32_t k0,
                                              uint32_t k1) {
   const uint64_t p0 = (uint64_t)kM0 * (uint64_t)c0;
   const uint64_t p1 = (uint64_t)kM1 * (uint64_t)c2;
-  const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-  const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+  const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+  const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
   c1 = (uint32_t)p1;
   c3 = (uint32_t)p0;
   c0 = n0;
@@ -69,7 +76,7 @@ struct PhiloxPath {
 
 __device__ __forceinline__ PhiloxPath philox_path(uint32_t path, uint32_t node, uint32_t k0) {
   const uint64_t A = (uint64_t)kM1 * (uint64_t)node;
-  const uint32_t x0 = (uint32_t)(A >> 32) ^ path ^ k0;
+  const uint32_t x0 = xor3((uint32_t)(A >> 32), path, k0);
   const uint64_t B = (uint64_t)kM0 * (uint64_t)x0;
   PhiloxPath pp;
   pp.x1 = (uint32_t)A;
@@ -82,12 +89,12 @@ __device__ __forceinline__ PhiloxPath philox_path(uint32_t path, uint32_t node, 
 __device__ __forceinline__ uint4 philox_pp(uint64_t P0, uint32_t c3, const PhiloxPath &pp, uint32_t k0,
                                            uint32_t k1) {
   // round 1 gives (x0, x1, hi(P0) ^ c3 ^ k1, lo(P0)); round 2 (key + W):
-  const uint32_t r1w2 = (uint32_t)(P0 >> 32) ^ c3 ^ k1;
+  const uint32_t r1w2 = xor3((uint32_t)(P0 >> 32), c3, k1);
   const uint32_t r1w3 = (uint32_t)P0;
   const uint64_t p1 = (uint64_t)kM1 * (uint64_t)r1w2;
-  uint32_t w0 = (uint32_t)(p1 >> 32) ^ pp.x1 ^ (k0 + kW0);
+  uint32_t w0 = xor3((uint32_t)(p1 >> 32), pp.x1, k0 + kW0);
   uint32_t w1 = (uint32_t)p1;
-  uint32_t w2 = pp.hb ^ r1w3 ^ (k1 + kW1);
+  uint32_t w2 = xor3(pp.hb, r1w3, k1 + kW1);
   uint32_t w3 = pp.lb;
 #pragma unroll
   for (uint32_t r = 2; r < 10; ++r) philox_round(w0, w1, w2, w3, k0 + r * kW0, k1 + r * kW1);
@@ -97,18 +104,29 @@ __device__ __forceinline__ uint4 philox_pp(uint64_t P0, uint32_t c3, const Philo
 // ---------------------------------------------------------------------------
 // Helpers shared by both precisions.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+// readfirstlane returns a signed int: every use goes through uint32_t so no
+// value is ever sign-extended when widened.
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float unif(float v) { return __builtin_bit_cast(float, uni(__builtin_bit_cast(uint32_t, v))); }
+__device__ __forceinline__ double unid(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint64_t r = ((uint64_t)uni((uint32_t)(u >> 32)) << 32) | (uint64_t)uni((uint32_t)u);
+  return __builtin_bit_cast(double, r);
+}
 
 template <class R> struct ExitInfo {
   R f, t;     // fraction of the last step; tangential coordinate of the exit
   int wall;   // 0 top, 1 right, 2 bottom, 3 left
 };
 
-// Phase increment of the region containing (y, z): primitives in list order,
-// the first match wins, else the background (index nprims).  The loop and the
-// primitive kinds are wave-uniform; only the tests are per lane.
+// ---------------------------------------------------------------------------
+// Region lookup: the phase increment c of the region containing a point.
+// Primitives in list order, the first match wins, else the background.
+// ---------------------------------------------------------------------------
+
+// Generic: loop over the primitives (kinds and parameters wave-uniform).
 template <class R, int STRIDE>
-__device__ __forceinline__ R region_c_impl(int np, const int32_t *kind, const R *prm, const R *cv, R y, R z) {
+__device__ __forceinline__ R region_c_generic(int np, const int32_t *kind, const R *prm, const R *cv, R y, R z) {
   R c = cv[np];
   for (int k = np - 1; k >= 0; --k) {
     const int kd = kind[k];
@@ -119,26 +137,108 @@ __device__ __forceinline__ R region_c_impl(int np, const int32_t *kind, const R 
     } else if (kd == kHalfY) {
       in = y < v[0];
     } else if (kd == kBox) {
-      in = (y >= v[0]) && (y < v[1]) && (z >= v[2]) && (z < v[3]);
+      in = (y >= v[0]) & (y < v[1]) & (z >= v[2]) & (z < v[3]);
     } else {
       const R e0 = (v[2] - v[0]) * (z - v[1]) - (v[3] - v[1]) * (y - v[0]);
       const R e1 = (v[4] - v[2]) * (z - v[3]) - (v[5] - v[3]) * (y - v[2]);
       const R e2 = (v[0] - v[4]) * (z - v[5]) - (v[1] - v[5]) * (y - v[4]);
-      const bool nn = (e0 >= R(0)) && (e1 >= R(0)) && (e2 >= R(0));
-      const bool np_ = (e0 <= R(0)) && (e1 <= R(0)) && (e2 <= R(0));
-      in = nn || np_;
+      in = ((e0 >= R(0)) & (e1 >= R(0)) & (e2 >= R(0))) | ((e0 <= R(0)) & (e1 <= R(0)) & (e2 <= R(0)));
     }
     c = in ? cv[k] : c;
   }
   return c;
 }
 
-__device__ __forceinline__ double region_c64(const DevReq &Q, double y, double z) {
-  return region_c_impl<double, 6>((int)Q.nprims, Q.kind, &Q.pd[0][0], Q.c, y, z);
-}
-__device__ __forceinline__ float region_c32(const DevReq &Q, float a, float b) {
-  return region_c_impl<float, 8>((int)Q.nprims, Q.kind, &Q.pf[0][0], Q.fc, a, b);
-}
+// FP64 lookup, exactly the plain definition (absolute coordinates).  The
+// specialised signatures hold the same primitives' parameters in registers.
+template <int SIG> struct Reg64 {
+  double cb, c0, c1;
+  double v[6];   // parameters of primitive 1 (HALF_Y / BOX / TRIANGLE)
+  double z0;     // primitive 0: air above z0
+  __device__ __forceinline__ void load(const DevReq &Q) {
+    const int np = (int)Q.nprims;
+    cb = unid(Q.c[np]);
+    if constexpr (SIG != kSigNone && SIG != kSigGeneric) {
+      c0 = unid(Q.c[0]);
+      z0 = unid(Q.pd[0][0]);
+    }
+    if constexpr (SIG == kSigZY || SIG == kSigZBox || SIG == kSigZTri) {
+      c1 = unid(Q.c[1]);
+#pragma unroll
+      for (int i = 0; i < 6; ++i) v[i] = unid(Q.pd[1][i]);
+    }
+  }
+  // The operands go through readfirstlane (free on uniform values) so that
+  // each select is between values, never a load through a selected pointer
+  // (which would keep the request data in scratch memory).
+  __device__ __forceinline__ double eval(const DevReq &Q, double y, double z) const {
+    if constexpr (SIG == kSigNone) {
+      return unid(cb);
+    } else if constexpr (SIG == kSigZ) {
+      return z < unid(z0) ? unid(c0) : unid(cb);
+    } else if constexpr (SIG == kSigZY) {
+      const double c = y < unid(v[0]) ? unid(c1) : unid(cb);
+      return z < unid(z0) ? unid(c0) : c;
+    } else if constexpr (SIG == kSigZBox) {
+      const bool in = (y >= unid(v[0])) & (y < unid(v[1])) & (z >= unid(v[2])) & (z < unid(v[3]));
+      const double c = in ? unid(c1) : unid(cb);
+      return z < unid(z0) ? unid(c0) : c;
+    } else if constexpr (SIG == kSigZTri) {
+      const double v0 = unid(v[0]), v1 = unid(v[1]), v2 = unid(v[2]), v3 = unid(v[3]), v4 = unid(v[4]),
+                   v5 = unid(v[5]);
+      const double e0 = (v2 - v0) * (z - v1) - (v3 - v1) * (y - v0);
+      const double e1 = (v4 - v2) * (z - v3) - (v5 - v3) * (y - v2);
+      const double e2 = (v0 - v4) * (z - v5) - (v1 - v5) * (y - v4);
+      const bool in = ((e0 >= 0.0) & (e1 >= 0.0) & (e2 >= 0.0)) | ((e0 <= 0.0) & (e1 <= 0.0) & (e2 <= 0.0));
+      const double c = in ? unid(c1) : unid(cb);
+      return z < unid(z0) ? unid(c0) : c;
+    } else {
+      return region_c_generic<double, 6>((int)Q.nprims, Q.kind, &Q.pd[0][0], Q.c, y, z);
+    }
+  }
+};
+
+// FP32 lookup in centred coordinates; the triangle as three linear forms.
+template <int SIG> struct Reg32 {
+  float cb, c0, c1;
+  float p[10];
+  __device__ __forceinline__ void load(const DevReq &Q) {
+    const int np = (int)Q.nprims;
+    cb = unif(Q.fc[np]);
+    if constexpr (SIG != kSigNone && SIG != kSigGeneric) {
+      c0 = unif(Q.fc[0]);
+      p[0] = unif(Q.sigp[0]);
+    }
+    if constexpr (SIG == kSigZY || SIG == kSigZBox || SIG == kSigZTri) {
+      c1 = unif(Q.fc[1]);
+#pragma unroll
+      for (int i = 1; i < 10; ++i) p[i] = unif(Q.sigp[i]);
+    }
+  }
+  __device__ __forceinline__ float eval(const DevReq &Q, float a, float b) const {
+    if constexpr (SIG == kSigNone) {
+      return unif(cb);
+    } else if constexpr (SIG == kSigZ) {
+      return b < unif(p[0]) ? unif(c0) : unif(cb);
+    } else if constexpr (SIG == kSigZY) {
+      const float c = a < unif(p[1]) ? unif(c1) : unif(cb);
+      return b < unif(p[0]) ? unif(c0) : c;
+    } else if constexpr (SIG == kSigZBox) {
+      const bool in = (a >= unif(p[1])) & (a < unif(p[2])) & (b >= unif(p[3])) & (b < unif(p[4]));
+      const float c = in ? unif(c1) : unif(cb);
+      return b < unif(p[0]) ? unif(c0) : c;
+    } else if constexpr (SIG == kSigZTri) {
+      const float e0 = __builtin_fmaf(unif(p[1]), a, __builtin_fmaf(unif(p[2]), b, unif(p[3])));
+      const float e1 = __builtin_fmaf(unif(p[4]), a, __builtin_fmaf(unif(p[5]), b, unif(p[6])));
+      const float e2 = __builtin_fmaf(unif(p[7]), a, __builtin_fmaf(unif(p[8]), b, unif(p[9])));
+      const bool in = (fminf(fminf(e0, e1), e2) >= 0.f) | (fmaxf(fmaxf(e0, e1), e2) <= 0.f);
+      const float c = in ? unif(c1) : unif(cb);
+      return b < unif(p[0]) ? unif(c0) : c;
+    } else {
+      return region_c_generic<float, 8>((int)Q.nprims, Q.kind, &Q.pf[0][0], Q.fc, a, b);
+    }
+  }
+};
 
 // The weight g(X_tau) exp(-i S) of a finished path, in FP64, from the exit
 // wall, the tangential coordinate t (absolute) and the phase S.
@@ -185,16 +285,19 @@ struct W64 {
   PhiloxPath pp;
 };
 
-struct U64 {
+template <int SIG> struct U64 {
   double ylo, yhi, zlo, zhi, s, dt, thr;
   uint32_t k0, k1, ctr3, max_steps;
+  Reg64<SIG> reg;
   __device__ __forceinline__ void load(const DevReq &Q) {
     ylo = Q.y_lo; yhi = Q.y_hi; zlo = Q.z_lo; zhi = Q.z_hi; s = Q.s; dt = Q.dt; thr = Q.thr;
     k0 = Q.key0; k1 = Q.key1; ctr3 = Q.ctr3; max_steps = Q.max_steps;
+    reg.load(Q);
   }
 };
 
-__device__ __forceinline__ void start64(const DevReq &Q, const U64 &U, W64 &W, uint32_t node, uint32_t path,
+template <int SIG>
+__device__ __forceinline__ void start64(const DevReq &Q, const U64<SIG> &U, W64 &W, uint32_t node, uint32_t path,
                                         uint64_t rec) {
   const double2 p = *reinterpret_cast<const double2 *>(Q.nodes + 2 * (size_t)node);
   W.y = p.x;
@@ -206,7 +309,7 @@ __device__ __forceinline__ void start64(const DevReq &Q, const U64 &U, W64 &W, u
   W.rec = rec;
   W.P = 0;
   W.pp = philox_path(path, node, U.k0);
-  W.cc = region_c64(Q, W.y, W.z);
+  W.cc = U.reg.eval(Q, W.y, W.z);
 }
 
 __device__ __forceinline__ double u01_64(uint32_t w) { return ((double)w + 0.5) * (1.0 / 4294967296.0); }
@@ -220,7 +323,8 @@ __device__ __forceinline__ void normals64(uint32_t a, uint32_t b, double &n0, do
 }
 
 // One FP64 step.  Returns true when the step reaches the outer boundary.
-__device__ __forceinline__ bool step64(const DevReq &Q, const U64 &U, W64 &W, double n0, double n1,
+template <int SIG>
+__device__ __forceinline__ bool step64(const DevReq &Q, const U64<SIG> &U, W64 &W, double n0, double n1,
                                        ExitInfo<double> &X) {
   const double yn = W.y + U.s * n0;
   const double zn = W.z + U.s * n1;
@@ -274,7 +378,7 @@ __device__ __forceinline__ bool step64(const DevReq &Q, const U64 &U, W64 &W, do
     }
     return true;
   }
-  const double c = region_c64(Q, yn, zn);
+  const double c = U.reg.eval(Q, yn, zn);
   W.S = W.S + c;
   W.cc = c;
   W.y = yn;
@@ -293,15 +397,16 @@ __device__ __forceinline__ PathRec finish64(const DevReq &Q, const W64 &W, const
 }
 
 // Two steps (one Philox call).  Returns 0 running, 1 exited, 2 step cap.
-__device__ __forceinline__ int iterate64(const DevReq &Q, const U64 &U, W64 &W, ExitInfo<double> &X) {
+template <int SIG>
+__device__ __forceinline__ int iterate64(const DevReq &Q, const U64<SIG> &U, W64 &W, ExitInfo<double> &X) {
   const uint4 w = philox_pp(W.P, U.ctr3, W.pp, U.k0, U.k1);
   double a0, a1, b0, b1;
   normals64(w.x, w.y, a0, a1);
   normals64(w.z, w.w, b0, b1);
-  if (step64(Q, U, W, a0, a1, X)) return 1;
+  if (step64<SIG>(Q, U, W, a0, a1, X)) return 1;
   W.n += 1u;
   if (W.n >= U.max_steps) return 2;
-  if (step64(Q, U, W, b0, b1, X)) return 1;
+  if (step64<SIG>(Q, U, W, b0, b1, X)) return 1;
   W.n += 1u;
   W.P += (uint64_t)kM0;
   return W.n >= U.max_steps ? 2 : 0;
@@ -327,12 +432,14 @@ struct W32 {
   PhiloxPath pp;
 };
 
-struct U32 {
+template <int SIG> struct U32 {
   float hy, hz, s, dt, thr, scr;
   uint32_t k0, k1, ctr3, max_steps;
+  Reg32<SIG> reg;
   __device__ __forceinline__ void load(const DevReq &Q) {
     hy = Q.fhy; hz = Q.fhz; s = Q.fs; dt = Q.fdt; thr = Q.fthr; scr = Q.fscr;
     k0 = Q.key0; k1 = Q.key1; ctr3 = Q.ctr3; max_steps = Q.max_steps;
+    reg.load(Q);
   }
 };
 
@@ -353,7 +460,8 @@ __device__ __forceinline__ float neglog32(uint32_t w) {
   return -0.69314718055994531f * __builtin_amdgcn_logf(u01_32(w));
 }
 
-__device__ __forceinline__ void start32(const DevReq &Q, const U32 &U, W32 &W, uint32_t node, uint32_t path,
+template <int SIG>
+__device__ __forceinline__ void start32(const DevReq &Q, const U32<SIG> &U, W32 &W, uint32_t node, uint32_t path,
                                         uint64_t rec) {
   const double2 p = *reinterpret_cast<const double2 *>(Q.nodes + 2 * (size_t)node);
   W.a = (float)(p.x - Q.ymid);
@@ -368,12 +476,12 @@ __device__ __forceinline__ void start32(const DevReq &Q, const U32 &U, W32 &W, u
   W.rec = rec;
   W.P = 0;
   W.pp = philox_path(path, node, U.k0);
-  W.cc = region_c32(Q, W.a, W.b);
+  W.cc = U.reg.eval(Q, W.a, W.b);
 }
 
 // Exact exit logic for a lane the screen flagged.
-__device__ __forceinline__ bool exit32(const U32 &U, const W32 &W, float an, float bn,
-                                                 ExitInfo<float> &X) {
+template <int SIG>
+__device__ __forceinline__ bool exit32(const U32<SIG> &U, const W32 &W, float an, float bn, ExitInfo<float> &X) {
   const bool upy = W.a > 0.f;   // a tie (a = 0) goes to the lower wall
   const bool upz = W.b > 0.f;
   const float d0y = W.d0y, d0z = W.d0z;
@@ -421,16 +529,17 @@ __device__ __forceinline__ void add_phase32(W32 &W, float c) {
   W.slo = W.slo + e;
 }
 
-__device__ __forceinline__ bool step32(const DevReq &Q, const U32 &U, W32 &W, float n0, float n1,
+template <int SIG>
+__device__ __forceinline__ bool step32(const DevReq &Q, const U32<SIG> &U, W32 &W, float n0, float n1,
                                        ExitInfo<float> &X) {
   const float an = __builtin_fmaf(U.s, n0, W.a);
   const float bn = __builtin_fmaf(U.s, n1, W.b);
   const float e1y = U.hy - fabsf(an);
   const float e1z = U.hz - fabsf(bn);
   if (fminf(W.d0y * e1y, W.d0z * e1z) <= U.scr) {
-    if (exit32(U, W, an, bn, X)) return true;
+    if (exit32<SIG>(U, W, an, bn, X)) return true;
   }
-  const float c = region_c32(Q, an, bn);
+  const float c = U.reg.eval(Q, an, bn);
   add_phase32(W, c);
   W.cc = c;
   W.a = an;
@@ -454,99 +563,176 @@ __device__ __forceinline__ PathRec finish32(const DevReq &Q, const W32 &W, const
   return r;
 }
 
-__device__ __forceinline__ int iterate32(const DevReq &Q, const U32 &U, W32 &W, ExitInfo<float> &X) {
+template <int SIG>
+__device__ __forceinline__ int iterate32(const DevReq &Q, const U32<SIG> &U, W32 &W, ExitInfo<float> &X) {
   const uint4 w = philox_pp(W.P, U.ctr3, W.pp, U.k0, U.k1);
   float a0, a1, b0, b1;
   normals32(w.x, w.y, a0, a1);
   normals32(w.z, w.w, b0, b1);
-  if (step32(Q, U, W, a0, a1, X)) return 1;
+  if (step32<SIG>(Q, U, W, a0, a1, X)) return 1;
   W.n += 1u;
   if (W.n >= U.max_steps) return 2;
-  if (step32(Q, U, W, b0, b1, X)) return 1;
+  if (step32<SIG>(Q, U, W, b0, b1, X)) return 1;
   W.n += 1u;
   W.P += (uint64_t)kM0;
   return W.n >= U.max_steps ? 2 : 0;
 }
 
 // Precision traits for the persistent loop.
-struct F64 {
+template <int SIG> struct F64 {
   using Walker = W64;
-  using Uni = U64;
+  using Uni = U64<SIG>;
   using Exit = ExitInfo<double>;
   static __device__ __forceinline__ void start(const DevReq &Q, const Uni &U, Walker &W, uint32_t node,
-                                               uint32_t path, uint64_t rec) { start64(Q, U, W, node, path, rec); }
+                                               uint32_t path, uint64_t rec) { start64<SIG>(Q, U, W, node, path, rec); }
   static __device__ __forceinline__ int iterate(const DevReq &Q, const Uni &U, Walker &W, Exit &X) {
-    return iterate64(Q, U, W, X);
+    return iterate64<SIG>(Q, U, W, X);
   }
   static __device__ __forceinline__ PathRec finish(const DevReq &Q, const Walker &W, const Exit &X) {
     return finish64(Q, W, X);
   }
+  // Suspension at a slice boundary (n is even there) and exact resumption.
+  static __device__ __forceinline__ void save(const Walker &W, SuspRec &s) {
+    s.x = W.y; s.y = W.z; s.s_hi = W.S; s.s_lo = 0.0; s.rec = W.rec;
+    s.n = W.n; s.path = W.path; s.node = W.node; s.pad = 0; s.pad1 = 0;
+  }
+  static __device__ __forceinline__ void resume(const DevReq &Q, const Uni &U, Walker &W, const SuspRec &s) {
+    W.y = s.x; W.z = s.y; W.S = s.s_hi; W.rec = s.rec; W.n = s.n; W.path = s.path; W.node = s.node;
+    W.P = (uint64_t)kM0 * (uint64_t)(W.n >> 1);
+    W.pp = philox_path(W.path, W.node, U.k0);
+    W.cc = U.reg.eval(Q, W.y, W.z);
+  }
 };
-struct F32 {
+template <int SIG> struct F32 {
   using Walker = W32;
-  using Uni = U32;
+  using Uni = U32<SIG>;
   using Exit = ExitInfo<float>;
   static __device__ __forceinline__ void start(const DevReq &Q, const Uni &U, Walker &W, uint32_t node,
-                                               uint32_t path, uint64_t rec) { start32(Q, U, W, node, path, rec); }
+                                               uint32_t path, uint64_t rec) { start32<SIG>(Q, U, W, node, path, rec); }
   static __device__ __forceinline__ int iterate(const DevReq &Q, const Uni &U, Walker &W, Exit &X) {
-    return iterate32(Q, U, W, X);
+    return iterate32<SIG>(Q, U, W, X);
   }
   static __device__ __forceinline__ PathRec finish(const DevReq &Q, const Walker &W, const Exit &X) {
     return finish32(Q, W, X);
+  }
+  static __device__ __forceinline__ void save(const Walker &W, SuspRec &s) {
+    s.x = (double)W.a; s.y = (double)W.b; s.s_hi = (double)W.shi; s.s_lo = (double)W.slo; s.rec = W.rec;
+    s.n = W.n; s.path = W.path; s.node = W.node; s.pad = 0; s.pad1 = 0;
+  }
+  static __device__ __forceinline__ void resume(const DevReq &Q, const Uni &U, Walker &W, const SuspRec &s) {
+    W.a = (float)s.x; W.b = (float)s.y; W.shi = (float)s.s_hi; W.slo = (float)s.s_lo; W.rec = s.rec;
+    W.n = s.n; W.path = s.path; W.node = s.node;
+    W.d0y = U.hy - fabsf(W.a);
+    W.d0z = U.hz - fabsf(W.b);
+    W.P = (uint64_t)kM0 * (uint64_t)(W.n >> 1);
+    W.pp = philox_path(W.path, W.node, U.k0);
+    W.cc = U.reg.eval(Q, W.a, W.b);
   }
 };
 
 // ---------------------------------------------------------------------------
 // Plain FP64 walker: one thread walks one path to its end.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) walk_plain(const DevReq *__restrict__ reqs, uint32_t node,
-                                                  uint32_t p0, uint32_t count, uint64_t rec0) {
+template <int SIG>
+__device__ __forceinline__ void plain_body(const DevReq &Q, uint32_t node, uint32_t p0, uint32_t count,
+                                           uint64_t rec0) {
   const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
   if (tid >= count) return;
-  const DevReq &Q = reqs[0];
-  U64 U;
+  U64<SIG> U;
   U.load(Q);
   W64 W;
-  start64(Q, U, W, node, p0 + tid, rec0 + tid);
+  start64<SIG>(Q, U, W, node, p0 + tid, rec0 + tid);
   ExitInfo<double> X;
   int st = W.n >= U.max_steps ? 2 : 0;
-  while (st == 0) st = iterate64(Q, U, W, X);
+  while (st == 0) st = iterate64<SIG>(Q, U, W, X);
   Q.recs[W.rec] = st == 1 ? finish64(Q, W, X) : unfinished_rec(U.max_steps);
+}
+
+__global__ void __launch_bounds__(256) walk_plain(const DevReq *__restrict__ reqs, uint32_t node, uint32_t p0,
+                                                  uint32_t count, uint64_t rec0) {
+  const DevReq &Q = reqs[0];
+  switch (Q.sig) {
+    case kSigNone: plain_body<kSigNone>(Q, node, p0, count, rec0); break;
+    case kSigZ: plain_body<kSigZ>(Q, node, p0, count, rec0); break;
+    case kSigZY: plain_body<kSigZY>(Q, node, p0, count, rec0); break;
+    case kSigZBox: plain_body<kSigZBox>(Q, node, p0, count, rec0); break;
+    case kSigZTri: plain_body<kSigZTri>(Q, node, p0, count, rec0); break;
+    default: plain_body<kSigGeneric>(Q, node, p0, count, rec0); break;
+  }
 }
 
 // ---------------------------------------------------------------------------
 // Persistent walker.
 // ---------------------------------------------------------------------------
+// Work a request still has: unclaimed tiles, tile remainders and suspended
+// walkers left by the previous slice (a rough count in tiles).
+__device__ __forceinline__ uint32_t work_left(const DevReq &Q) {
+  const uint32_t taken = uni(__hip_atomic_load(Q.tile_counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  uint32_t left = taken < Q.n_tiles ? Q.n_tiles - taken : 0u;
+  if (Q.slice_ctl) {
+    const uint32_t pc = uni(__hip_atomic_load(Q.slice_ctl + kPoolCursor, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    const uint32_t ec = uni(__hip_atomic_load(Q.slice_ctl + kExtraCursor, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    left += ec < Q.extra_in_n ? Q.extra_in_n - ec : 0u;
+    left += pc < Q.pool_in_n ? (Q.pool_in_n - pc + 63u) / 64u : 0u;
+  }
+  return left;
+}
+
 __device__ __forceinline__ uint32_t pick_request(const DevReq *__restrict__ reqs, uint32_t n_req) {
-  // the request with the most unclaimed tiles (ties: lowest index)
+  // the request with the most work left (ties: lowest index)
   uint32_t best = kNoRequest, best_left = 0;
   for (uint32_t r = 0; r < n_req; ++r) {
-    const uint32_t taken = uni(__hip_atomic_load(reqs[r].tile_counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    const uint32_t nt = reqs[r].n_tiles;
-    const uint32_t left = taken < nt ? nt - taken : 0u;
+    const uint32_t left = work_left(reqs[r]);
     if (left > best_left) { best_left = left; best = r; }
   }
   return best;
 }
 
+// Walk request Q with this wave until its work runs out (returns false) or
+// the wave's slice budget is spent (returns true: in-flight walkers and the
+// tile remainder were suspended for the next slice).  budget == 0: no limit.
 template <class T>
-__device__ __forceinline__ void run_request(const DevReq &Q) {
+__device__ __forceinline__ bool run_request(const DevReq &Q, uint32_t budget, uint32_t refill_mask, uint32_t &iters) {
   const uint32_t lane = __lane_id();
   typename T::Uni U;
   U.load(Q);
   const uint32_t n_tiles = Q.n_tiles;
+  uint32_t *ctl = Q.slice_ctl;
   typename T::Walker W;
   bool active = false;
 
-  // wave-uniform tile cursor
+  // wave-uniform cursors
   uint32_t t_node = 0, t_p0 = 0, t_next = 0, t_end = 0;
   uint64_t t_rec0 = 0;
+  bool pool_done = (ctl == nullptr) || (Q.pool_in_n == 0u);
+  bool extra_done = (ctl == nullptr) || (Q.extra_in_n == 0u);
   bool exhausted = false;
+  bool suspended = false;
   uint32_t finished = 0;   // paths this wave completed
 
   for (;;) {
-    // refill free lanes in rank order from the wave's tile, claiming tiles
-    const uint64_t freemask = __ballot(!active);
+    uint64_t freemask = __ballot(!active);
+    // refill every (refill_mask + 1) iterations, and whenever every lane is idle
+    const bool refill = ((iters & refill_mask) == 0u) || (freemask == ~0ull);
+    if (!refill) freemask = 0ull;
+    // resume walkers suspended by the previous slice first
+    if (freemask != 0ull && !pool_done) {
+      const uint32_t nfree = (uint32_t)__popcll(freemask);
+      const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(freemask >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)freemask, 0u));
+      uint32_t base = 0;
+      if (lane == 0) base = atomicAdd(ctl + kPoolCursor, nfree);
+      base = uni(base);
+      const uint32_t avail = base < Q.pool_in_n ? min(nfree, Q.pool_in_n - base) : 0u;
+      if (avail < nfree) pool_done = true;
+      if (!active && rank < avail) {
+        T::resume(Q, U, W, Q.pool_in[base + rank]);
+        active = true;
+      }
+      freemask = __ballot(!active);
+    }
+    // then refill free lanes in rank order from the wave's tile, claiming
+    // tile remainders of the previous slice before new tiles
     if (freemask != 0ull && !exhausted) {
       const uint32_t nfree = (uint32_t)__popcll(freemask);
       const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(freemask >> 32),
@@ -554,11 +740,22 @@ __device__ __forceinline__ void run_request(const DevReq &Q) {
       uint32_t given = 0;
       while (given < nfree) {
         if (t_next == t_end) {
-          uint32_t t = 0;
-          if (lane == 0) t = atomicAdd(Q.tile_counter, 1u);
-          t = uni(t);
-          if (t >= n_tiles) { exhausted = true; break; }
-          const DevTile Tl = Q.tiles[t];
+          const DevTile *src = nullptr;
+          if (!extra_done) {
+            uint32_t e = 0;
+            if (lane == 0) e = atomicAdd(ctl + kExtraCursor, 1u);
+            e = uni(e);
+            if (e < Q.extra_in_n) src = Q.extra_in + e;
+            else extra_done = true;
+          }
+          if (src == nullptr) {
+            uint32_t t = 0;
+            if (lane == 0) t = atomicAdd(Q.tile_counter, 1u);
+            t = uni(t);
+            if (t >= n_tiles) { exhausted = true; break; }
+            src = Q.tiles + t;
+          }
+          const DevTile Tl = *src;
           t_node = uni(Tl.node);
           t_p0 = uni(Tl.p0);
           t_next = t_p0;
@@ -575,6 +772,7 @@ __device__ __forceinline__ void run_request(const DevReq &Q) {
         given += take;
       }
     }
+    // every lane idle after a refill: this wave can get no more work here
     const uint64_t freemask_after_refill = __ballot(!active);
     if (freemask_after_refill == ~0ull) break;
 
@@ -587,13 +785,59 @@ __device__ __forceinline__ void run_request(const DevReq &Q) {
       }
     }
     finished += (uint32_t)__popcll(__ballot(!active)) - (uint32_t)__popcll(freemask_after_refill);
+    iters += 1u;
+    if (budget != 0u && iters >= budget) {
+      // suspend: in-flight walkers to pool_out, the tile remainder to extra_out
+      const uint64_t am = __ballot(active);
+      const uint32_t cnt = (uint32_t)__popcll(am);
+      if (cnt) {
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(ctl + kPoolOut, cnt);
+        base = uni(base);
+        const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(am >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)am, 0u));
+        // the host sizes pool_out for every lane of the launch; a count past
+        // the capacity is reported to it (the walker is not written)
+        if (active && base + r < Q.pool_cap) T::save(W, Q.pool_out[base + r]);
+      }
+      if (t_next < t_end) {
+        uint32_t e = 0;
+        if (lane == 0) e = atomicAdd(ctl + kExtraOut, 1u);
+        e = uni(e);
+        if (lane == 0 && e < Q.extra_cap) {
+          DevTile Tl;
+          Tl.node = t_node;
+          Tl.p0 = t_next;
+          Tl.count = t_end - t_next;
+          Tl.pad = 0;
+          Tl.rec0 = t_rec0 + (t_next - t_p0);
+          Tl.pad1 = 0;
+          Q.extra_out[e] = Tl;
+        }
+      }
+      suspended = true;
+      break;
+    }
   }
   if (lane == 0) atomicAdd(Q.done_counter, (unsigned long long)finished);
+  return suspended;
 }
 
-template <class T>
+template <template <int> class T>
+__device__ __forceinline__ bool run_dispatch(const DevReq &Q, uint32_t budget, uint32_t refill_mask, uint32_t &iters) {
+  switch (uni((uint32_t)Q.sig)) {
+    case kSigNone: return run_request<T<kSigNone>>(Q, budget, refill_mask, iters);
+    case kSigZ: return run_request<T<kSigZ>>(Q, budget, refill_mask, iters);
+    case kSigZY: return run_request<T<kSigZY>>(Q, budget, refill_mask, iters);
+    case kSigZBox: return run_request<T<kSigZBox>>(Q, budget, refill_mask, iters);
+    case kSigZTri: return run_request<T<kSigZTri>>(Q, budget, refill_mask, iters);
+    default: return run_request<T<kSigGeneric>>(Q, budget, refill_mask, iters);
+  }
+}
+
+template <template <int> class T>
 __device__ __forceinline__ void persist_body(const DevReq *__restrict__ reqs, uint32_t n_req,
-                                             const uint32_t *__restrict__ wave_start) {
+                                             const uint32_t *__restrict__ wave_start, uint32_t budget,
+                                             uint32_t refill_mask) {
   const uint32_t wid = uni((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   // initial request: waves are shared out in proportion to each request's work
   uint32_t r = kNoRequest;
@@ -601,23 +845,26 @@ __device__ __forceinline__ void persist_body(const DevReq *__restrict__ reqs, ui
     if (wid >= wave_start[i] && wid < wave_start[i + 1]) r = i;
   r = uni(r);
   if (r == kNoRequest) r = pick_request(reqs, n_req);
-  // Each visit either claims a tile or finds the request's tiles exhausted,
-  // after which pick_request never returns it again: the loop ends once every
-  // tile of every request has been claimed.
+  // Each visit either claims work or finds the request's work gone, after
+  // which pick_request never returns it again (claim cursors only grow): the
+  // loop ends once all work is claimed, or at the slice budget.
+  uint32_t iters = 0;
   while (r != kNoRequest) {
-    run_request<T>(reqs[r]);
+    if (run_dispatch<T>(reqs[r], budget, refill_mask, iters)) break;
     r = pick_request(reqs, n_req);
   }
 }
 
 __global__ void __launch_bounds__(256) walk_persist_f64(const DevReq *__restrict__ reqs, uint32_t n_req,
-                                                        const uint32_t *__restrict__ wave_start) {
-  persist_body<F64>(reqs, n_req, wave_start);
+                                                        const uint32_t *__restrict__ wave_start, uint32_t budget,
+                                             uint32_t refill_mask) {
+  persist_body<F64>(reqs, n_req, wave_start, budget, refill_mask);
 }
 
 __global__ void __launch_bounds__(256) walk_persist_f32(const DevReq *__restrict__ reqs, uint32_t n_req,
-                                                        const uint32_t *__restrict__ wave_start) {
-  persist_body<F32>(reqs, n_req, wave_start);
+                                                        const uint32_t *__restrict__ wave_start, uint32_t budget,
+                                             uint32_t refill_mask) {
+  persist_body<F32>(reqs, n_req, wave_start, budget, refill_mask);
 }
 
 // ---------------------------------------------------------------------------
@@ -738,11 +985,14 @@ hipError_t launch_walk_plain(const DevReq *req_dev, uint32_t node, uint32_t p0, 
 }
 
 hipError_t launch_walk_persist(int precision, const DevReq *reqs_dev, uint32_t n_req,
-                               const uint32_t *wave_start_dev, uint32_t blocks, uint32_t threads, hipStream_t st) {
+                               const uint32_t *wave_start_dev, uint32_t budget, uint32_t refill_mask, uint32_t blocks,
+                               uint32_t threads, hipStream_t st) {
   if (precision == 0)
-    hipLaunchKernelGGL(walk_persist_f64, dim3(blocks), dim3(threads), 0, st, reqs_dev, n_req, wave_start_dev);
+    hipLaunchKernelGGL(walk_persist_f64, dim3(blocks), dim3(threads), 0, st, reqs_dev, n_req, wave_start_dev, budget,
+                       refill_mask);
   else
-    hipLaunchKernelGGL(walk_persist_f32, dim3(blocks), dim3(threads), 0, st, reqs_dev, n_req, wave_start_dev);
+    hipLaunchKernelGGL(walk_persist_f32, dim3(blocks), dim3(threads), 0, st, reqs_dev, n_req, wave_start_dev, budget,
+                       refill_mask);
   return hipGetLastError();
 }
 

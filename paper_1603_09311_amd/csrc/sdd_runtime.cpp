@@ -11,6 +11,7 @@
 #include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -28,7 +29,8 @@ namespace sdd {
 hipError_t launch_walk_plain(const DevReq *req_dev, uint32_t node, uint32_t p0, uint32_t count, uint64_t rec0,
                              hipStream_t st);
 hipError_t launch_walk_persist(int precision, const DevReq *reqs_dev, uint32_t n_req,
-                               const uint32_t *wave_start_dev, uint32_t blocks, uint32_t threads, hipStream_t st);
+                               const uint32_t *wave_start_dev, uint32_t budget, uint32_t refill_mask, uint32_t blocks,
+                               uint32_t threads, hipStream_t st);
 hipError_t launch_reduce(const NodeJob *jobs_dev, uint32_t n_jobs, hipStream_t st);
 hipError_t launch_reset(uint32_t *tile_counters, unsigned long long *done, uint32_t n, hipStream_t st);
 int persist_blocks_per_cu(int precision, uint32_t threads);
@@ -157,6 +159,7 @@ struct Prepared {
   std::vector<uint64_t> pilot_off; // per node pilot record offset
   std::vector<uint32_t> pilot_cnt;
   int pass = 0;                    // 0 fixed/pilot, 1 extension
+  uint32_t slot = 0;               // done-counter slot in a prepared batch
 };
 
 struct Ticket {
@@ -167,13 +170,24 @@ struct Ticket {
   std::string error;
 };
 
+struct sdd_ctx;
+
+// exec for a caller thread.  The served worker takes exec once per slice and
+// gives way to any caller waiting for it (std::mutex promises no fairness).
+struct ExecGuard {
+  explicit ExecGuard(sdd_ctx *ctx);
+  ~ExecGuard();
+  sdd_ctx *ctx;
+};
+
 struct sdd_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   Arena arena;
   int cus = 0;
-  sdd_tuning tuning{256, 0, 512, 4096};
+  sdd_tuning tuning{256, 0, 512, 4096, 1};
   std::mutex exec;                 // one launch sequence at a time on the stream
+  std::atomic<int> exec_waiters{0};   // callers (not the served worker) waiting for exec
   std::mutex mu;                   // guards everything below and the arena
   char *alloc(size_t b) {
     std::lock_guard<std::mutex> lk(mu);
@@ -195,7 +209,21 @@ struct sdd_ctx {
   // timing of the last walk / reduction launches (guarded by exec)
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   sdd_stats stats{};
+  bool debug = false;              // SDD_DEBUG=1: per-slice trace of the served loop on stderr
 };
+
+ExecGuard::ExecGuard(sdd_ctx *c) : ctx(c) {
+  ctx->exec_waiters.fetch_add(1);
+  ctx->exec.lock();
+  ctx->exec_waiters.fetch_sub(1);
+}
+ExecGuard::~ExecGuard() { ctx->exec.unlock(); }
+
+// exec for the served worker: first let every waiting caller through.
+static std::unique_lock<std::mutex> worker_exec(sdd_ctx *ctx) {
+  while (ctx->exec_waiters.load() > 0) std::this_thread::yield();
+  return std::unique_lock<std::mutex>(ctx->exec);
+}
 
 // Takes no lock: a Prepared may be destroyed while ctx->mu is held.
 Prepared::~Prepared() {
@@ -294,6 +322,40 @@ static void fill_devreq(Prepared &P) {
     }
   }
   q.c[np] = alpha_of(r, m, m.desc.sigma_background) * r.dt / 2.0;
+  // model signature: air above z0 first, then at most one other primitive
+  q.sig = kSigGeneric;
+  const auto &R = m.regions;
+  if (np == 0) {
+    q.sig = kSigNone;
+  } else if (R[0].kind == SDD_HALF_Z_LT && np <= 2) {
+    q.sigp[0] = (float)(R[0].v[0] - q.zmid);
+    if (np == 1) {
+      q.sig = kSigZ;
+    } else if (R[1].kind == SDD_HALF_Y_LT) {
+      q.sig = kSigZY;
+      q.sigp[1] = (float)(R[1].v[0] - q.ymid);
+    } else if (R[1].kind == SDD_BOX) {
+      q.sig = kSigZBox;
+      q.sigp[1] = (float)(R[1].v[0] - q.ymid);
+      q.sigp[2] = (float)(R[1].v[1] - q.ymid);
+      q.sigp[3] = (float)(R[1].v[2] - q.zmid);
+      q.sigp[4] = (float)(R[1].v[3] - q.zmid);
+    } else if (R[1].kind == SDD_TRIANGLE) {
+      q.sig = kSigZTri;
+      // edge k from vertex k to vertex k+1 as A a + B b + C in centred coordinates
+      double vy[3], vz[3];
+      for (int i = 0; i < 3; ++i) {
+        vy[i] = R[1].v[2 * i] - q.ymid;
+        vz[i] = R[1].v[2 * i + 1] - q.zmid;
+      }
+      for (int k = 0; k < 3; ++k) {
+        const int l = (k + 1) % 3;
+        q.sigp[1 + 3 * k] = (float)(-(vz[l] - vz[k]));
+        q.sigp[2 + 3 * k] = (float)(vy[l] - vy[k]);
+        q.sigp[3 + 3 * k] = (float)((vz[l] - vz[k]) * vy[k] - (vy[l] - vy[k]) * vz[k]);
+      }
+    }
+  }
   q.fhy = (float)(0.5 * (q.y_hi - q.y_lo));
   q.fhz = (float)(0.5 * (q.z_hi - q.z_lo));
   q.fs = (float)q.s;
@@ -367,6 +429,17 @@ static void build_tiles(Prepared &P, uint32_t tile_paths) {
   P.n_paths = off;
 }
 
+// Paths per tile: the tuned size, lowered for a small request so that its
+// tiles reach every wave of a launch instead of queueing behind a few.
+static uint32_t tile_size(sdd_ctx *ctx, const Prepared &P) {
+  const uint32_t cap = ctx->tuning.tile_paths ? ctx->tuning.tile_paths : 512u;
+  uint64_t total = 0;
+  for (uint32_t c : P.pcnt) total += c;
+  const uint64_t waves = (uint64_t)std::max(ctx->cus, 1) * 4 * 4;
+  const uint64_t per = ((total + waves - 1) / waves + 63) / 64 * 64;
+  return (uint32_t)std::min<uint64_t>(cap, std::max<uint64_t>(per, 64));
+}
+
 static size_t pass_bytes(const Prepared &P) {
   return Arena::round(P.g.size() * 8) + Arena::round(P.nodes.size() * 8 + 16) +
          Arena::round(P.tiles.size() * sizeof(DevTile) + 16) + Arena::round(P.n_paths * sizeof(PathRec) + 16);
@@ -388,7 +461,7 @@ static void release_all(sdd_ctx *ctx, Prepared &P) {
 
 // Allocate and upload one pass's inputs (caller holds ctx->mu).
 static sdd_status upload_pass(sdd_ctx *ctx, Prepared &P) {
-  build_tiles(P, ctx->tuning.tile_paths ? ctx->tuning.tile_paths : 512u);
+  build_tiles(P, tile_size(ctx, P));
   P.d_g = ctx->alloc(P.g.size() * 8);
   P.d_nodes = ctx->alloc(P.nodes.size() * 8 + 16);
   P.d_tiles = ctx->alloc(P.tiles.size() * sizeof(DevTile) + 16);
@@ -430,6 +503,10 @@ struct BatchScratch {
     d_reqs = d_ctr = d_done = d_ws = nullptr;
   }
 };
+
+static uint32_t refill_mask(const sdd_ctx *ctx) {
+  return ctx->tuning.refill_every ? ctx->tuning.refill_every - 1u : 0u;
+}
 
 static void launch_shape(sdd_ctx *ctx, int precision, uint32_t &blocks, uint32_t &threads) {
   threads = ctx->tuning.block_threads ? ctx->tuning.block_threads : 256u;
@@ -485,7 +562,8 @@ static sdd_status run_group(sdd_ctx *ctx, std::vector<Prepared *> &passes, int p
   if (st == SDD_OK) check(hipEventRecord(ctx->ev[0], ctx->stream), "event");
   if (st == SDD_OK)
     check(launch_walk_persist(precision, reinterpret_cast<const DevReq *>(B.d_reqs), n,
-                              reinterpret_cast<const uint32_t *>(B.d_ws), blocks, threads, ctx->stream),
+                              reinterpret_cast<const uint32_t *>(B.d_ws), 0u, refill_mask(ctx), blocks, threads,
+                              ctx->stream),
           "walk_persist");
   if (st == SDD_OK) check(hipEventRecord(ctx->ev[1], ctx->stream), "event");
   std::vector<unsigned long long> done(n, 0);
@@ -703,7 +781,7 @@ static sdd_status execute(sdd_ctx *ctx, std::vector<Prepared *> &Ps, std::vector
 // Workspace a request needs while it runs (upper bound for target-SE
 // requests, whose extension size is known only after the pilot).
 static uint64_t footprint(sdd_ctx *ctx, Prepared &P) {
-  build_tiles(P, ctx->tuning.tile_paths ? ctx->tuning.tile_paths : 512u);
+  build_tiles(P, tile_size(ctx, P));
   const uint64_t n = P.pbeg.size();
   uint64_t b = pass_bytes(P) + Arena::round(n * (sizeof(NodeOut) + sizeof(NodeJob))) + 4 * 1024 +
                Arena::round(sizeof(DevReq) * 2);
@@ -722,13 +800,243 @@ static void finish_ticket(sdd_ctx *ctx, Ticket &T, sdd_status st, const char *er
   T.done = true;
 }
 
+// A request in flight in served mode: its passes run in time slices of the
+// persistent walker; at each slice end the walkers still running are
+// suspended into `pool` and partly used tiles into `extra`, double-buffered
+// (index `par` is what the next slice resumes from).
+struct Flight {
+  std::shared_ptr<Ticket> T;
+  Prepared *P = nullptr;
+  bool uploaded = false;
+  char *d_pool[2] = {nullptr, nullptr}, *d_extra[2] = {nullptr, nullptr};
+  uint32_t pool_cap = 0, extra_cap = 0;
+  int par = 0;
+  uint32_t pool_n = 0, extra_n = 0;
+  uint32_t tile_counter = 0;
+  uint64_t done = 0;
+  uint64_t reserved = 0;   // workspace bytes counted at admission
+};
+
+// Control words of one flight for one slice (device and host copies).
+struct FlightCtl {
+  uint32_t slice[4];
+  uint32_t tile_counter;
+  uint32_t pad;
+  unsigned long long done;
+};
+
+static void release_flight(sdd_ctx *ctx, Flight &F) {
+  for (int i = 0; i < 2; ++i) {
+    ctx->release(F.d_pool[i]);
+    ctx->release(F.d_extra[i]);
+    F.d_pool[i] = F.d_extra[i] = nullptr;
+  }
+  if (F.P) release_all(ctx, *F.P);
+}
+
+// Pools large enough for every lane and wave of a launch; suspended walkers
+// already waiting in the input pool are carried over.
+static sdd_status ensure_pools(sdd_ctx *ctx, Flight &F, uint32_t lanes, uint32_t waves) {
+  if (F.pool_cap >= lanes && F.extra_cap >= waves && F.d_pool[0]) return SDD_OK;
+  char *np[2] = {ctx->alloc((size_t)lanes * sizeof(SuspRec)), ctx->alloc((size_t)lanes * sizeof(SuspRec))};
+  char *ne[2] = {ctx->alloc((size_t)waves * sizeof(DevTile)), ctx->alloc((size_t)waves * sizeof(DevTile))};
+  if (!np[0] || !np[1] || !ne[0] || !ne[1]) {
+    for (int i = 0; i < 2; ++i) { ctx->release(np[i]); ctx->release(ne[i]); }
+    return fail(SDD_E_NOMEM, "no workspace left for the suspension pools");
+  }
+  if (F.pool_n) HIP_TRY(hipMemcpyAsync(np[F.par], F.d_pool[F.par], (size_t)F.pool_n * sizeof(SuspRec),
+                                       hipMemcpyDeviceToDevice, ctx->stream));
+  if (F.extra_n) HIP_TRY(hipMemcpyAsync(ne[F.par], F.d_extra[F.par], (size_t)F.extra_n * sizeof(DevTile),
+                                        hipMemcpyDeviceToDevice, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  for (int i = 0; i < 2; ++i) {
+    ctx->release(F.d_pool[i]);
+    ctx->release(F.d_extra[i]);
+    F.d_pool[i] = np[i];
+    F.d_extra[i] = ne[i];
+  }
+  F.pool_cap = lanes;
+  F.extra_cap = waves;
+  return SDD_OK;
+}
+
+// One time slice over the flights of one precision (caller holds exec).
+static sdd_status run_slice(sdd_ctx *ctx, std::vector<Flight *> &fl, int precision) {
+  const uint32_t n = (uint32_t)fl.size();
+  if (n == 0) return SDD_OK;
+  uint32_t blocks, threads;
+  launch_shape(ctx, precision, blocks, threads);
+  const uint32_t lanes = blocks * threads, waves = blocks * (threads / 64);
+  for (auto *F : fl) {
+    sdd_status st = ensure_pools(ctx, *F, lanes, waves);
+    if (st != SDD_OK) return st;
+  }
+  char *d_reqs = ctx->alloc(n * sizeof(DevReq));
+  char *d_ctl = ctx->alloc(n * sizeof(FlightCtl));
+  char *d_ws = ctx->alloc((n + 1) * sizeof(uint32_t));
+  sdd_status st = SDD_OK;
+  if (!d_reqs || !d_ctl || !d_ws) st = fail(SDD_E_NOMEM, "no workspace left for a slice");
+  std::vector<DevReq> dq(n);
+  std::vector<FlightCtl> ctl(n);
+  std::vector<uint32_t> ws(n + 1, 0);
+  // Wave shares, shortest remaining work first: every flight holds at least
+  // waves / 4n waves, then flights in order of remaining paths get the waves
+  // that cover them.  Waves left over start on whichever flight has the most
+  // work left, as do waves whose flight runs dry.
+  std::vector<uint64_t> rem(n), share(n);
+  std::vector<uint32_t> order(n);
+  const uint64_t floor_w = std::max<uint64_t>(1, waves / (4ull * n));
+  uint64_t given = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    rem[i] = fl[i]->P->n_paths - std::min<uint64_t>(fl[i]->done, fl[i]->P->n_paths);
+    share[i] = std::min<uint64_t>({(rem[i] + 63) / 64, floor_w, waves - given});
+    given += share[i];
+    order[i] = i;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return rem[a] < rem[b]; });
+  for (uint32_t i : order) {
+    const uint64_t add = std::min<uint64_t>((rem[i] + 63) / 64 - share[i], waves - given);
+    share[i] += add;
+    given += add;
+  }
+  uint64_t acc = 0;
+  for (uint32_t i = 0; i < n && st == SDD_OK; ++i) {
+    Flight &F = *fl[i];
+    FlightCtl &c = ctl[i];
+    std::memset(&c, 0, sizeof(c));
+    c.tile_counter = F.tile_counter;
+    c.done = F.done;
+    FlightCtl *dc = reinterpret_cast<FlightCtl *>(d_ctl) + i;
+    DevReq &q = dq[i];
+    q = F.P->dreq;
+    q.tile_counter = &dc->tile_counter;
+    q.done_counter = &dc->done;
+    q.slice_ctl = dc->slice;
+    q.pool_in = reinterpret_cast<const SuspRec *>(F.d_pool[F.par]);
+    q.pool_in_n = F.pool_n;
+    q.pool_out = reinterpret_cast<SuspRec *>(F.d_pool[F.par ^ 1]);
+    q.pool_cap = F.pool_cap;
+    q.extra_in = reinterpret_cast<const DevTile *>(F.d_extra[F.par]);
+    q.extra_in_n = F.extra_n;
+    q.extra_out = reinterpret_cast<DevTile *>(F.d_extra[F.par ^ 1]);
+    q.extra_cap = F.extra_cap;
+    ws[i] = (uint32_t)acc;
+    acc += share[i];
+  }
+  ws[n] = (uint32_t)acc;
+  hipError_t e = hipSuccess;
+  if (st == SDD_OK) {
+    e = hipMemcpyAsync(d_reqs, dq.data(), n * sizeof(DevReq), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_ctl, ctl.data(), n * sizeof(FlightCtl), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_ws, ws.data(), (n + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipEventRecord(ctx->ev[0], ctx->stream);
+    if (e == hipSuccess)
+      e = launch_walk_persist(precision, reinterpret_cast<const DevReq *>(d_reqs), n,
+                              reinterpret_cast<const uint32_t *>(d_ws),
+                              ctx->tuning.slice_iters ? ctx->tuning.slice_iters : 4096u, refill_mask(ctx), blocks, threads,
+                              ctx->stream);
+    if (e == hipSuccess) e = hipEventRecord(ctx->ev[1], ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ctl.data(), d_ctl, n * sizeof(FlightCtl), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) st = fail(SDD_E_DEVICE, "slice: %s", hipGetErrorString(e));
+  }
+  ctx->release(d_reqs);
+  ctx->release(d_ctl);
+  ctx->release(d_ws);
+  if (st != SDD_OK) return st;
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]) == hipSuccess) ctx->stats.last_walk_ms = ms;
+  ctx->stats.launches += 1;
+  for (uint32_t i = 0; i < n; ++i) {
+    Flight &F = *fl[i];
+    const FlightCtl &c = ctl[i];
+    if (c.slice[kPoolOut] > F.pool_cap || c.slice[kExtraOut] > F.extra_cap)
+      return fail(SDD_E_DEVICE, "suspension pool overflow (%u > %u walkers)", c.slice[kPoolOut], F.pool_cap);
+    F.par ^= 1;
+    F.pool_n = c.slice[kPoolOut];
+    F.extra_n = c.slice[kExtraOut];
+    F.tile_counter = c.tile_counter;
+    F.done = c.done;
+  }
+  return SDD_OK;
+}
+
+// Finish the flights whose pass has every path done: a pilot is turned into
+// its extension; everything else is reduced and handed back.
+static void complete_flights(sdd_ctx *ctx, std::vector<std::unique_ptr<Flight>> &flights) {
+  std::vector<Flight *> fin;
+  for (auto &F : flights) {
+    if (F->done < F->P->n_paths || F->pool_n || F->extra_n) continue;
+    if (F->P->req.target_rel_se > 0.0 && F->P->pass == 0) {
+      std::vector<Prepared *> one{F->P};
+      std::vector<NodeOut> rows;
+      sdd_status st = reduce_passes(ctx, one, rows);
+      if (st == SDD_OK) {
+        plan_extension(*F->P, rows.data());
+        F->P->d_recs_pilot = F->P->d_recs;
+        F->P->d_recs = nullptr;
+        release_pass(ctx, *F->P);
+        st = upload_pass(ctx, *F->P);
+      }
+      if (st == SDD_OK) {
+        F->uploaded = true;
+        F->tile_counter = 0;
+        F->done = 0;
+        F->pool_n = F->extra_n = 0;
+        continue;
+      }
+      F->T->error = g_last_error;
+      F->T->status = st;
+      fin.push_back(F.get());
+      continue;
+    }
+    fin.push_back(F.get());
+  }
+  if (fin.empty()) return;
+  std::vector<Prepared *> Ps;
+  for (auto *F : fin)
+    if (F->T->status == SDD_OK) Ps.push_back(F->P);
+  std::vector<NodeOut> rows;
+  sdd_status st = reduce_passes(ctx, Ps, rows);
+  std::string err = st == SDD_OK ? std::string() : g_last_error;
+  uint64_t row = 0;
+  for (auto *P : Ps) {
+    Flight *F = nullptr;
+    for (auto *f : fin)
+      if (f->P == P) F = f;
+    if (st == SDD_OK && !F->T->cancelled) {
+      scatter(*P, rows.data() + row, &F->T->res);
+      sdd_status s2 = copy_records(ctx, *P, &F->T->res);
+      if (s2 != SDD_OK) { F->T->status = s2; F->T->error = g_last_error; }
+    } else if (st != SDD_OK) {
+      F->T->status = st;
+      F->T->error = err;
+    }
+    row += P->pbeg.size();
+  }
+  for (auto *F : fin) release_flight(ctx, *F);
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (auto *F : fin) {
+      finish_ticket(ctx, *F->T, F->T->status, F->T->error.empty() ? nullptr : F->T->error.c_str());
+      F->T->P.reset();
+      F->P = nullptr;
+    }
+  }
+  flights.erase(std::remove_if(flights.begin(), flights.end(), [](const std::unique_ptr<Flight> &F) { return F->P == nullptr; }),
+                flights.end());
+  ctx->done_cv.notify_all();
+}
+
 static void worker_main(sdd_ctx *ctx) {
   hipSetDevice(ctx->device);
+  std::vector<std::unique_ptr<Flight>> flights;
+  uint64_t reserved = 0;   // workspace promised to flights
   for (;;) {
-    std::vector<std::shared_ptr<Ticket>> batch;
+    std::vector<std::unique_ptr<Flight>> dropped;
     {
       std::unique_lock<std::mutex> lk(ctx->mu);
-      ctx->cv.wait(lk, [&] { return ctx->stop || !ctx->queue.empty(); });
+      ctx->cv.wait(lk, [&] { return ctx->stop || !ctx->queue.empty() || !flights.empty(); });
       if (ctx->stop) {
         for (auto &T : ctx->queue) {
           T->cancelled = true;
@@ -736,58 +1044,93 @@ static void worker_main(sdd_ctx *ctx) {
           T->P.reset();
         }
         ctx->queue.clear();
-        ctx->done_cv.notify_all();
-        return;
+        for (auto &F : flights) F->T->cancelled = true;
       }
+      // cancelled flights leave at the slice boundary
+      for (auto &F : flights)
+        if (F->T->cancelled) dropped.push_back(std::move(F));
+      flights.erase(std::remove(flights.begin(), flights.end(), nullptr), flights.end());
       // admission by workspace: FIFO while the footprints fit
-      uint64_t room = ctx->arena.largest_free();
-      while (!ctx->queue.empty()) {
+      while (!ctx->stop && !ctx->queue.empty()) {
         auto T = ctx->queue.front();
-        lk.unlock();
-        const uint64_t need = footprint(ctx, *T->P);
-        lk.lock();
+        const uint64_t pools = 2ull * 1024 * 1024 * 64 + 2ull * 64 * 1024 * 32;   // at most 2^20 lanes
+        const uint64_t need = footprint(ctx, *T->P) + pools;
         if (need > ctx->arena.size()) {
           ctx->queue.pop_front();
           finish_ticket(ctx, *T, SDD_E_NOMEM, "request can never fit in the workspace");
           T->P.reset();
           continue;
         }
-        if (need > room && !batch.empty()) break;
-        if (need > room) break;   // wait for memory held by blocking callers
-        room -= need;
-        batch.push_back(T);
+        // the promised footprints of everything in flight stay within the
+        // workspace (what blocking callers and models hold counts too)
+        const uint64_t others = ctx->arena.used() > reserved ? ctx->arena.used() - reserved : 0;
+        if (reserved + need + others > ctx->arena.size()) break;   // wait for memory to free up
+        auto F = std::make_unique<Flight>();
+        F->T = T;
+        F->P = T->P.get();
+        F->reserved = need;
+        reserved += need;
+        flights.push_back(std::move(F));
         ctx->queue.pop_front();
       }
     }
-    if (batch.empty()) {
-      std::this_thread::sleep_for(std::chrono::milliseconds(1));
-      continue;
-    }
-    std::vector<Prepared *> Ps;
-    for (auto &T : batch) Ps.push_back(T->P.get());
-    std::vector<std::vector<NodeOut>> rows;
-    sdd_status st;
-    std::string err;
-    {
-      std::lock_guard<std::mutex> ex(ctx->exec);
-      st = execute(ctx, Ps, rows);
-      if (st != SDD_OK) err = g_last_error;
-      for (size_t i = 0; i < batch.size() && st == SDD_OK; ++i) {
-        if (batch[i]->cancelled) continue;
-        scatter(*Ps[i], rows[i].data(), &batch[i]->res);
-        sdd_status s2 = copy_records(ctx, *Ps[i], &batch[i]->res);
-        if (s2 != SDD_OK) { st = s2; err = g_last_error; }
-      }
-      for (auto *P : Ps) release_all(ctx, *P);
-    }
-    {
+    for (auto &F : dropped) {
+      auto ex = worker_exec(ctx);
+      release_flight(ctx, *F);
+      reserved -= F->reserved;
       std::lock_guard<std::mutex> lk(ctx->mu);
-      for (auto &T : batch) {
-        finish_ticket(ctx, *T, st, st == SDD_OK ? nullptr : err.c_str());
-        T->P.reset();
-      }
+      finish_ticket(ctx, *F->T, SDD_E_CANCELLED, "cancelled");
+      F->T->P.reset();
     }
-    ctx->done_cv.notify_all();
+    if (!dropped.empty()) ctx->done_cv.notify_all();
+    if (ctx->stop && flights.empty()) return;
+    if (flights.empty()) continue;
+    {
+      auto ex = worker_exec(ctx);
+      // upload newly admitted requests
+      for (auto &F : flights) {
+        if (F->uploaded) continue;
+        sdd_status st = upload_pass(ctx, *F->P);
+        if (st == SDD_OK) {
+          F->uploaded = true;
+        } else {
+          F->T->status = st;
+          F->T->error = g_last_error;
+          F->done = F->P->n_paths;   // completes (with the error) below
+          F->uploaded = true;
+        }
+      }
+      // one slice per precision present
+      sdd_status st = SDD_OK;
+      for (int prec : {SDD_FP32_MIXED, SDD_FP64}) {
+        std::vector<Flight *> group;
+        for (auto &F : flights)
+          if ((int)F->P->dreq.precision == prec && F->T->status == SDD_OK) group.push_back(F.get());
+        st = run_slice(ctx, group, prec);
+        if (st != SDD_OK) {
+          for (auto *F : group) {
+            F->T->status = st;
+            F->T->error = g_last_error;
+            F->done = F->P->n_paths;
+            F->pool_n = F->extra_n = 0;
+          }
+        }
+      }
+      if (ctx->debug) {
+        std::fprintf(stderr, "[sdd] slice %.3f ms:", ctx->stats.last_walk_ms);
+        for (auto &F : flights)
+          std::fprintf(stderr, " {done %llu/%llu tiles %u/%u pool %u extra %u}", (unsigned long long)F->done,
+                       (unsigned long long)F->P->n_paths, F->tile_counter, F->P->dreq.n_tiles, F->pool_n,
+                       F->extra_n);
+        std::fprintf(stderr, "\n");
+      }
+      const size_t before = flights.size();
+      uint64_t freed = 0;
+      for (auto &F : flights) freed += F->reserved;
+      complete_flights(ctx, flights);
+      for (auto &F : flights) freed -= F->reserved;
+      if (flights.size() != before) reserved -= freed;
+    }
   }
 }
 
@@ -832,6 +1175,8 @@ sdd_status sdd_create(int device, void *workspace_dev, size_t workspace_bytes, v
   ctx->device = device;
   ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
   ctx->cus = prop.multiProcessorCount;
+  const char *dbg = std::getenv("SDD_DEBUG");
+  ctx->debug = dbg && dbg[0] == '1';
   ctx->arena.init(reinterpret_cast<char *>(workspace_dev), workspace_bytes);
   *out = ctx.release();
   return SDD_OK;
@@ -846,7 +1191,7 @@ sdd_status sdd_destroy(sdd_ctx_t ctx) {
   ctx->cv.notify_all();
   if (ctx->worker.joinable()) ctx->worker.join();
   {
-    std::lock_guard<std::mutex> ex(ctx->exec);   // no blocking call still running
+    ExecGuard ex(ctx);   // no blocking call still running
     for (auto &e : ctx->ev)
       if (e) hipEventDestroy(e);
   }
@@ -893,7 +1238,7 @@ sdd_status sdd_model_create(sdd_ctx_t ctx, const sdd_model_desc *d, sdd_model_t 
   m->dev = ctx->alloc(sizeof(DevModel));
   if (!m->dev) return fail(SDD_E_NOMEM, "no workspace left for the model");
   {
-    std::lock_guard<std::mutex> ex(ctx->exec);
+    ExecGuard ex(ctx);
     hipError_t e = hipSetDevice(ctx->device);
     if (e == hipSuccess) e = hipMemcpyAsync(m->dev, &dm, sizeof(dm), hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
@@ -936,7 +1281,7 @@ sdd_status sdd_solve_batch(sdd_ctx_t ctx, uint32_t n, const sdd_request *reqs, s
     sdd_status st = prepare(ctx, &reqs[i], own[i]);
     if (st != SDD_OK) return st;
   }
-  std::lock_guard<std::mutex> ex(ctx->exec);
+  ExecGuard ex(ctx);
   HIP_TRY(hipSetDevice(ctx->device));
   std::vector<Prepared *> Ps;
   for (auto &P : own) Ps.push_back(P.get());
@@ -958,7 +1303,7 @@ sdd_status sdd_solve_plain(sdd_ctx_t ctx, const sdd_request *req, sdd_result *re
   sdd_status st = prepare(ctx, req, P);
   if (st != SDD_OK) return st;
   P->dreq.precision = SDD_FP64;
-  std::lock_guard<std::mutex> ex(ctx->exec);
+  ExecGuard ex(ctx);
   HIP_TRY(hipSetDevice(ctx->device));
   st = upload_pass(ctx, *P);
   if (st != SDD_OK) return st;
@@ -1063,18 +1408,21 @@ sdd_status sdd_set_tuning(sdd_ctx_t ctx, const sdd_tuning *t) {
     return fail(SDD_E_INVALID, "block_threads must be a multiple of 64, at most 256 (the walker's launch bound)");
   if (t->blocks_per_cu > 64) return fail(SDD_E_INVALID, "blocks_per_cu at most 64");
   if (t->tile_paths > (1u << 24)) return fail(SDD_E_INVALID, "tile_paths at most 2^24");
-  std::lock_guard<std::mutex> ex(ctx->exec);
+  if (t->refill_every > 64 || (t->refill_every & (t->refill_every - 1)) != 0)
+    return fail(SDD_E_INVALID, "refill_every must be a power of 2, at most 64");
+  ExecGuard ex(ctx);
   std::lock_guard<std::mutex> lk(ctx->mu);
   ctx->tuning = *t;
   if (!ctx->tuning.block_threads) ctx->tuning.block_threads = 256;
   if (!ctx->tuning.tile_paths) ctx->tuning.tile_paths = 512;
   if (!ctx->tuning.slice_iters) ctx->tuning.slice_iters = 4096;
+  if (!ctx->tuning.refill_every) ctx->tuning.refill_every = 1;
   return SDD_OK;
 }
 
 sdd_status sdd_get_stats(sdd_ctx_t ctx, sdd_stats *out) {
   if (!ctx || !out) return fail(SDD_E_INVALID, "NULL argument");
-  std::lock_guard<std::mutex> ex(ctx->exec);
+  ExecGuard ex(ctx);
   *out = ctx->stats;
   return SDD_OK;
 }
@@ -1083,6 +1431,294 @@ sdd_status sdd_get_tuning(sdd_ctx_t ctx, sdd_tuning *t) {
   if (!ctx || !t) return fail(SDD_E_INVALID, "NULL argument");
   std::lock_guard<std::mutex> lk(ctx->mu);
   *t = ctx->tuning;
+  return SDD_OK;
+}
+
+sdd_status sdd_autotune(sdd_ctx_t ctx, const sdd_request *req, uint32_t sample_paths, sdd_tuning *chosen,
+                        sdd_tune_trial *trials, uint32_t max_trials, uint32_t *n_trials) {
+  if (!ctx || !req) return fail(SDD_E_INVALID, "NULL argument");
+  if (req->n_nodes == 0) return fail(SDD_E_INVALID, "autotune needs a request with nodes");
+  if (trials == nullptr && max_trials) return fail(SDD_E_INVALID, "trials is NULL");
+  if (n_trials) *n_trials = 0;
+  sdd_request s = *req;
+  s.target_rel_se = 0.0;
+  if (!sample_paths) {
+    uint32_t b, t;
+    launch_shape(ctx, (int)req->precision, b, t);
+    sample_paths = (uint32_t)std::min<uint64_t>(1u << 24, (4ull * b * t + req->n_nodes - 1) / req->n_nodes);
+  }
+  std::vector<uint32_t> cnt(req->n_nodes);
+  uint64_t total = 0;
+  for (uint32_t j = 0; j < req->n_nodes; ++j) {
+    const uint32_t c = req->path_count ? req->path_count[j] : req->paths_uniform;
+    cnt[j] = std::min(c, sample_paths);
+    total += cnt[j];
+  }
+  if (total == 0) return fail(SDD_E_INVALID, "autotune needs a request with paths");
+  s.path_count = cnt.data();
+  std::unique_ptr<Prepared> P;
+  sdd_status st = prepare(ctx, &s, P);
+  if (st != SDD_OK) return st;
+
+  ExecGuard ex(ctx);
+  HIP_TRY(hipSetDevice(ctx->device));
+  const sdd_tuning base = ctx->tuning;
+  uint32_t n_done = 0;
+  auto trial = [&](const sdd_tuning &t, double &ms) -> sdd_status {
+    {
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      ctx->tuning = t;
+    }
+    std::vector<Prepared *> Ps{P.get()};
+    std::vector<std::vector<NodeOut>> rows;
+    sdd_status r = execute(ctx, Ps, rows);
+    release_all(ctx, *P);
+    if (r != SDD_OK) return r;
+    ms = ctx->stats.last_walk_ms;
+    if (n_done < max_trials) {
+      trials[n_done].tuning = t;
+      trials[n_done].walk_ms = ms;
+      trials[n_done].walk_steps_per_s = ms > 0 ? (double)ctx->stats.last_walk_steps / (ms * 1e-3) : 0.0;
+    }
+    ++n_done;
+    return SDD_OK;
+  };
+  // Coordinate descent from the current tuning: launch block size, then
+  // tile size, then refill cadence, each swept with the others held.
+  sdd_tuning best = base;
+  double best_ms = 0.0;
+  double warm = 0.0;
+  st = trial(best, warm);   // warm-up (first-touch of the workspace, clocks)
+  if (st == SDD_OK) st = trial(best, best_ms);
+  const uint32_t threads_c[] = {256, 128, 64};
+  const uint32_t tiles_c[] = {128, 512, 2048, 8192};
+  const uint32_t refill_c[] = {1, 2, 4, 8};
+  for (int axis = 0; axis < 3 && st == SDD_OK; ++axis) {
+    const uint32_t *vals = axis == 0 ? threads_c : axis == 1 ? tiles_c : refill_c;
+    const int nv = axis == 0 ? 3 : 4;
+    sdd_tuning round_best = best;
+    for (int k = 0; k < nv && st == SDD_OK; ++k) {
+      sdd_tuning t = best;
+      uint32_t &field = axis == 0 ? t.block_threads : axis == 1 ? t.tile_paths : t.refill_every;
+      if (field == vals[k]) continue;
+      field = vals[k];
+      if (axis == 0) t.blocks_per_cu = 0;   // occupancy of the new block size
+      double ms = 0.0;
+      st = trial(t, ms);
+      if (st == SDD_OK && ms < best_ms) { best_ms = ms; round_best = t; }
+    }
+    best = round_best;
+  }
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->tuning = st == SDD_OK ? best : base;
+  }
+  if (n_trials) *n_trials = std::min(n_done, max_trials);
+  if (st != SDD_OK) return st;
+  if (chosen) *chosen = best;
+  return SDD_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Prepared batches replayed as HIP graphs.
+// ---------------------------------------------------------------------------
+struct sdd_batch {
+  sdd_ctx *ctx = nullptr;
+  std::vector<std::unique_ptr<Prepared>> Ps;
+  struct Group {
+    int prec;
+    std::vector<Prepared *> P;
+    char *d_reqs = nullptr, *d_ctr = nullptr, *d_done = nullptr, *d_ws = nullptr;
+    uint32_t blocks = 0, threads = 0;
+  };
+  std::vector<Group> groups;
+  char *d_jobs = nullptr, *d_out = nullptr, *d_done_all = nullptr;
+  NodeOut *h_out = nullptr;                // pinned
+  unsigned long long *h_done = nullptr;    // pinned, one per request (group order)
+  uint64_t total_nodes = 0;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+static void batch_free(sdd_batch *b) {
+  if (!b) return;
+  sdd_ctx *ctx = b->ctx;
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  if (b->cap) hipStreamDestroy(b->cap);
+  if (b->h_out) hipHostFree(b->h_out);
+  if (b->h_done) hipHostFree(b->h_done);
+  for (auto &g : b->groups) {
+    ctx->release(g.d_reqs);
+    ctx->release(g.d_ctr);
+    ctx->release(g.d_ws);
+  }
+  ctx->release(b->d_done_all);
+  ctx->release(b->d_jobs);
+  ctx->release(b->d_out);
+  for (auto &P : b->Ps) release_all(ctx, *P);
+  delete b;
+}
+
+extern "C" {
+
+sdd_status sdd_batch_create(sdd_ctx_t ctx, uint32_t n, const sdd_request *reqs, sdd_batch_t *out) {
+  if (!ctx || !out || (n && !reqs)) return fail(SDD_E_INVALID, "NULL argument");
+  *out = nullptr;
+  auto *b = new sdd_batch();
+  b->ctx = ctx;
+  b->Ps.resize(n);
+  for (uint32_t i = 0; i < n; ++i) {
+    if (reqs[i].target_rel_se > 0.0) {
+      batch_free(b);
+      return fail(SDD_E_INVALID, "request %u: a prepared batch takes fixed path counts", i);
+    }
+    sdd_status st = prepare(ctx, &reqs[i], b->Ps[i]);
+    if (st != SDD_OK) { batch_free(b); return st; }
+  }
+  ExecGuard ex(ctx);
+  auto bail = [&](sdd_status st) { batch_free(b); return st; };
+  if (hipSetDevice(ctx->device) != hipSuccess) return bail(fail(SDD_E_DEVICE, "hipSetDevice failed"));
+  for (auto &P : b->Ps) {
+    sdd_status st = upload_pass(ctx, *P);
+    if (st != SDD_OK) return bail(st);
+    b->total_nodes += P->pbeg.size();
+  }
+  // per-precision descriptors, counters and wave shares
+  b->d_done_all = ctx->alloc(std::max<size_t>(n, 1) * sizeof(unsigned long long));
+  if (!b->d_done_all) return bail(fail(SDD_E_NOMEM, "no workspace for the batch counters"));
+  uint32_t done_slot = 0;
+  std::vector<uint32_t> done_index(n, 0);
+  for (int prec : {SDD_FP32_MIXED, SDD_FP64}) {
+    sdd_batch::Group g;
+    g.prec = prec;
+    for (uint32_t i = 0; i < n; ++i)
+      if ((int)b->Ps[i]->dreq.precision == prec) g.P.push_back(b->Ps[i].get());
+    if (g.P.empty()) continue;
+    const uint32_t m = (uint32_t)g.P.size();
+    launch_shape(ctx, prec, g.blocks, g.threads);
+    const uint32_t waves = g.blocks * (g.threads / 64);
+    g.d_reqs = ctx->alloc(m * sizeof(DevReq));
+    g.d_ctr = ctx->alloc(m * sizeof(uint32_t));
+    g.d_ws = ctx->alloc((m + 1) * sizeof(uint32_t));
+    g.d_done = b->d_done_all + (size_t)done_slot * sizeof(unsigned long long);
+    if (!g.d_reqs || !g.d_ctr || !g.d_ws) {
+      b->groups.push_back(g);
+      return bail(fail(SDD_E_NOMEM, "no workspace for the batch descriptors"));
+    }
+    std::vector<DevReq> dq(m);
+    std::vector<uint32_t> ws(m + 1, 0);
+    double total = 0.0, acc = 0.0;
+    for (auto *P : g.P) total += (double)P->n_paths;
+    for (uint32_t i = 0; i < m; ++i) {
+      dq[i] = g.P[i]->dreq;
+      dq[i].tile_counter = reinterpret_cast<uint32_t *>(g.d_ctr) + i;
+      dq[i].done_counter = reinterpret_cast<unsigned long long *>(g.d_done) + i;
+      ws[i] = total > 0 ? (uint32_t)std::llround(acc / total * waves) : 0u;
+      acc += (double)g.P[i]->n_paths;
+      for (uint32_t k = 0; k < n; ++k)
+        if (b->Ps[k].get() == g.P[i]) done_index[k] = done_slot + i;
+    }
+    ws[m] = waves;
+    done_slot += m;
+    if (hipMemcpy(g.d_reqs, dq.data(), m * sizeof(DevReq), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(g.d_ws, ws.data(), (m + 1) * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess) {
+      b->groups.push_back(g);
+      return bail(fail(SDD_E_DEVICE, "batch descriptor upload failed"));
+    }
+    b->groups.push_back(g);
+  }
+  // reduction jobs in request order
+  b->d_out = ctx->alloc(std::max<uint64_t>(b->total_nodes, 1) * sizeof(NodeOut));
+  b->d_jobs = ctx->alloc(std::max<uint64_t>(b->total_nodes, 1) * sizeof(NodeJob));
+  if (!b->d_out || !b->d_jobs) return bail(fail(SDD_E_NOMEM, "no workspace for the batch reduction"));
+  std::vector<NodeJob> jobs;
+  uint64_t row = 0;
+  for (auto &P : b->Ps)
+    for (uint32_t j = 0; j < P->pbeg.size(); ++j, ++row) {
+      NodeJob J{};
+      J.out = reinterpret_cast<NodeOut *>(b->d_out) + row;
+      J.recs0 = reinterpret_cast<const PathRec *>(P->d_recs) + P->rec_off[j];
+      J.count0 = P->pcnt[j];
+      jobs.push_back(J);
+    }
+  if (!jobs.empty() &&
+      hipMemcpy(b->d_jobs, jobs.data(), jobs.size() * sizeof(NodeJob), hipMemcpyHostToDevice) != hipSuccess)
+    return bail(fail(SDD_E_DEVICE, "batch job upload failed"));
+  if (hipHostMalloc(reinterpret_cast<void **>(&b->h_out), std::max<uint64_t>(b->total_nodes, 1) * sizeof(NodeOut),
+                    hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void **>(&b->h_done), std::max<size_t>(n, 1) * sizeof(unsigned long long),
+                    hipHostMallocDefault) != hipSuccess)
+    return bail(fail(SDD_E_DEVICE, "pinned host buffers"));
+  // capture: counter reset (a kernel, not a memset), walks, reduction, copies
+  if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess)
+    return bail(fail(SDD_E_DEVICE, "capture stream"));
+  hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed);
+  for (auto &g : b->groups)
+    if (e == hipSuccess)
+      e = launch_reset(reinterpret_cast<uint32_t *>(g.d_ctr), reinterpret_cast<unsigned long long *>(g.d_done),
+                       (uint32_t)g.P.size(), b->cap);
+  if (e == hipSuccess) e = hipEventRecord(ctx->ev[0], b->cap);
+  for (auto &g : b->groups)
+    if (e == hipSuccess)
+      e = launch_walk_persist(g.prec, reinterpret_cast<const DevReq *>(g.d_reqs), (uint32_t)g.P.size(),
+                              reinterpret_cast<const uint32_t *>(g.d_ws), 0u, refill_mask(ctx), g.blocks, g.threads,
+                              b->cap);
+  if (e == hipSuccess) e = hipEventRecord(ctx->ev[1], b->cap);
+  if (e == hipSuccess) e = launch_reduce(reinterpret_cast<const NodeJob *>(b->d_jobs), (uint32_t)b->total_nodes, b->cap);
+  if (e == hipSuccess && b->total_nodes)
+    e = hipMemcpyAsync(b->h_out, b->d_out, b->total_nodes * sizeof(NodeOut), hipMemcpyDeviceToHost, b->cap);
+  if (e == hipSuccess && n)
+    e = hipMemcpyAsync(b->h_done, b->d_done_all, n * sizeof(unsigned long long), hipMemcpyDeviceToHost, b->cap);
+  hipGraph_t graph = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(b->cap, &graph);
+  b->graph = graph;
+  if (e == hipSuccess) e = e2;
+  if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return bail(fail(SDD_E_DEVICE, "graph capture: %s", hipGetErrorString(e)));
+  *out = b;
+  for (uint32_t i = 0; i < n; ++i) b->Ps[i]->slot = done_index[i];
+  return SDD_OK;
+}
+
+sdd_status sdd_batch_run(sdd_batch_t b, sdd_result *res) {
+  if (!b) return fail(SDD_E_INVALID, "batch is NULL");
+  const uint32_t n = (uint32_t)b->Ps.size();
+  if (n && !res) return fail(SDD_E_INVALID, "results are NULL");
+  sdd_ctx *ctx = b->ctx;
+  ExecGuard ex(ctx);
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipGraphLaunch(b->exec, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]) == hipSuccess) ctx->stats.last_walk_ms = ms;
+  ctx->stats.launches += b->groups.size();
+  uint64_t row = 0, steps = 0, paths = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    const Prepared &P = *b->Ps[i];
+    if (b->h_done[P.slot] != P.n_paths)
+      return fail(SDD_E_DEVICE, "request %u: %llu of %llu paths completed", i, b->h_done[P.slot],
+                  (unsigned long long)P.n_paths);
+    scatter(P, b->h_out + row, &res[i]);
+    for (uint32_t j = 0; j < P.pbeg.size(); ++j) steps += b->h_out[row + j].steps;
+    row += P.pbeg.size();
+    paths += P.n_paths;
+    sdd_status st = copy_records(ctx, P, &res[i]);
+    if (st != SDD_OK) return st;
+  }
+  ctx->stats.last_walk_steps = steps;
+  ctx->stats.last_walk_paths = paths;
+  return SDD_OK;
+}
+
+sdd_status sdd_batch_destroy(sdd_batch_t b) {
+  if (!b) return fail(SDD_E_INVALID, "batch is NULL");
+  sdd_ctx *ctx = b->ctx;
+  ExecGuard ex(ctx);
+  batch_free(b);
   return SDD_OK;
 }
 

@@ -66,7 +66,11 @@ class sdd_result(C.Structure):
 
 class sdd_tuning(C.Structure):
     _fields_ = [("block_threads", C.c_uint32), ("blocks_per_cu", C.c_uint32), ("tile_paths", C.c_uint32),
-                ("slice_iters", C.c_uint32)]
+                ("slice_iters", C.c_uint32), ("refill_every", C.c_uint32)]
+
+
+class sdd_tune_trial(C.Structure):
+    _fields_ = [("tuning", sdd_tuning), ("walk_ms", C.c_double), ("walk_steps_per_s", C.c_double)]
 
 
 class sdd_stats(C.Structure):
@@ -90,8 +94,13 @@ _PROTOS = [
     ("sdd_cancel", C.c_int, [C.c_void_p, C.c_uint64]),
     ("sdd_set_tuning", C.c_int, [C.c_void_p, C.POINTER(sdd_tuning)]),
     ("sdd_get_tuning", C.c_int, [C.c_void_p, C.POINTER(sdd_tuning)]),
+    ("sdd_autotune", C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.POINTER(sdd_tuning),
+                               C.POINTER(sdd_tune_trial), C.c_uint32, C.POINTER(C.c_uint32)]),
     ("sdd_get_stats", C.c_int, [C.c_void_p, C.POINTER(sdd_stats)]),
     ("sdd_request_footprint", C.c_int, [C.c_void_p, C.POINTER(sdd_request), C.POINTER(C.c_uint64)]),
+    ("sdd_batch_create", C.c_int, [C.c_void_p, C.c_uint32, C.POINTER(sdd_request), C.POINTER(C.c_void_p)]),
+    ("sdd_batch_run", C.c_int, [C.c_void_p, C.POINTER(sdd_result)]),
+    ("sdd_batch_destroy", C.c_int, [C.c_void_p]),
     ("sdd_status_string", C.c_char_p, [C.c_int]),
     ("sdd_last_error", C.c_char_p, []),
 ]
@@ -236,8 +245,21 @@ class Context:
             _check(lib().sdd_model_destroy(self.h, self._models.pop(key)))
 
     # tuning -----------------------------------------------------------------
-    def set_tuning(self, block_threads=0, blocks_per_cu=0, tile_paths=0, slice_iters=0):
-        t = sdd_tuning(block_threads, blocks_per_cu, tile_paths, slice_iters)
+    def autotune(self, p, sample_paths: int = 0, precision: Optional[int] = None):
+        """Time the walker on a sample of problem p under candidate tunings,
+        keep the fastest on this context; returns (chosen tuning dict, list of
+        trial dicts)."""
+        q = _Req(p, self.model(p), precision)
+        chosen = sdd_tuning()
+        trials = (sdd_tune_trial * 32)()
+        n = C.c_uint32()
+        _check(lib().sdd_autotune(self.h, C.byref(q.s), sample_paths, C.byref(chosen), trials, 32, C.byref(n)))
+        tdict = lambda t: {f: getattr(t, f) for f, _ in sdd_tuning._fields_}  # noqa: E731
+        return tdict(chosen), [dict(tdict(trials[i].tuning), walk_ms=trials[i].walk_ms,
+                                    walk_steps_per_s=trials[i].walk_steps_per_s) for i in range(n.value)]
+
+    def set_tuning(self, block_threads=0, blocks_per_cu=0, tile_paths=0, slice_iters=0, refill_every=0):
+        t = sdd_tuning(block_threads, blocks_per_cu, tile_paths, slice_iters, refill_every)
         _check(lib().sdd_set_tuning(self.h, C.byref(t)))
 
     def stats(self) -> dict:
@@ -277,6 +299,10 @@ class Context:
         _check(lib().sdd_solve_batch(self.h, len(qs), reqs, ress))
         return [r.as_dict() for r in rs]
 
+    def batch(self, ps: Sequence, records: bool = False) -> "Batch":
+        """A prepared batch replayed as a HIP graph (see Batch)."""
+        return Batch(self, ps, records)
+
     # served mode --------------------------------------------------------------
     def submit(self, p, precision: Optional[int] = None, records: bool = False, target_rel_se: float = 0.0):
         q = _Req(p, self.model(p), precision, target_rel_se)
@@ -311,3 +337,34 @@ class Context:
     def cancel(self, ticket: int) -> int:
         """SDD_OK if cancelled, SDD_E_BUSY if it had already finished."""
         return lib().sdd_cancel(self.h, ticket)
+
+
+class Batch:
+    """Requests kept resident with their launch sequence captured as a HIP
+    graph; run() replays it and returns one result dict per request."""
+
+    def __init__(self, ctx: Context, ps: Sequence, records: bool = False):
+        self.ctx = ctx
+        self.qs = [_Req(p, ctx.model(p)) for p in ps]
+        self.records = records
+        reqs = (sdd_request * max(1, len(self.qs)))(*[q.s for q in self.qs])
+        h = C.c_void_p()
+        _check(lib().sdd_batch_create(ctx.h, len(self.qs), reqs, C.byref(h)))
+        self.h = h
+
+    def run(self) -> List[dict]:
+        rs = [_Res(q.n, q.total if self.records else 0) for q in self.qs]
+        ress = (sdd_result * max(1, len(rs)))(*[r.s for r in rs])
+        _check(lib().sdd_batch_run(self.h, ress))
+        return [r.as_dict() for r in rs]
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sdd_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -182,14 +182,15 @@ def test_launch_shape_does_not_change_a_bit(ctx):
     p = W.unit_square(paths=1500, precision=W.FP32_MIXED, seed=4)
     ref = ctx.solve(p, records=True)
     try:
-        for bt, bpc, tile in [(64, 1, 1), (128, 2, 64), (192, 1, 4096), (256, 3, 100)]:
-            ctx.set_tuning(block_threads=bt, blocks_per_cu=bpc, tile_paths=tile)
+        for bt, bpc, tile, rf in [(64, 1, 1, 1), (128, 2, 64, 2), (192, 1, 4096, 8), (256, 3, 100, 64)]:
+            ctx.set_tuning(block_threads=bt, blocks_per_cu=bpc, tile_paths=tile, refill_every=rf)
             got = ctx.solve(p, records=True)
-            assert got["records"].tobytes() == ref["records"].tobytes(), (bt, bpc, tile)
+            assert got["records"].tobytes() == ref["records"].tobytes(), (bt, bpc, tile, rf)
             assert np.array_equal(got["mean"], ref["mean"])
-        with pytest.raises(sdd.SddError) as e:
-            ctx.set_tuning(block_threads=512)
-        assert e.value.status == sdd.SDD_E_INVALID
+        for bad in ({"block_threads": 512}, {"refill_every": 3}, {"refill_every": 128}):
+            with pytest.raises(sdd.SddError) as e:
+                ctx.set_tuning(**bad)
+            assert e.value.status == sdd.SDD_E_INVALID
     finally:
         ctx.set_tuning()
 
@@ -293,3 +294,82 @@ def test_served_results_equal_blocking(ctx):
     with pytest.raises(sdd.SddError) as e:
         ctx.poll(987654321)
     assert e.value.status == sdd.SDD_E_NOTFOUND
+
+
+def test_served_time_slices_are_exact(ctx):
+    """Tiny slices: walkers are suspended and resumed thousands of times;
+    every result is still bitwise the blocking one (alone vs in the mix)."""
+    ps = [small_mixed_model().with_paths(150), W.unit_square(paths=400, precision=W.FP32_MIXED, seed=3),
+          W.quarter_space(paths=24, precision=W.FP32_MIXED, M=1024).subset(np.arange(0, 512, 40)),
+          W.block_in_half_space(10.0, paths=20, precision=W.FP64, M=1024).subset(np.arange(0, 1024, 90)),
+          W.unit_square(paths=1, precision=W.FP32_MIXED, n_nodes=3, dt=4e-4)]
+    try:
+        ctx.set_tuning(slice_iters=8, tile_paths=37)
+        tickets = [ctx.submit(p, records=True) for p in ps[:4]]
+        tickets.append(ctx.submit(ps[4], target_rel_se=2e-2))
+        got = [ctx.wait(t, timeout_s=100) for t in tickets]
+    finally:
+        ctx.set_tuning()
+    for p, r in zip(ps[:4], got[:4]):
+        alone = ctx.solve(p, records=True)
+        assert r["records"].tobytes() == alone["records"].tobytes()
+        assert np.array_equal(r["mean"], alone["mean"]) and np.array_equal(r["se"], alone["se"])
+    alone = ctx.solve(ps[4], target_rel_se=2e-2)
+    assert np.array_equal(got[4]["mean"], alone["mean"]) and np.array_equal(got[4]["paths_done"], alone["paths_done"])
+
+
+def test_served_requests_join_while_others_run(ctx):
+    """Continuous batching: a small request submitted while a long one is on
+    the GPU finishes first, and its result equals the blocking one."""
+    big = W.quarter_space(paths=4096, precision=W.FP32_MIXED, M=2048)
+    small = W.unit_square(paths=256, precision=W.FP32_MIXED, seed=21)
+    t_big = ctx.submit(big)
+    time.sleep(0.05)
+    t_small = ctx.submit(small, records=True)
+    r_small = ctx.wait(t_small, timeout_s=100)
+    big_done_early = ctx.poll(t_big)
+    r_big = big_done_early if big_done_early is not None else ctx.wait(t_big, timeout_s=100)
+    assert big_done_early is None, "the long request should still be running"
+    assert r_small["records"].tobytes() == ctx.solve(small, records=True)["records"].tobytes()
+    assert r_big["paths_done"].sum() == big.total_paths
+
+
+def test_batch_graph_replays_bitwise(ctx):
+    """A prepared batch replayed as a HIP graph several times, with eager
+    work and synchronisations in between: every replay equals the eager
+    batch solve bitwise."""
+    import torch
+    ps = [small_mixed_model().with_paths(90), W.unit_square(paths=300, precision=W.FP32_MIXED, seed=12),
+          W.quarter_space(paths=16, precision=W.FP32_MIXED, M=1024).subset(np.arange(0, 512, 50))]
+    eager = ctx.solve_batch(ps, records=True)
+    b = ctx.batch(ps, records=True)
+    try:
+        for rep in range(3):
+            got = b.run()
+            for e, g in zip(eager, got):
+                assert g["records"].tobytes() == e["records"].tobytes(), rep
+                assert np.array_equal(g["mean"], e["mean"]) and np.array_equal(g["var_re"], e["var_re"])
+            ctx.solve(W.unit_square(paths=64, seed=rep))   # eager work between replays
+            torch.cuda.synchronize()
+    finally:
+        b.close()
+
+
+def test_autotune_changes_speed_not_results(ctx):
+    """The autotuner's trials cover its candidate sweep, it leaves the chosen
+    tuning on the context, and solves under that tuning are bitwise the
+    solves under the default."""
+    p = W.quarter_space(paths=64, precision=W.FP32_MIXED, M=1024).subset(np.arange(0, 512, 8))
+    ref = ctx.solve(p, records=True)
+    try:
+        chosen, trials = ctx.autotune(p, sample_paths=64)
+        assert len(trials) >= 8
+        assert all(t["walk_ms"] > 0 and t["walk_steps_per_s"] > 0 for t in trials)
+        assert ctx.get_tuning() == chosen
+        assert chosen["block_threads"] in (64, 128, 256) and chosen["refill_every"] in (1, 2, 4, 8)
+        fastest = min(t["walk_ms"] for t in trials[1:])
+        assert any(t["walk_ms"] == fastest and all(t[k] == chosen[k] for k in chosen) for t in trials[1:])
+        got = ctx.solve(p, records=True)
+        assert got["records"].tobytes() == ref["records"].tobytes()
+    finally:
+        ctx.set_tuning()
