@@ -241,6 +241,29 @@ sdd_status sdd_batch_create(sdd_ctx_t ctx, uint32_t n, const sdd_request *reqs, 
 sdd_status sdd_batch_run(sdd_batch_t batch, sdd_result *res);
 sdd_status sdd_batch_destroy(sdd_batch_t batch);
 
+/* Multi-frequency solve (one walk, many frequencies).  In the TE equation
+ * the walk itself does not depend on the frequency: only the phase rate
+ * alpha = omega mu0 sigma L^2 does, and the phase of a path is linear in it
+ * (Feynman-Kac weight exp(-i S), S = 1/2 int alpha ds: Sec. 2.2, and the
+ * estimator of Sec. 3.1).  So one walk at the request's frequency, recording
+ * each path's phase S and exit point, gives for every frequency f_k the
+ * weight g_k(exit point) exp(-i S f_k / f) of the same path: the per-node
+ * estimates at all frequencies come from the same paths (correlated across
+ * frequencies) and each equals, up to rounding, what sdd_solve returns for
+ * the request at f_k with the same seed and stream.
+ *   req        fixed-path request; its freq_hz (or alpha_direct when that is
+ *              > 0) must be > 0 and sets the walk's phase scale; its own
+ *              g_tables are validated but not used for any result.
+ *   freqs      n_freq frequencies in Hz (alpha values when the request gives
+ *              alpha directly), each finite and > 0.
+ *   g_tables   n_freq tables, each laid out as sdd_request.g_tables with the
+ *              request's g_samples.
+ *   res        n_freq results (per node as sdd_solve; path_records must be
+ *              NULL).
+ * Errors: SDD_E_INVALID for the above, SDD_E_NOMEM, SDD_E_DEVICE. */
+sdd_status sdd_solve_multi_freq(sdd_ctx_t ctx, const sdd_request *req, uint32_t n_freq, const double *freqs,
+                                const double *const *g_tables, sdd_result *res);
+
 /* Bytes of workspace a request needs (tables, nodes, tiles, records). */
 sdd_status sdd_request_footprint(sdd_ctx_t ctx, const sdd_request *req, uint64_t *bytes);
 

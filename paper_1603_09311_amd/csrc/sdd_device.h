@@ -79,6 +79,17 @@ struct NodeJob {
   uint64_t pad;
 };
 
+// One (node, frequency) result of a multi-frequency solve: the node's phase
+// records weighted with the frequency's boundary tables and phase scale.
+struct FanJob {
+  const PathRec *recs;
+  uint64_t count;
+  const double *g;     // 4 x (M + 1) x (re, im) at this frequency
+  double scale;        // frequency / the walk's frequency
+  NodeOut *out;
+  uint64_t pad;
+};
+
 // Per-request device descriptor.
 struct DevReq {
   // FP64 walk (absolute coordinates, the same arithmetic as a plain FP64 reference)
@@ -102,7 +113,11 @@ struct DevReq {
   //   kSigZBox: [z0, y0, y1, zb0, zb1]    + box
   //   kSigZTri: [z0, A0,B0,C0, A1,B1,C1, A2,B2,C2]  + triangle, edges A a + B b + C
   int32_t sig;
-  int32_t sig_pad[3];
+  // 1: finished paths record the phase and the exit point instead of the
+  // weight (w_re = S at this request's frequency, w_im = tangential exit
+  // coordinate), for weights at other frequencies computed afterwards
+  uint32_t fanout;
+  int32_t sig_pad[2];
   float sigp[12];
   // streams and limits
   uint32_t key0, key1;  // Philox key (seed low, high)

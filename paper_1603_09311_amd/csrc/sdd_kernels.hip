@@ -241,19 +241,20 @@ template <int SIG> struct Reg32 {
 };
 
 // The weight g(X_tau) exp(-i S) of a finished path, in FP64, from the exit
-// wall, the tangential coordinate t (absolute) and the phase S.
-__device__ __forceinline__ void weight(const DevReq &Q, int wall, double t, double S, double &wre, double &wim) {
+// wall, the tangential coordinate t (absolute) and the phase S; g is the
+// wall's table, linear between its M + 1 equispaced samples.
+__device__ __forceinline__ void weight_tab(const double *g, int M, double y_lo, double y_hi, double z_lo, double z_hi,
+                                           int wall, double t, double S, double &wre, double &wim) {
   const bool along_y = (wall == 0) || (wall == 2);
-  const double t0 = along_y ? Q.y_lo : Q.z_lo;
-  const double t1 = along_y ? Q.y_hi : Q.z_hi;
-  const int M = (int)Q.M;
+  const double t0 = along_y ? y_lo : z_lo;
+  const double t1 = along_y ? y_hi : z_hi;
   const double h = (t1 - t0) / (double)M;
   const double u = (t - t0) / h;
   int i = (int)floor(u);
   i = i < 0 ? 0 : i;
   i = i > M - 1 ? M - 1 : i;
   const double lam = u - (double)i;
-  const double *gw = Q.g + (size_t)wall * (size_t)(M + 1) * 2;
+  const double *gw = g + (size_t)wall * (size_t)(M + 1) * 2;
   const double2 ga = *reinterpret_cast<const double2 *>(gw + 2 * i);
   const double2 gb = *reinterpret_cast<const double2 *>(gw + 2 * i + 2);
   const double gre = (1.0 - lam) * ga.x + lam * gb.x;
@@ -261,6 +262,21 @@ __device__ __forceinline__ void weight(const DevReq &Q, int wall, double t, doub
   const double cs = cos(S), sn = sin(S);
   wre = gre * cs + gim * sn;
   wim = gim * cs - gre * sn;
+}
+
+__device__ __forceinline__ void weight(const DevReq &Q, int wall, double t, double S, double &wre, double &wim) {
+  weight_tab(Q.g, (int)Q.M, Q.y_lo, Q.y_hi, Q.z_lo, Q.z_hi, wall, t, S, wre, wim);
+}
+
+// Record of a finished path: its weight, or (multi-frequency requests) its
+// phase and tangential exit coordinate.
+__device__ __forceinline__ void finish_weight(const DevReq &Q, int wall, double t, double S, PathRec &r) {
+  if (Q.fanout) {
+    r.w_re = S;
+    r.w_im = t;
+  } else {
+    weight(Q, wall, t, S, r.w_re, r.w_im);
+  }
 }
 
 __device__ __forceinline__ PathRec unfinished_rec(uint32_t steps) {
@@ -389,7 +405,7 @@ __device__ __forceinline__ bool step64(const DevReq &Q, const U64<SIG> &U, W64 &
 __device__ __forceinline__ PathRec finish64(const DevReq &Q, const W64 &W, const ExitInfo<double> &X) {
   const double S = W.S + W.cc * X.f;
   PathRec r;
-  weight(Q, X.wall, X.t, S, r.w_re, r.w_im);
+  finish_weight(Q, X.wall, X.t, S, r);
   r.tau = ((double)W.n + X.f) * Q.dt;
   r.steps = W.n + 1u;
   r.wall = X.wall;
@@ -556,7 +572,7 @@ __device__ __forceinline__ PathRec finish32(const DevReq &Q, const W32 &W, const
   const double lo = along_y ? Q.y_lo : Q.z_lo, hi = along_y ? Q.y_hi : Q.z_hi;
   t = t < lo ? lo : (t > hi ? hi : t);
   PathRec r;
-  weight(Q, X.wall, t, S, r.w_re, r.w_im);
+  finish_weight(Q, X.wall, t, S, r);
   r.tau = ((double)W.n + (double)X.f) * Q.dt;
   r.steps = W.n + 1u;
   r.wall = X.wall;
@@ -903,19 +919,25 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double (*lds)[K]) {
   __syncthreads();
 }
 
-__global__ void __launch_bounds__(kRedThreads) reduce_nodes(const NodeJob *__restrict__ jobs) {
+// Statistics of one node from its records, two passes in a fixed order;
+// REC(i) gives path i's (valid, w_re, w_im, tau, steps).
+struct RecView {
+  bool done;
+  double w_re, w_im, tau;
+  uint32_t steps;
+};
+
+template <class REC>
+__device__ __forceinline__ void reduce_body(uint64_t count, const REC &rec, NodeOut *out) {
   __shared__ double lds[kRedThreads / 64][4];
   __shared__ unsigned long long ldsu[kRedThreads / 64][3];
-  const NodeJob J = jobs[blockIdx.x];
   const int tid = threadIdx.x;
-  const uint64_t count = J.count0 + J.count1;
-  auto rec = [&](uint64_t i) { return i < J.count0 ? J.recs0[i] : J.recs1[i - J.count0]; };
   double s[4] = {0.0, 0.0, 0.0, 0.0};  // sum re, sum im, sum tau, (unused)
   unsigned long long cnt[3] = {0ull, 0ull, 0ull};  // done, unfinished, steps
   for (uint64_t i = tid; i < count; i += kRedThreads) {
-    const PathRec r = rec(i);
+    const RecView r = rec(i);
     cnt[2] += r.steps;
-    if (r.wall < 0) { cnt[1] += 1ull; continue; }
+    if (!r.done) { cnt[1] += 1ull; continue; }
     cnt[0] += 1ull;
     s[0] += r.w_re;
     s[1] += r.w_im;
@@ -937,8 +959,8 @@ __global__ void __launch_bounds__(kRedThreads) reduce_nodes(const NodeJob *__res
   const double mre = s[0] / N, mim = s[1] / N;
   double q[4] = {0.0, 0.0, 0.0, 0.0};  // (re-m)^2, (im-m)^2, (re-m)(im-m)
   for (uint64_t i = tid; i < count; i += kRedThreads) {
-    const PathRec r = rec(i);
-    if (r.wall < 0) continue;
+    const RecView r = rec(i);
+    if (!r.done) continue;
     const double dr = r.w_re - mre, di = r.w_im - mim;
     q[0] += dr * dr;
     q[1] += di * di;
@@ -959,8 +981,31 @@ __global__ void __launch_bounds__(kRedThreads) reduce_nodes(const NodeJob *__res
     o.paths_done = cnt[0];
     o.unfinished = cnt[1];
     o.steps = cnt[2];
-    *J.out = o;
+    *out = o;
   }
+}
+
+__global__ void __launch_bounds__(kRedThreads) reduce_nodes(const NodeJob *__restrict__ jobs) {
+  const NodeJob J = jobs[blockIdx.x];
+  auto rec = [&](uint64_t i) {
+    const PathRec r = i < J.count0 ? J.recs0[i] : J.recs1[i - J.count0];
+    return RecView{r.wall >= 0, r.w_re, r.w_im, r.tau, r.steps};
+  };
+  reduce_body(J.count0 + J.count1, rec, J.out);
+}
+
+// Multi-frequency results: path i's weight at this job's frequency is
+// g_f(exit point) exp(-i scale S), from the phase record of the one walk.
+__global__ void __launch_bounds__(kRedThreads) reduce_fanout(const FanJob *__restrict__ jobs, int M, double y_lo,
+                                                              double y_hi, double z_lo, double z_hi) {
+  const FanJob J = jobs[blockIdx.x];
+  auto rec = [&](uint64_t i) {
+    const PathRec r = J.recs[i];
+    RecView v{r.wall >= 0, 0.0, 0.0, r.tau, r.steps};
+    if (v.done) weight_tab(J.g, M, y_lo, y_hi, z_lo, z_hi, r.wall, r.w_im, J.scale * r.w_re, v.w_re, v.w_im);
+    return v;
+  };
+  reduce_body(J.count, rec, J.out);
 }
 
 // Sets every request's claim counter and done counter to zero (a kernel, so
@@ -993,6 +1038,13 @@ hipError_t launch_walk_persist(int precision, const DevReq *reqs_dev, uint32_t n
   else
     hipLaunchKernelGGL(walk_persist_f32, dim3(blocks), dim3(threads), 0, st, reqs_dev, n_req, wave_start_dev, budget,
                        refill_mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_fanout(const FanJob *jobs_dev, uint32_t n_jobs, int M, double y_lo, double y_hi, double z_lo,
+                                double z_hi, hipStream_t st) {
+  if (n_jobs == 0) return hipSuccess;
+  hipLaunchKernelGGL(reduce_fanout, dim3(n_jobs), dim3(kRedThreads), 0, st, jobs_dev, M, y_lo, y_hi, z_lo, z_hi);
   return hipGetLastError();
 }
 

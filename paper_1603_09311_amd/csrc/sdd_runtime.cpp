@@ -32,6 +32,8 @@ hipError_t launch_walk_persist(int precision, const DevReq *reqs_dev, uint32_t n
                                const uint32_t *wave_start_dev, uint32_t budget, uint32_t refill_mask, uint32_t blocks,
                                uint32_t threads, hipStream_t st);
 hipError_t launch_reduce(const NodeJob *jobs_dev, uint32_t n_jobs, hipStream_t st);
+hipError_t launch_reduce_fanout(const FanJob *jobs_dev, uint32_t n_jobs, int M, double y_lo, double y_hi, double z_lo,
+                                double z_hi, hipStream_t st);
 hipError_t launch_reset(uint32_t *tile_counters, unsigned long long *done, uint32_t n, hipStream_t st);
 int persist_blocks_per_cu(int precision, uint32_t threads);
 }  // namespace sdd
@@ -1292,6 +1294,85 @@ sdd_status sdd_solve_batch(sdd_ctx_t ctx, uint32_t n, const sdd_request *reqs, s
     st = copy_records(ctx, *Ps[i], &res[i]);
   }
   for (auto *P : Ps) release_all(ctx, *P);
+  return st;
+}
+
+sdd_status sdd_solve_multi_freq(sdd_ctx_t ctx, const sdd_request *req, uint32_t n_freq, const double *freqs,
+                                const double *const *g_tables, sdd_result *res) {
+  if (!ctx || !req) return fail(SDD_E_INVALID, "NULL argument");
+  if (n_freq && (!freqs || !g_tables || !res)) return fail(SDD_E_INVALID, "NULL frequencies, tables or results");
+  if (req->target_rel_se > 0.0) return fail(SDD_E_INVALID, "multi-frequency solves take fixed-path requests");
+  const double ref = req->alpha_direct > 0.0 ? req->alpha_direct : req->freq_hz;
+  if (!(ref > 0.0) || !std::isfinite(ref))
+    return fail(SDD_E_INVALID, "multi-frequency solves need a positive request frequency (or alpha)");
+  for (uint32_t k = 0; k < n_freq; ++k) {
+    if (!(freqs[k] > 0.0) || !std::isfinite(freqs[k])) return fail(SDD_E_INVALID, "frequency %u is not positive", k);
+    if (!g_tables[k]) return fail(SDD_E_INVALID, "g_tables[%u] is NULL", k);
+    for (uint64_t i = 0; i < 8ull * req->g_samples; ++i)
+      if (!std::isfinite(g_tables[k][i])) return fail(SDD_E_INVALID, "g_tables[%u] holds a non-finite value", k);
+    if (!res[k].mean && req->n_nodes) return fail(SDD_E_INVALID, "result %u: mean is NULL", k);
+    if (res[k].path_records) return fail(SDD_E_INVALID, "result %u: no path records in multi-frequency solves", k);
+  }
+  std::unique_ptr<Prepared> P;
+  sdd_status st = prepare(ctx, req, P);
+  if (st != SDD_OK) return st;
+  P->dreq.fanout = 1u;
+  ExecGuard ex(ctx);
+  HIP_TRY(hipSetDevice(ctx->device));
+  st = upload_pass(ctx, *P);
+  std::vector<Prepared *> Ps{P.get()};
+  if (st == SDD_OK) st = run_persistent(ctx, Ps);
+  const uint32_t n = (uint32_t)P->pbeg.size();
+  const uint64_t n_jobs = (uint64_t)n * n_freq;
+  const size_t tab = (size_t)8 * req->g_samples;
+  char *d_g = nullptr, *d_jobs = nullptr, *d_out = nullptr;
+  std::vector<NodeOut> rows(n_jobs);
+  if (st == SDD_OK && n_jobs) {
+    d_g = ctx->alloc(n_freq * tab * sizeof(double));
+    d_jobs = ctx->alloc(n_jobs * sizeof(FanJob));
+    d_out = ctx->alloc(n_jobs * sizeof(NodeOut));
+    if (!d_g || !d_jobs || !d_out) st = fail(SDD_E_NOMEM, "no workspace left for the multi-frequency reduction");
+  }
+  if (st == SDD_OK && n_jobs) {
+    std::vector<FanJob> jobs(n_jobs);
+    for (uint32_t k = 0; k < n_freq; ++k)
+      for (uint32_t j = 0; j < n; ++j) {
+        FanJob &J = jobs[(uint64_t)k * n + j];
+        J.recs = reinterpret_cast<const PathRec *>(P->d_recs) + P->rec_off[j];
+        J.count = P->pcnt[j];
+        J.g = reinterpret_cast<const double *>(d_g) + k * tab;
+        J.scale = freqs[k] / ref;
+        J.out = reinterpret_cast<NodeOut *>(d_out) + (uint64_t)k * n + j;
+      }
+    hipError_t e = hipSuccess;
+    for (uint32_t k = 0; k < n_freq && e == hipSuccess; ++k)
+      e = hipMemcpyAsync(d_g + k * tab * sizeof(double), g_tables[k], tab * sizeof(double), hipMemcpyHostToDevice,
+                         ctx->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(d_jobs, jobs.data(), n_jobs * sizeof(FanJob), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipEventRecord(ctx->ev[2], ctx->stream);
+    if (e == hipSuccess)
+      e = launch_reduce_fanout(reinterpret_cast<const FanJob *>(d_jobs), (uint32_t)n_jobs, (int)P->dreq.M,
+                               P->dreq.y_lo, P->dreq.y_hi, P->dreq.z_lo, P->dreq.z_hi, ctx->stream);
+    if (e == hipSuccess) e = hipEventRecord(ctx->ev[3], ctx->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(rows.data(), d_out, n_jobs * sizeof(NodeOut), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) st = fail(SDD_E_DEVICE, "multi-frequency reduction: %s", hipGetErrorString(e));
+    float ms = 0.f;
+    if (st == SDD_OK && hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]) == hipSuccess) ctx->stats.last_reduce_ms = ms;
+    if (st == SDD_OK && n) {
+      uint64_t steps = 0;
+      for (uint32_t j = 0; j < n; ++j) steps += rows[j].steps;
+      ctx->stats.last_walk_steps = steps;
+    }
+  }
+  ctx->release(d_g);
+  ctx->release(d_jobs);
+  ctx->release(d_out);
+  if (st == SDD_OK)
+    for (uint32_t k = 0; k < n_freq; ++k) scatter(*P, rows.data() + (uint64_t)k * n, &res[k]);
+  release_all(ctx, *P);
   return st;
 }
 

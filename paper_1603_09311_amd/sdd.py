@@ -88,6 +88,8 @@ _PROTOS = [
     ("sdd_solve", C.c_int, [C.c_void_p, C.POINTER(sdd_request), C.POINTER(sdd_result)]),
     ("sdd_solve_batch", C.c_int, [C.c_void_p, C.c_uint32, C.POINTER(sdd_request), C.POINTER(sdd_result)]),
     ("sdd_solve_plain", C.c_int, [C.c_void_p, C.POINTER(sdd_request), C.POINTER(sdd_result)]),
+    ("sdd_solve_multi_freq", C.c_int, [C.c_void_p, C.POINTER(sdd_request), C.c_uint32, C.POINTER(C.c_double),
+                                       C.POINTER(C.POINTER(C.c_double)), C.POINTER(sdd_result)]),
     ("sdd_submit", C.c_int, [C.c_void_p, C.POINTER(sdd_request), C.POINTER(sdd_result), C.POINTER(C.c_uint64)]),
     ("sdd_poll", C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_int)]),
     ("sdd_wait", C.c_int, [C.c_void_p, C.c_uint64, C.c_int64]),
@@ -284,6 +286,27 @@ class Context:
         r = _Res(q.n, q.total if records else 0)
         _check(lib().sdd_solve(self.h, C.byref(q.s), C.byref(r.s)))
         return r.as_dict()
+
+    def solve_multi_freq(self, p, freqs: Sequence[float], g_tables: Sequence[np.ndarray],
+                         precision: Optional[int] = None) -> List[dict]:
+        """One walk of problem p (its own frequency sets the phase scale),
+        weighted for every frequency in freqs with that frequency's (4, M+1)
+        complex boundary tables; one result dict per frequency."""
+        if len(freqs) != len(g_tables):
+            raise ValueError("one table set per frequency")
+        q = _Req(p, self.model(p), precision)
+        fr = np.ascontiguousarray(freqs, dtype=np.float64)
+        tabs = []
+        for g in g_tables:
+            g = np.asarray(g)
+            if g.shape != p.g.shape:
+                raise ValueError(f"tables of shape {g.shape}, the request has {p.g.shape}")
+            tabs.append(np.ascontiguousarray(np.stack([g.real, g.imag], axis=-1).reshape(-1), dtype=np.float64))
+        ptrs = (C.POINTER(C.c_double) * max(1, len(tabs)))(*[_ptr(t, C.c_double) for t in tabs])
+        rs = [_Res(q.n) for _ in tabs]
+        ress = (sdd_result * max(1, len(rs)))(*[r.s for r in rs])
+        _check(lib().sdd_solve_multi_freq(self.h, C.byref(q.s), len(tabs), _ptr(fr, C.c_double), ptrs, ress))
+        return [r.as_dict() for r in rs]
 
     def solve_plain(self, p, records: bool = False):
         q = _Req(p, self.model(p), SDD_FP64)

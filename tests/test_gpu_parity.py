@@ -373,3 +373,42 @@ def test_autotune_changes_speed_not_results(ctx):
         assert got["records"].tobytes() == ref["records"].tobytes()
     finally:
         ctx.set_tuning()
+
+
+def test_multi_frequency_one_walk(ctx, orc):
+    """One walk weighted for four frequencies: each frequency's result
+    matches the oracle solved at that frequency with the same streams (FP64
+    bar); at the walk's own frequency it is bitwise the ordinary solve."""
+    freqs = [0.1, 1.0, 10.0, 100.0]
+    sel = [0, 130, 260, 400, 600, 1000]
+    probs = [W.block_in_half_space(f, paths=48, precision=W.FP64, M=1024).subset(sel) for f in freqs]
+    base = probs[1]
+    got = ctx.solve_multi_freq(base, freqs, [q.g for q in probs])
+    assert len(got) == 4
+    for f, q, g in zip(freqs, probs, got):
+        o, orec = oracle_solve(orc, q, records=True)
+        log(f"multi-frequency fp64 f={f}")
+        # The oracle sums the phase at frequency f; the one walk sums it at the
+        # walk's frequency and scales.  The two sums of n terms differ by at
+        # most n 2^-52 |S| (relative rounding per term), which moves a weight
+        # by at most |g|max times that: per node, the mean of this bound.
+        gmax = np.abs(q.g).max()
+        bound = ((orec["steps"].astype(float) + 2) * 2.0 ** -52 * np.abs(orec["S"]) * gmax)
+        bound = bound.reshape(q.n_nodes, -1).mean(axis=1)
+        e_o = o["mean_re"] + 1j * o["mean_im"]
+        d = np.abs(g["mean"] - e_o)
+        assert np.all(d <= TOL_FP64 * np.fmax(np.abs(e_o), o["se"]) + bound), (f, d, bound)
+        assert np.array_equal(g["steps"], o["steps"]) and np.array_equal(g["paths_done"], o["paths_done"])
+        assert np.allclose(g["mean_exit_time"], o["mean_exit_time"], rtol=1e-12)
+        assert np.allclose(g["se"], o["se"], rtol=1e-6)
+    alone = ctx.solve(base)
+    assert np.array_equal(got[1]["mean"], alone["mean"]) and np.array_equal(got[1]["se"], alone["se"])
+    # FP32-mixed walk: within SE of the oracle at every frequency
+    probs32 = [W.block_in_half_space(f, paths=2048, precision=W.FP32_MIXED, M=1024).subset(sel[:4])
+               for f in freqs[:3]]
+    got32 = ctx.solve_multi_freq(probs32[1], freqs[:3], [q.g for q in probs32])
+    for q, g in zip(probs32, got32):
+        o, _ = oracle_solve(orc, q)
+        assert_within_se(g, o)
+    with pytest.raises(sdd.SddError):
+        ctx.solve_multi_freq(base, [1.0, -2.0], [probs[0].g, probs[1].g])

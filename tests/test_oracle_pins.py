@@ -350,3 +350,22 @@ def test_path_ranges_are_stream_slices(orc):
     q = p.replace(path_begin=np.array([17], np.uint32), path_count=np.array([11], np.uint32))
     _, part = orc.solve(q, records=True)
     assert np.array_equal(part, all_[17:28])
+
+
+def test_walk_is_frequency_free_and_phase_linear(orc):
+    """TE walks are standard Brownian motion whatever the frequency: the same
+    (seed, stream, node, path) gives the same steps, exit wall, exit point and
+    exit time at every frequency, and the phase S = 1/2 int alpha ds scales
+    with the frequency (alpha = omega mu0 sigma L^2).  This is what lets one
+    walk serve every frequency."""
+    for node in (0, 200, 700):
+        a = W.block_in_half_space(1.0, paths=4, precision=W.FP64, M=256).subset([node])
+        b = W.block_in_half_space(37.0, paths=4, precision=W.FP64, M=256).subset([node])
+        for path in range(4):
+            ra, rb = orc.walk_path(a, 0, path), orc.walk_path(b, 0, path)
+            for k in ("steps", "wall", "tau", "exit_t"):
+                assert ra[k] == rb[k], k
+            assert ra["S"] > 0.0
+            # the two sums of ra["steps"] terms differ only by rounding
+            tol = (ra["steps"] + 2) * 2.0 ** -52
+            assert rb["S"] == pytest.approx(37.0 * ra["S"], rel=tol)
