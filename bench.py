@@ -39,17 +39,17 @@ VALU_PEAK = CUS * SIMDS * LANES * CLOCK
 # model: every operation the method needs, each in its cheapest gfx950
 # instruction form, one lane-operation slot per instruction (the counters show
 # the walker retiring about one VALU instruction per 4 cycles per SIMD,
-# transcendentals and 32x32->64 products included):
-#   Philox4x32-10, one call per two steps: rounds 3-10 (2 products + 2 3-input
-#     xors each) 32, round 2: 3, round 1: 1, step-pair counter product 2 -> 38/2 = 19
-#   two uniforms (shift, convert, fma)                                     =  6
-#   Box-Muller (log2, mul, sqrt, sin, cos, 2 mul)                          =  7
-#   Euler-Maruyama position update (2 fma)                                 =  2
-#   exit screen, both axes (2 sub |.|, 2 mul, min, compare)                =  6
-#   region lookup, 2 half-planes (2 compares, 2 selects)                   =  4
-#   compensated phase add (TwoSum)                                         =  6
-#   step counter                                                           =  1
-OPS_PER_STEP = 19 + 6 + 7 + 2 + 6 + 4 + 6 + 1   # = 51
+# transcendentals and 32x32->64 products included).  Per Philox call (two
+# steps): rounds 3-10, 2 products + 2 three-input xors each = 32; round 2,
+# 1 product + 2 xors = 3; round 1, 1 xor = 1; counter product update = 1.
+#   Philox4x32-10, half a call                                 37/2 = 18.5
+#   uniforms: radius (align + exact subtract), angle (align)         =  3
+#   Box-Muller + proposal (log2, sqrt, mul, cos, sin, 2 fma)         =  7
+#   exit screen, both axes (2 sub |.|, 2 mul, min, compare)          =  6
+#   region lookup, 2 half-planes (2 compares, 2 selects)             =  4
+#   compensated phase add (Fast2Sum + low-part accumulate)           =  4
+#   step counter and cap (one add and one compare per two steps)     =  1
+OPS_PER_STEP = 18.5 + 3 + 7 + 6 + 4 + 4 + 1   # = 43.5
 
 
 def kernel_source_hash() -> str:

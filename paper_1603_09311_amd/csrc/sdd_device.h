@@ -102,9 +102,10 @@ struct DevReq {
   // FP32-mixed walk: coordinates relative to (ymid, zmid), walls at +-h
   float fhy, fhz;      // half-widths
   float fs, fdt;       // sqrt(dt), dt
-  float fthr;          // 22.9 dt, compared with 2 d0 d1
+  float fthr;          // 16.7 dt, compared with 2 d0 d1 (FP32 uniforms are >= 2^-24)
   float fscr;          // fthr / 2, compared with d0 d1' in the per-step screen
-  float fpad[2];
+  float fK;            // sqrt(dt) sqrt(2 ln 2): step length per sqrt(-log2 u)
+  float fpad;
   float fc[kMaxRegions + 3];
   // model signature (which specialised region lookup the walkers use) and its
   // FP32 parameters in centred coordinates:

@@ -198,42 +198,65 @@ template <int SIG> struct Reg64 {
   }
 };
 
+// A wave-uniform value copied into a VGPR once: a per-lane select between it
+// and a scalar operand is then one v_cndmask (two scalar operands would need
+// a move or a branch per select).
+__device__ __forceinline__ float in_vgpr(float x) {
+  float r;
+  asm("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
+  return r;
+}
+
 // FP32 lookup in centred coordinates; the triangle as three linear forms.
+// The phase rates of the regions live in VGPRs (loop-invariant copies), so
+// every select is a single v_cndmask on two VGPRs.
 template <int SIG> struct Reg32 {
   float cb, c0, c1;
   float p[10];
   __device__ __forceinline__ void load(const DevReq &Q) {
     const int np = (int)Q.nprims;
-    cb = unif(Q.fc[np]);
+    cb = in_vgpr(unif(Q.fc[np]));
     if constexpr (SIG != kSigNone && SIG != kSigGeneric) {
-      c0 = unif(Q.fc[0]);
+      c0 = in_vgpr(unif(Q.fc[0]));
       p[0] = unif(Q.sigp[0]);
     }
     if constexpr (SIG == kSigZY || SIG == kSigZBox || SIG == kSigZTri) {
-      c1 = unif(Q.fc[1]);
+      c1 = in_vgpr(unif(Q.fc[1]));
 #pragma unroll
       for (int i = 1; i < 10; ++i) p[i] = unif(Q.sigp[i]);
     }
   }
+  // The scalar operands are read (readfirstlane, which is convergent) before
+  // the selects, so that each select stays a select (v_cndmask) rather than
+  // a branch around a convergent call.
   __device__ __forceinline__ float eval(const DevReq &Q, float a, float b) const {
+    const float vb = cb;
     if constexpr (SIG == kSigNone) {
-      return unif(cb);
+      return vb;
     } else if constexpr (SIG == kSigZ) {
-      return b < unif(p[0]) ? unif(c0) : unif(cb);
+      const float z0 = unif(p[0]), va = c0;
+      return b < z0 ? va : vb;
     } else if constexpr (SIG == kSigZY) {
-      const float c = a < unif(p[1]) ? unif(c1) : unif(cb);
-      return b < unif(p[0]) ? unif(c0) : c;
+      const float z0 = unif(p[0]), y1 = unif(p[1]), va = c0, vl = c1;
+      const float c = a < y1 ? vl : vb;
+      return b < z0 ? va : c;
     } else if constexpr (SIG == kSigZBox) {
-      const bool in = (a >= unif(p[1])) & (a < unif(p[2])) & (b >= unif(p[3])) & (b < unif(p[4]));
-      const float c = in ? unif(c1) : unif(cb);
-      return b < unif(p[0]) ? unif(c0) : c;
+      const float z0 = unif(p[0]), y0 = unif(p[1]), y1 = unif(p[2]), zb0 = unif(p[3]), zb1 = unif(p[4]);
+      const float va = c0, vx = c1;
+      const bool in = (a >= y0) & (a < y1) & (b >= zb0) & (b < zb1);
+      const float c = in ? vx : vb;
+      return b < z0 ? va : c;
     } else if constexpr (SIG == kSigZTri) {
-      const float e0 = __builtin_fmaf(unif(p[1]), a, __builtin_fmaf(unif(p[2]), b, unif(p[3])));
-      const float e1 = __builtin_fmaf(unif(p[4]), a, __builtin_fmaf(unif(p[5]), b, unif(p[6])));
-      const float e2 = __builtin_fmaf(unif(p[7]), a, __builtin_fmaf(unif(p[8]), b, unif(p[9])));
+      float q[10];
+#pragma unroll
+      for (int i = 0; i < 10; ++i) q[i] = unif(p[i]);
+      const float va = c0, vx = c1;
+      const float e0 = __builtin_fmaf(q[1], a, __builtin_fmaf(q[2], b, q[3]));
+      const float e1 = __builtin_fmaf(q[4], a, __builtin_fmaf(q[5], b, q[6]));
+      const float e2 = __builtin_fmaf(q[7], a, __builtin_fmaf(q[8], b, q[9]));
       const bool in = (fminf(fminf(e0, e1), e2) >= 0.f) | (fmaxf(fmaxf(e0, e1), e2) <= 0.f);
-      const float c = in ? unif(c1) : unif(cb);
-      return b < unif(p[0]) ? unif(c0) : c;
+      const float c = in ? vx : vb;
+      return b < q[0] ? va : c;
     } else {
       return region_c_generic<float, 8>((int)Q.nprims, Q.kind, &Q.pf[0][0], Q.fc, a, b);
     }
@@ -432,10 +455,15 @@ __device__ __forceinline__ int iterate64(const DevReq &Q, const U64<SIG> &U, W64
 // FP32-mixed walk: coordinates (a, b) relative to the domain centre, walls
 // at +-h.  The distance of the current point to its nearer wall, d0 = h - |a|,
 // is carried from step to step.  A proposal can only reach a wall, or need a
-// bridge uniform, if d0 d1 <= 11.45 dt on some axis, where d1 is the distance
+// bridge uniform, if 2 d0 d1 <= 16.7 dt on some axis, where d1 is the distance
 // of the proposal to the wall nearer to the current point; d1' = h - |a'|
 // (distance to the wall nearer to the proposal) satisfies d1' <= d1, so the
-// screen min(d0y d1y', d0z d1z') <= 11.45 dt never misses one.
+// screen min(d0y d1y', d0z d1z') <= 8.35 dt never misses one.
+//
+// One iteration is two steps (one Philox call).  Both steps update the walker
+// unconditionally; an exit in the first step is recorded in the exit info,
+// which the second step leaves alone, and the walker state after an exit is
+// discarded.  This keeps every state update in place (no per-lane merges).
 // ===========================================================================
 struct W32 {
   float a, b;       // y - ymid, z - zmid
@@ -448,32 +476,47 @@ struct W32 {
   PhiloxPath pp;
 };
 
+// Exit of an FP32 walker: everything its record needs.
+struct X32 {
+  float f, t;       // fraction of the last step; tangential coordinate (centred)
+  float sh, sl;     // phase at the exit point: sh + sl
+  uint32_t n;       // index of the exit step
+  int wall;         // 0 top, 1 right, 2 bottom, 3 left
+};
+
 template <int SIG> struct U32 {
-  float hy, hz, s, dt, thr, scr;
-  uint32_t k0, k1, ctr3, max_steps;
+  float hy, hz, K, dt, thr, scr;
+  uint32_t k0, k1, ctr3, max_steps, cap1, cap2;
   Reg32<SIG> reg;
   __device__ __forceinline__ void load(const DevReq &Q) {
-    hy = Q.fhy; hz = Q.fhz; s = Q.fs; dt = Q.fdt; thr = Q.fthr; scr = Q.fscr;
+    hy = Q.fhy; hz = Q.fhz; K = Q.fK; dt = Q.fdt; thr = Q.fthr; scr = Q.fscr;
     k0 = Q.key0; k1 = Q.key1; ctr3 = Q.ctr3; max_steps = Q.max_steps;
+    cap1 = max_steps - 1u;                          // n >= cap1: step n is the last allowed
+    cap2 = max_steps >= 2u ? max_steps - 2u : 0u;   // n >= cap2: step n + 1 is
     reg.load(Q);
   }
 };
 
-// ((w >> 8) + 1/2) 2^-24: exact in FP32, never 0 or 1.
-__device__ __forceinline__ float u01_32(uint32_t w) { return __builtin_fmaf((float)(w >> 8), 0x1p-24f, 0x1p-25f); }
-
-// Box-Muller with the hardware transcendentals: v_log_f32 (log2), v_sqrt_f32,
-// and v_sin/v_cos_f32, whose argument is in revolutions (no 2 pi multiply).
-__device__ __forceinline__ void normals32(uint32_t a, uint32_t b, float &n0, float &n1) {
-  const float m2ln2 = -1.3862943611198906f;  // -2 ln 2
-  const float r = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u01_32(a)));
-  const float ub = u01_32(b);
-  n0 = r * __builtin_amdgcn_cosf(ub);
-  n1 = r * __builtin_amdgcn_sinf(ub);
+// 1 + (w >> 9) 2^-23 in [1, 2): the word's top 23 bits under the exponent of 1.
+__device__ __forceinline__ float one_frac32(uint32_t w) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_alignbit(0x7Fu, w, 9u));
 }
+// (2 (w >> 9) + 1) 2^-24: exact in FP32 (the subtraction is exact), in (0, 1).
+__device__ __forceinline__ float u01_32(uint32_t w) { return one_frac32(w) - 0x1.fffffep-1f; }
 
 __device__ __forceinline__ float neglog32(uint32_t w) {
   return -0.69314718055994531f * __builtin_amdgcn_logf(u01_32(w));
+}
+
+// Box-Muller and the Euler-Maruyama proposal in one: with the hardware log2,
+// sqrt(-2 ln u) sqrt(dt) = K sqrt(-log2 u), K = sqrt(dt) sqrt(2 ln 2); the
+// angle is in revolutions (v_sin/v_cos_f32), and 1 + k 2^-23 is the same
+// angle as k 2^-23.
+__device__ __forceinline__ void propose32(float K, float a, float b, uint32_t wa, uint32_t wb, float &an, float &bn) {
+  const float rk = K * __builtin_amdgcn_sqrtf(-__builtin_amdgcn_logf(u01_32(wa)));
+  const float ang = one_frac32(wb);
+  an = __builtin_fmaf(__builtin_amdgcn_cosf(ang), rk, a);
+  bn = __builtin_fmaf(__builtin_amdgcn_sinf(ang), rk, b);
 }
 
 template <int SIG>
@@ -495,9 +538,10 @@ __device__ __forceinline__ void start32(const DevReq &Q, const U32<SIG> &U, W32 
   W.cc = U.reg.eval(Q, W.a, W.b);
 }
 
-// Exact exit logic for a lane the screen flagged.
+// Exact exit logic for a lane the screen flagged (step index nstep).
 template <int SIG>
-__device__ __forceinline__ bool exit32(const U32<SIG> &U, const W32 &W, float an, float bn, ExitInfo<float> &X) {
+__device__ __forceinline__ bool exit32(const U32<SIG> &U, const W32 &W, float an, float bn, uint32_t nstep,
+                                       X32 &X) {
   const bool upy = W.a > 0.f;   // a tie (a = 0) goes to the lower wall
   const bool upz = W.b > 0.f;
   const float d0y = W.d0y, d0z = W.d0z;
@@ -510,88 +554,89 @@ __device__ __forceinline__ bool exit32(const U32<SIG> &U, const W32 &W, float an
   const bool ny = !cy && (qy <= U.thr);
   const bool nz = !cz && (qz <= U.thr);
   if (ny || nz) {
-    const uint64_t Pn = (W.P << 1) + ((W.n & 1u) ? (uint64_t)kM0 : 0ull);
+    const uint64_t Pn = (W.P << 1) + ((nstep & 1u) ? (uint64_t)kM0 : 0ull);
     const uint4 u = philox_pp(Pn, U.ctr3 + 1u, W.pp, U.k0, U.k1);
     if (ny) {
-      const float L = neglog32(u.x);
-      if (qy <= U.dt * L) { hy = true; fy = qy / (U.dt * L); }
+      const float L = U.dt * neglog32(u.x);
+      if (qy <= L) { hy = true; fy = qy * __builtin_amdgcn_rcpf(L); }
     }
     if (nz) {
-      const float L = neglog32(u.y);
-      if (qz <= U.dt * L) { hz = true; fz = qz / (U.dt * L); }
+      const float L = U.dt * neglog32(u.y);
+      if (qz <= L) { hz = true; fz = qz * __builtin_amdgcn_rcpf(L); }
     }
   }
   if (!(hy || hz)) return false;
-  if (cy) fy = d0y / (d0y - d1y);
-  if (cz) fz = d0z / (d0z - d1z);
+  // fractions from the hardware reciprocal (1 ulp), kept in [0, 1]
+  if (cy) fy = d0y * __builtin_amdgcn_rcpf(d0y - d1y);
+  if (cz) fz = d0z * __builtin_amdgcn_rcpf(d0z - d1z);
+  float f;
   if (hy && (!hz || fy <= fz)) {
-    X.f = fy;
+    f = fminf(fy, 1.f);
     X.wall = upy ? 1 : 3;
-    X.t = fminf(fmaxf(__builtin_fmaf(fy, bn - W.b, W.b), -U.hz), U.hz);
+    X.t = fminf(fmaxf(__builtin_fmaf(f, bn - W.b, W.b), -U.hz), U.hz);
   } else {
-    X.f = fz;
+    f = fminf(fz, 1.f);
     X.wall = upz ? 2 : 0;
-    X.t = fminf(fmaxf(__builtin_fmaf(fz, an - W.a, W.a), -U.hy), U.hy);
+    X.t = fminf(fmaxf(__builtin_fmaf(f, an - W.a, W.a), -U.hy), U.hy);
   }
+  X.f = f;
+  X.n = nstep;
+  X.sh = W.shi;
+  X.sl = __builtin_fmaf(W.cc, f, W.slo);   // partial step in the last inside region
   return true;
 }
 
-// Compensated FP32 accumulation (Knuth's TwoSum): shi + slo carries S.
-__device__ __forceinline__ void add_phase32(W32 &W, float c) {
-  const float s = W.shi + c;
-  const float bb = s - W.shi;
-  const float e = (W.shi - (s - bb)) + (c - bb);
-  W.shi = s;
-  W.slo = W.slo + e;
-}
-
+// One step; returns true if the walker left the domain (recorded in X when
+// `live`).  The state is advanced either way.
 template <int SIG>
-__device__ __forceinline__ bool step32(const DevReq &Q, const U32<SIG> &U, W32 &W, float n0, float n1,
-                                       ExitInfo<float> &X) {
-  const float an = __builtin_fmaf(U.s, n0, W.a);
-  const float bn = __builtin_fmaf(U.s, n1, W.b);
+__device__ __forceinline__ bool step32(const DevReq &Q, const U32<SIG> &U, W32 &W, uint32_t wa, uint32_t wb,
+                                       bool live, uint32_t nstep, X32 &X) {
+  float an, bn;
+  propose32(U.K, W.a, W.b, wa, wb, an, bn);
   const float e1y = U.hy - fabsf(an);
   const float e1z = U.hz - fabsf(bn);
-  if (fminf(W.d0y * e1y, W.d0z * e1z) <= U.scr) {
-    if (exit32<SIG>(U, W, an, bn, X)) return true;
-  }
+  bool ex = false;
+  if (live && fminf(W.d0y * e1y, W.d0z * e1z) <= U.scr) ex = exit32<SIG>(U, W, an, bn, nstep, X);
+  // phase of the full step (right-point rule), compensated (Fast2Sum: S_hi
+  // grows from 0 by increments c >= 0)
   const float c = U.reg.eval(Q, an, bn);
-  add_phase32(W, c);
+  const float s = W.shi + c;
+  W.slo += c - (s - W.shi);
+  W.shi = s;
   W.cc = c;
   W.a = an;
   W.b = bn;
   W.d0y = e1y;
   W.d0z = e1z;
-  return false;
+  return ex;
 }
 
-__device__ __forceinline__ PathRec finish32(const DevReq &Q, const W32 &W, const ExitInfo<float> &X) {
-  const double S = ((double)W.shi + (double)W.slo) + (double)(W.cc * X.f);
+__device__ __forceinline__ PathRec finish32(const DevReq &Q, const X32 &X) {
+  const double S = (double)X.sh + (double)X.sl;
   const bool along_y = (X.wall == 0) || (X.wall == 2);
   double t = (double)X.t + (along_y ? Q.ymid : Q.zmid);
   const double lo = along_y ? Q.y_lo : Q.z_lo, hi = along_y ? Q.y_hi : Q.z_hi;
   t = t < lo ? lo : (t > hi ? hi : t);
   PathRec r;
   finish_weight(Q, X.wall, t, S, r);
-  r.tau = ((double)W.n + (double)X.f) * Q.dt;
-  r.steps = W.n + 1u;
+  r.tau = ((double)X.n + (double)X.f) * Q.dt;
+  r.steps = X.n + 1u;
   r.wall = X.wall;
   return r;
 }
 
+// Two steps.  Returns 0 running, 1 exited, 2 step cap.
 template <int SIG>
-__device__ __forceinline__ int iterate32(const DevReq &Q, const U32<SIG> &U, W32 &W, ExitInfo<float> &X) {
+__device__ __forceinline__ int iterate32(const DevReq &Q, const U32<SIG> &U, W32 &W, X32 &X) {
   const uint4 w = philox_pp(W.P, U.ctr3, W.pp, U.k0, U.k1);
-  float a0, a1, b0, b1;
-  normals32(w.x, w.y, a0, a1);
-  normals32(w.z, w.w, b0, b1);
-  if (step32<SIG>(Q, U, W, a0, a1, X)) return 1;
-  W.n += 1u;
-  if (W.n >= U.max_steps) return 2;
-  if (step32<SIG>(Q, U, W, b0, b1, X)) return 1;
-  W.n += 1u;
+  const uint32_t n = W.n;
+  const bool exA = step32<SIG>(Q, U, W, w.x, w.y, true, n, X);
+  const bool capA = n >= U.cap1;
+  const bool exB = step32<SIG>(Q, U, W, w.z, w.w, !exA && !capA, n + 1u, X);
+  W.n = n + 2u;
   W.P += (uint64_t)kM0;
-  return W.n >= U.max_steps ? 2 : 0;
+  if (exA || exB) return 1;
+  return (capA || n >= U.cap2) ? 2 : 0;
 }
 
 // Precision traits for the persistent loop.
@@ -622,14 +667,14 @@ template <int SIG> struct F64 {
 template <int SIG> struct F32 {
   using Walker = W32;
   using Uni = U32<SIG>;
-  using Exit = ExitInfo<float>;
+  using Exit = X32;
   static __device__ __forceinline__ void start(const DevReq &Q, const Uni &U, Walker &W, uint32_t node,
                                                uint32_t path, uint64_t rec) { start32<SIG>(Q, U, W, node, path, rec); }
   static __device__ __forceinline__ int iterate(const DevReq &Q, const Uni &U, Walker &W, Exit &X) {
     return iterate32<SIG>(Q, U, W, X);
   }
-  static __device__ __forceinline__ PathRec finish(const DevReq &Q, const Walker &W, const Exit &X) {
-    return finish32(Q, W, X);
+  static __device__ __forceinline__ PathRec finish(const DevReq &Q, const Walker &, const Exit &X) {
+    return finish32(Q, X);
   }
   static __device__ __forceinline__ void save(const Walker &W, SuspRec &s) {
     s.x = (double)W.a; s.y = (double)W.b; s.s_hi = (double)W.shi; s.s_lo = (double)W.slo; s.rec = W.rec;
@@ -724,10 +769,10 @@ __device__ __forceinline__ bool run_request(const DevReq &Q, uint32_t budget, ui
   bool extra_done = (ctl == nullptr) || (Q.extra_in_n == 0u);
   bool exhausted = false;
   bool suspended = false;
-  uint32_t finished = 0;   // paths this wave completed
+  uint32_t finished = 0;   // paths this lane completed
 
   for (;;) {
-    uint64_t freemask = __ballot(!active);
+    uint64_t freemask = __builtin_amdgcn_ballot_w64(!active);
     // refill every (refill_mask + 1) iterations, and whenever every lane is idle
     const bool refill = ((iters & refill_mask) == 0u) || (freemask == ~0ull);
     if (!refill) freemask = 0ull;
@@ -745,7 +790,7 @@ __device__ __forceinline__ bool run_request(const DevReq &Q, uint32_t budget, ui
         T::resume(Q, U, W, Q.pool_in[base + rank]);
         active = true;
       }
-      freemask = __ballot(!active);
+      freemask = __builtin_amdgcn_ballot_w64(!active);
     }
     // then refill free lanes in rank order from the wave's tile, claiming
     // tile remainders of the previous slice before new tiles
@@ -789,7 +834,7 @@ __device__ __forceinline__ bool run_request(const DevReq &Q, uint32_t budget, ui
       }
     }
     // every lane idle after a refill: this wave can get no more work here
-    const uint64_t freemask_after_refill = __ballot(!active);
+    const uint64_t freemask_after_refill = __builtin_amdgcn_ballot_w64(!active);
     if (freemask_after_refill == ~0ull) break;
 
     if (active) {
@@ -798,13 +843,13 @@ __device__ __forceinline__ bool run_request(const DevReq &Q, uint32_t budget, ui
       if (st != 0) {
         Q.recs[W.rec] = st == 1 ? T::finish(Q, W, X) : unfinished_rec(U.max_steps);
         active = false;
+        finished += 1u;
       }
     }
-    finished += (uint32_t)__popcll(__ballot(!active)) - (uint32_t)__popcll(freemask_after_refill);
     iters += 1u;
     if (budget != 0u && iters >= budget) {
       // suspend: in-flight walkers to pool_out, the tile remainder to extra_out
-      const uint64_t am = __ballot(active);
+      const uint64_t am = __builtin_amdgcn_ballot_w64(active);
       const uint32_t cnt = (uint32_t)__popcll(am);
       if (cnt) {
         uint32_t base = 0;
@@ -834,6 +879,8 @@ __device__ __forceinline__ bool run_request(const DevReq &Q, uint32_t budget, ui
       break;
     }
   }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) finished += __shfl_xor(finished, m, 64);
   if (lane == 0) atomicAdd(Q.done_counter, (unsigned long long)finished);
   return suspended;
 }
@@ -850,7 +897,16 @@ __device__ __forceinline__ bool run_dispatch(const DevReq &Q, uint32_t budget, u
   }
 }
 
-template <template <int> class T>
+// SIG >= 0: every request of the launch has model signature SIG (the walker
+// is compiled for it alone, which keeps the register allocation of the other
+// signatures out of the loop); SIG < 0: requests of any signature.
+template <template <int> class T, int SIG>
+__device__ __forceinline__ bool run_sig(const DevReq &Q, uint32_t budget, uint32_t refill_mask, uint32_t &iters) {
+  if constexpr (SIG < 0) return run_dispatch<T>(Q, budget, refill_mask, iters);
+  else return run_request<T<SIG>>(Q, budget, refill_mask, iters);
+}
+
+template <template <int> class T, int SIG>
 __device__ __forceinline__ void persist_body(const DevReq *__restrict__ reqs, uint32_t n_req,
                                              const uint32_t *__restrict__ wave_start, uint32_t budget,
                                              uint32_t refill_mask) {
@@ -866,21 +922,45 @@ __device__ __forceinline__ void persist_body(const DevReq *__restrict__ reqs, ui
   // loop ends once all work is claimed, or at the slice budget.
   uint32_t iters = 0;
   while (r != kNoRequest) {
-    if (run_dispatch<T>(reqs[r], budget, refill_mask, iters)) break;
+    if (run_sig<T, SIG>(reqs[r], budget, refill_mask, iters)) break;
     r = pick_request(reqs, n_req);
   }
 }
 
+template <int SIG>
 __global__ void __launch_bounds__(256) walk_persist_f64(const DevReq *__restrict__ reqs, uint32_t n_req,
                                                         const uint32_t *__restrict__ wave_start, uint32_t budget,
-                                             uint32_t refill_mask) {
-  persist_body<F64>(reqs, n_req, wave_start, budget, refill_mask);
+                                                        uint32_t refill_mask) {
+  persist_body<F64, SIG>(reqs, n_req, wave_start, budget, refill_mask);
 }
 
+template <int SIG>
 __global__ void __launch_bounds__(256) walk_persist_f32(const DevReq *__restrict__ reqs, uint32_t n_req,
                                                         const uint32_t *__restrict__ wave_start, uint32_t budget,
-                                             uint32_t refill_mask) {
-  persist_body<F32>(reqs, n_req, wave_start, budget, refill_mask);
+                                                        uint32_t refill_mask) {
+  persist_body<F32, SIG>(reqs, n_req, wave_start, budget, refill_mask);
+}
+
+using PersistKernel = void (*)(const DevReq *, uint32_t, const uint32_t *, uint32_t, uint32_t);
+
+template <int SIG> struct K64 { static constexpr PersistKernel fn = walk_persist_f64<SIG>; };
+template <int SIG> struct K32 { static constexpr PersistKernel fn = walk_persist_f32<SIG>; };
+
+template <template <int> class K>
+static PersistKernel pick_kernel(int sig) {
+  switch (sig) {
+    case kSigNone: return K<kSigNone>::fn;
+    case kSigZ: return K<kSigZ>::fn;
+    case kSigZY: return K<kSigZY>::fn;
+    case kSigZBox: return K<kSigZBox>::fn;
+    case kSigZTri: return K<kSigZTri>::fn;
+    case kSigGeneric: return K<kSigGeneric>::fn;
+    default: return K<-1>::fn;
+  }
+}
+
+static PersistKernel persist_kernel(int precision, int sig) {
+  return precision == 0 ? pick_kernel<K64>(sig) : pick_kernel<K32>(sig);
 }
 
 // ---------------------------------------------------------------------------
@@ -1029,16 +1109,19 @@ hipError_t launch_walk_plain(const DevReq *req_dev, uint32_t node, uint32_t p0, 
   return hipGetLastError();
 }
 
-hipError_t launch_walk_persist(int precision, const DevReq *reqs_dev, uint32_t n_req,
+hipError_t launch_walk_persist(int precision, int sig, const DevReq *reqs_dev, uint32_t n_req,
                                const uint32_t *wave_start_dev, uint32_t budget, uint32_t refill_mask, uint32_t blocks,
                                uint32_t threads, hipStream_t st) {
-  if (precision == 0)
-    hipLaunchKernelGGL(walk_persist_f64, dim3(blocks), dim3(threads), 0, st, reqs_dev, n_req, wave_start_dev, budget,
-                       refill_mask);
-  else
-    hipLaunchKernelGGL(walk_persist_f32, dim3(blocks), dim3(threads), 0, st, reqs_dev, n_req, wave_start_dev, budget,
-                       refill_mask);
+  hipLaunchKernelGGL(persist_kernel(precision, sig), dim3(blocks), dim3(threads), 0, st, reqs_dev, n_req,
+                     wave_start_dev, budget, refill_mask);
   return hipGetLastError();
+}
+
+int persist_blocks_per_cu(int precision, int sig, uint32_t threads) {
+  int nb = 0;
+  const hipError_t e =
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persist_kernel(precision, sig), (int)threads, 0);
+  return e == hipSuccess ? nb : 0;
 }
 
 hipError_t launch_reduce_fanout(const FanJob *jobs_dev, uint32_t n_jobs, int M, double y_lo, double y_hi, double z_lo,
@@ -1046,14 +1129,6 @@ hipError_t launch_reduce_fanout(const FanJob *jobs_dev, uint32_t n_jobs, int M, 
   if (n_jobs == 0) return hipSuccess;
   hipLaunchKernelGGL(reduce_fanout, dim3(n_jobs), dim3(kRedThreads), 0, st, jobs_dev, M, y_lo, y_hi, z_lo, z_hi);
   return hipGetLastError();
-}
-
-int persist_blocks_per_cu(int precision, uint32_t threads) {
-  int nb = 0;
-  const hipError_t e = precision == 0
-      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_persist_f64, (int)threads, 0)
-      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_persist_f32, (int)threads, 0);
-  return e == hipSuccess ? nb : 0;
 }
 
 hipError_t launch_reduce(const NodeJob *jobs_dev, uint32_t n_jobs, hipStream_t st) {

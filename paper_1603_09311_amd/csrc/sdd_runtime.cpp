@@ -28,14 +28,14 @@
 namespace sdd {
 hipError_t launch_walk_plain(const DevReq *req_dev, uint32_t node, uint32_t p0, uint32_t count, uint64_t rec0,
                              hipStream_t st);
-hipError_t launch_walk_persist(int precision, const DevReq *reqs_dev, uint32_t n_req,
+hipError_t launch_walk_persist(int precision, int sig, const DevReq *reqs_dev, uint32_t n_req,
                                const uint32_t *wave_start_dev, uint32_t budget, uint32_t refill_mask, uint32_t blocks,
                                uint32_t threads, hipStream_t st);
 hipError_t launch_reduce(const NodeJob *jobs_dev, uint32_t n_jobs, hipStream_t st);
 hipError_t launch_reduce_fanout(const FanJob *jobs_dev, uint32_t n_jobs, int M, double y_lo, double y_hi, double z_lo,
                                 double z_hi, hipStream_t st);
 hipError_t launch_reset(uint32_t *tile_counters, unsigned long long *done, uint32_t n, hipStream_t st);
-int persist_blocks_per_cu(int precision, uint32_t threads);
+int persist_blocks_per_cu(int precision, int sig, uint32_t threads);
 }  // namespace sdd
 
 using namespace sdd;
@@ -362,8 +362,11 @@ static void fill_devreq(Prepared &P) {
   q.fhz = (float)(0.5 * (q.z_hi - q.z_lo));
   q.fs = (float)q.s;
   q.fdt = (float)q.dt;
-  q.fthr = 22.9f * q.fdt;
+  // FP32 uniforms are at least 2^-24, so -ln U <= 24 ln 2 = 16.64: no bridge
+  // hit is possible once 2 d0 d1 > 16.7 dt
+  q.fthr = 16.7f * q.fdt;
   q.fscr = 0.5f * q.fthr;
+  q.fK = (float)(q.s * std::sqrt(2.0 * std::log(2.0)));
   for (uint32_t k = 0; k <= np; ++k) q.fc[k] = (float)q.c[k];
   q.key0 = (uint32_t)(r.seed & 0xFFFFFFFFu);
   q.key1 = (uint32_t)(r.seed >> 32);
@@ -510,11 +513,24 @@ static uint32_t refill_mask(const sdd_ctx *ctx) {
   return ctx->tuning.refill_every ? ctx->tuning.refill_every - 1u : 0u;
 }
 
-static void launch_shape(sdd_ctx *ctx, int precision, uint32_t &blocks, uint32_t &threads) {
+// The model signature shared by every request of a launch, or -1 if they
+// differ (then the walker that handles every signature is launched).
+template <class It, class Get>
+static int common_sig(It begin, It end, Get get) {
+  int sig = -2;
+  for (It i = begin; i != end; ++i) {
+    const int s = get(*i);
+    if (sig == -2) sig = s;
+    else if (sig != s) return -1;
+  }
+  return sig == -2 ? -1 : sig;
+}
+
+static void launch_shape(sdd_ctx *ctx, int precision, int sig, uint32_t &blocks, uint32_t &threads) {
   threads = ctx->tuning.block_threads ? ctx->tuning.block_threads : 256u;
   uint32_t per_cu = ctx->tuning.blocks_per_cu;
   if (!per_cu) {
-    const int occ = persist_blocks_per_cu(precision, threads);
+    const int occ = persist_blocks_per_cu(precision, sig, threads);
     per_cu = occ > 0 ? (uint32_t)occ : 1u;
   }
   blocks = (uint32_t)ctx->cus * per_cu;
@@ -526,7 +542,8 @@ static sdd_status run_group(sdd_ctx *ctx, std::vector<Prepared *> &passes, int p
   const uint32_t n = (uint32_t)passes.size();
   if (n == 0) return SDD_OK;
   uint32_t blocks, threads;
-  launch_shape(ctx, precision, blocks, threads);
+  const int sig = common_sig(passes.begin(), passes.end(), [](const Prepared *P) { return P->dreq.sig; });
+  launch_shape(ctx, precision, sig, blocks, threads);
   const uint32_t waves = blocks * (threads / 64);
   BatchScratch B;
   B.d_reqs = ctx->alloc(n * sizeof(DevReq));
@@ -563,7 +580,7 @@ static sdd_status run_group(sdd_ctx *ctx, std::vector<Prepared *> &passes, int p
         "reset counters");
   if (st == SDD_OK) check(hipEventRecord(ctx->ev[0], ctx->stream), "event");
   if (st == SDD_OK)
-    check(launch_walk_persist(precision, reinterpret_cast<const DevReq *>(B.d_reqs), n,
+    check(launch_walk_persist(precision, sig, reinterpret_cast<const DevReq *>(B.d_reqs), n,
                               reinterpret_cast<const uint32_t *>(B.d_ws), 0u, refill_mask(ctx), blocks, threads,
                               ctx->stream),
           "walk_persist");
@@ -836,12 +853,17 @@ static void release_flight(sdd_ctx *ctx, Flight &F) {
   if (F.P) release_all(ctx, *F.P);
 }
 
-// Pools large enough for every lane and wave of a launch; suspended walkers
-// already waiting in the input pool are carried over.
+// Pools for one slice: its output must hold every walker the launch can
+// suspend (one per lane) and every tile remainder (one per wave), plus the
+// entries of the input pools that the slice leaves unclaimed (carried over by
+// the host; a launch may have fewer lanes than the previous slice had).
+// Suspended walkers already waiting in the input pool are kept.
 static sdd_status ensure_pools(sdd_ctx *ctx, Flight &F, uint32_t lanes, uint32_t waves) {
-  if (F.pool_cap >= lanes && F.extra_cap >= waves && F.d_pool[0]) return SDD_OK;
-  char *np[2] = {ctx->alloc((size_t)lanes * sizeof(SuspRec)), ctx->alloc((size_t)lanes * sizeof(SuspRec))};
-  char *ne[2] = {ctx->alloc((size_t)waves * sizeof(DevTile)), ctx->alloc((size_t)waves * sizeof(DevTile))};
+  const uint32_t need_p = lanes + F.pool_n, need_e = waves + F.extra_n;
+  if (F.pool_cap >= need_p && F.extra_cap >= need_e && F.d_pool[0]) return SDD_OK;
+  const uint32_t cap_p = std::max(need_p, F.pool_cap), cap_e = std::max(need_e, F.extra_cap);
+  char *np[2] = {ctx->alloc((size_t)cap_p * sizeof(SuspRec)), ctx->alloc((size_t)cap_p * sizeof(SuspRec))};
+  char *ne[2] = {ctx->alloc((size_t)cap_e * sizeof(DevTile)), ctx->alloc((size_t)cap_e * sizeof(DevTile))};
   if (!np[0] || !np[1] || !ne[0] || !ne[1]) {
     for (int i = 0; i < 2; ++i) { ctx->release(np[i]); ctx->release(ne[i]); }
     return fail(SDD_E_NOMEM, "no workspace left for the suspension pools");
@@ -857,8 +879,8 @@ static sdd_status ensure_pools(sdd_ctx *ctx, Flight &F, uint32_t lanes, uint32_t
     F.d_pool[i] = np[i];
     F.d_extra[i] = ne[i];
   }
-  F.pool_cap = lanes;
-  F.extra_cap = waves;
+  F.pool_cap = cap_p;
+  F.extra_cap = cap_e;
   return SDD_OK;
 }
 
@@ -867,7 +889,8 @@ static sdd_status run_slice(sdd_ctx *ctx, std::vector<Flight *> &fl, int precisi
   const uint32_t n = (uint32_t)fl.size();
   if (n == 0) return SDD_OK;
   uint32_t blocks, threads;
-  launch_shape(ctx, precision, blocks, threads);
+  const int sig = common_sig(fl.begin(), fl.end(), [](const Flight *F) { return F->P->dreq.sig; });
+  launch_shape(ctx, precision, sig, blocks, threads);
   const uint32_t lanes = blocks * threads, waves = blocks * (threads / 64);
   for (auto *F : fl) {
     sdd_status st = ensure_pools(ctx, *F, lanes, waves);
@@ -933,7 +956,7 @@ static sdd_status run_slice(sdd_ctx *ctx, std::vector<Flight *> &fl, int precisi
     if (e == hipSuccess) e = hipMemcpyAsync(d_ws, ws.data(), (n + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess) e = hipEventRecord(ctx->ev[0], ctx->stream);
     if (e == hipSuccess)
-      e = launch_walk_persist(precision, reinterpret_cast<const DevReq *>(d_reqs), n,
+      e = launch_walk_persist(precision, sig, reinterpret_cast<const DevReq *>(d_reqs), n,
                               reinterpret_cast<const uint32_t *>(d_ws),
                               ctx->tuning.slice_iters ? ctx->tuning.slice_iters : 4096u, refill_mask(ctx), blocks, threads,
                               ctx->stream);
@@ -952,11 +975,26 @@ static sdd_status run_slice(sdd_ctx *ctx, std::vector<Flight *> &fl, int precisi
   for (uint32_t i = 0; i < n; ++i) {
     Flight &F = *fl[i];
     const FlightCtl &c = ctl[i];
-    if (c.slice[kPoolOut] > F.pool_cap || c.slice[kExtraOut] > F.extra_cap)
-      return fail(SDD_E_DEVICE, "suspension pool overflow (%u > %u walkers)", c.slice[kPoolOut], F.pool_cap);
-    F.par ^= 1;
-    F.pool_n = c.slice[kPoolOut];
-    F.extra_n = c.slice[kExtraOut];
+    // entries of the input pools no wave claimed move to the end of the
+    // output pools
+    const uint32_t pc = std::min(c.slice[kPoolCursor], F.pool_n);
+    const uint32_t ec = std::min(c.slice[kExtraCursor], F.extra_n);
+    const uint32_t carry_p = F.pool_n - pc, carry_e = F.extra_n - ec;
+    if (c.slice[kPoolOut] + carry_p > F.pool_cap || c.slice[kExtraOut] + carry_e > F.extra_cap)
+      return fail(SDD_E_DEVICE, "suspension pool overflow (%u + %u > %u walkers)", c.slice[kPoolOut], carry_p,
+                  F.pool_cap);
+    const int in = F.par, out = F.par ^ 1;
+    if (carry_p)
+      HIP_TRY(hipMemcpyAsync(F.d_pool[out] + (size_t)c.slice[kPoolOut] * sizeof(SuspRec),
+                             F.d_pool[in] + (size_t)pc * sizeof(SuspRec), (size_t)carry_p * sizeof(SuspRec),
+                             hipMemcpyDeviceToDevice, ctx->stream));
+    if (carry_e)
+      HIP_TRY(hipMemcpyAsync(F.d_extra[out] + (size_t)c.slice[kExtraOut] * sizeof(DevTile),
+                             F.d_extra[in] + (size_t)ec * sizeof(DevTile), (size_t)carry_e * sizeof(DevTile),
+                             hipMemcpyDeviceToDevice, ctx->stream));
+    F.par = out;
+    F.pool_n = c.slice[kPoolOut] + carry_p;
+    F.extra_n = c.slice[kExtraOut] + carry_e;
     F.tile_counter = c.tile_counter;
     F.done = c.done;
   }
@@ -1525,7 +1563,7 @@ sdd_status sdd_autotune(sdd_ctx_t ctx, const sdd_request *req, uint32_t sample_p
   s.target_rel_se = 0.0;
   if (!sample_paths) {
     uint32_t b, t;
-    launch_shape(ctx, (int)req->precision, b, t);
+    launch_shape(ctx, (int)req->precision, -1, b, t);
     sample_paths = (uint32_t)std::min<uint64_t>(1u << 24, (4ull * b * t + req->n_nodes - 1) / req->n_nodes);
   }
   std::vector<uint32_t> cnt(req->n_nodes);
@@ -1610,6 +1648,7 @@ struct sdd_batch {
   std::vector<std::unique_ptr<Prepared>> Ps;
   struct Group {
     int prec;
+    int sig = -1;
     std::vector<Prepared *> P;
     char *d_reqs = nullptr, *d_ctr = nullptr, *d_done = nullptr, *d_ws = nullptr;
     uint32_t blocks = 0, threads = 0;
@@ -1680,7 +1719,8 @@ sdd_status sdd_batch_create(sdd_ctx_t ctx, uint32_t n, const sdd_request *reqs, 
       if ((int)b->Ps[i]->dreq.precision == prec) g.P.push_back(b->Ps[i].get());
     if (g.P.empty()) continue;
     const uint32_t m = (uint32_t)g.P.size();
-    launch_shape(ctx, prec, g.blocks, g.threads);
+    g.sig = common_sig(g.P.begin(), g.P.end(), [](const Prepared *P) { return P->dreq.sig; });
+    launch_shape(ctx, prec, g.sig, g.blocks, g.threads);
     const uint32_t waves = g.blocks * (g.threads / 64);
     g.d_reqs = ctx->alloc(m * sizeof(DevReq));
     g.d_ctr = ctx->alloc(m * sizeof(uint32_t));
@@ -1745,7 +1785,7 @@ sdd_status sdd_batch_create(sdd_ctx_t ctx, uint32_t n, const sdd_request *reqs, 
   if (e == hipSuccess) e = hipEventRecord(ctx->ev[0], b->cap);
   for (auto &g : b->groups)
     if (e == hipSuccess)
-      e = launch_walk_persist(g.prec, reinterpret_cast<const DevReq *>(g.d_reqs), (uint32_t)g.P.size(),
+      e = launch_walk_persist(g.prec, g.sig, reinterpret_cast<const DevReq *>(g.d_reqs), (uint32_t)g.P.size(),
                               reinterpret_cast<const uint32_t *>(g.d_ws), 0u, refill_mask(ctx), g.blocks, g.threads,
                               b->cap);
   if (e == hipSuccess) e = hipEventRecord(ctx->ev[1], b->cap);

@@ -35,6 +35,14 @@ def test_library_exports_every_declared_symbol():
 
 
 @pytest.mark.skipif(not os.path.exists(sdd.LIB_PATH), reason="libsdd.so not built")
+def test_library_has_no_unresolved_own_symbols():
+    """Every function of the library's own namespace is defined in it (a
+    shared object links with undefined symbols and fails only when loaded)."""
+    nm = subprocess.run(["nm", "-D", "--undefined-only", sdd.LIB_PATH], capture_output=True, text=True).stdout
+    own = [ln for ln in nm.splitlines() if "3sdd" in ln or " sdd_" in ln]
+    assert not own, own
+
+
 def test_status_strings_and_errors_without_gpu():
     L = sdd.lib()
     assert L.sdd_status_string(0) == b"ok"

@@ -334,6 +334,25 @@ def test_served_requests_join_while_others_run(ctx):
     assert r_big["paths_done"].sum() == big.total_paths
 
 
+def test_served_slices_survive_a_narrower_launch(ctx):
+    """Walkers suspended by a wide launch can outnumber the lanes of the next,
+    narrower one (another tuning, or another walker build with less
+    occupancy): the ones no wave resumes carry over to later slices and the
+    result is still bitwise the blocking one."""
+    p = W.quarter_space(paths=256, precision=W.FP32_MIXED, M=1024).subset(np.arange(0, 512, 4))
+    try:
+        ctx.set_tuning(slice_iters=64)
+        t = ctx.submit(p, records=True)
+        time.sleep(0.02)
+        ctx.set_tuning(slice_iters=64, blocks_per_cu=1, block_threads=64)
+        r = ctx.wait(t, timeout_s=100)
+    finally:
+        ctx.set_tuning()
+    alone = ctx.solve(p, records=True)
+    assert r["records"].tobytes() == alone["records"].tobytes()
+    assert np.array_equal(r["mean"], alone["mean"])
+
+
 def test_batch_graph_replays_bitwise(ctx):
     """A prepared batch replayed as a HIP graph several times, with eager
     work and synchronisations in between: every replay equals the eager
