@@ -46,10 +46,9 @@ VALU_PEAK = CUS * SIMDS * LANES * CLOCK
 #   uniforms: radius (align + exact subtract), angle (align)         =  3
 #   Box-Muller + proposal (log2, sqrt, mul, cos, sin, 2 fma)         =  7
 #   exit screen, both axes (2 sub |.|, 2 mul, min, compare)          =  6
-#   region lookup, 2 half-planes (2 compares, 2 selects)             =  4
-#   compensated phase add (Fast2Sum + low-part accumulate)           =  4
+#   region of the proposal: 2 tests, 2 count increments              =  4
 #   step counter and cap (one add and one compare per two steps)     =  1
-OPS_PER_STEP = 18.5 + 3 + 7 + 6 + 4 + 4 + 1   # = 43.5
+OPS_PER_STEP = 18.5 + 3 + 7 + 6 + 4 + 1   # = 39.5
 
 
 def kernel_source_hash() -> str:

@@ -198,68 +198,112 @@ template <int SIG> struct Reg64 {
   }
 };
 
-// A wave-uniform value copied into a VGPR once: a per-lane select between it
-// and a scalar operand is then one v_cndmask (two scalar operands would need
-// a move or a branch per select).
-__device__ __forceinline__ float in_vgpr(float x) {
-  float r;
-  asm("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
-  return r;
+// Index of the first primitive containing (y, z), or np (background).
+template <class R, int STRIDE>
+__device__ __forceinline__ int region_index_generic(int np, const int32_t *kind, const R *prm, R y, R z) {
+  int idx = np;
+  for (int k = np - 1; k >= 0; --k) {
+    const int kd = kind[k];
+    const R *v = prm + k * STRIDE;
+    bool in;
+    if (kd == kHalfZ) {
+      in = z < v[0];
+    } else if (kd == kHalfY) {
+      in = y < v[0];
+    } else if (kd == kBox) {
+      in = (y >= v[0]) & (y < v[1]) & (z >= v[2]) & (z < v[3]);
+    } else {
+      const R e0 = (v[2] - v[0]) * (z - v[1]) - (v[3] - v[1]) * (y - v[0]);
+      const R e1 = (v[4] - v[2]) * (z - v[3]) - (v[5] - v[3]) * (y - v[2]);
+      const R e2 = (v[0] - v[4]) * (z - v[5]) - (v[1] - v[5]) * (y - v[4]);
+      in = ((e0 >= R(0)) & (e1 >= R(0)) & (e2 >= R(0))) | ((e0 <= R(0)) & (e1 <= R(0)) & (e2 <= R(0)));
+    }
+    idx = in ? k : idx;
+  }
+  return idx;
 }
 
-// FP32 lookup in centred coordinates; the triangle as three linear forms.
-// The phase rates of the regions live in VGPRs (loop-invariant copies), so
-// every select is a single v_cndmask on two VGPRs.
+// FP32 region tests in centred coordinates; the triangle as three linear
+// forms.  The specialised signatures have at most three regions: primitive 0
+// (air above z0), primitive 1 (half-plane, box or triangle) and the
+// background.  Their walkers count full steps per region instead of summing
+// phase increments: the phase of n full steps is then exactly
+// c0 n0 + c1 n1 + cb (n - n0 - n1), formed in FP64 when the path exits.  The
+// generic signature sums FP32 increments (compensated).
 template <int SIG> struct Reg32 {
-  float cb, c0, c1;
+  static constexpr bool kCounted = SIG != kSigGeneric;
   float p[10];
   __device__ __forceinline__ void load(const DevReq &Q) {
-    const int np = (int)Q.nprims;
-    cb = in_vgpr(unif(Q.fc[np]));
-    if constexpr (SIG != kSigNone && SIG != kSigGeneric) {
-      c0 = in_vgpr(unif(Q.fc[0]));
-      p[0] = unif(Q.sigp[0]);
-    }
+    if constexpr (SIG != kSigNone && SIG != kSigGeneric) p[0] = unif(Q.sigp[0]);
     if constexpr (SIG == kSigZY || SIG == kSigZBox || SIG == kSigZTri) {
-      c1 = in_vgpr(unif(Q.fc[1]));
 #pragma unroll
       for (int i = 1; i < 10; ++i) p[i] = unif(Q.sigp[i]);
     }
   }
-  // The scalar operands are read (readfirstlane, which is convergent) before
-  // the selects, so that each select stays a select (v_cndmask) rather than
-  // a branch around a convergent call.
-  __device__ __forceinline__ float eval(const DevReq &Q, float a, float b) const {
-    const float vb = cb;
-    if constexpr (SIG == kSigNone) {
-      return vb;
-    } else if constexpr (SIG == kSigZ) {
-      const float z0 = unif(p[0]), va = c0;
-      return b < z0 ? va : vb;
-    } else if constexpr (SIG == kSigZY) {
-      const float z0 = unif(p[0]), y1 = unif(p[1]), va = c0, vl = c1;
-      const float c = a < y1 ? vl : vb;
-      return b < z0 ? va : c;
+  // region index: 0, 1, or 2 for the background (generic: its own numbering,
+  // np for the background)
+  __device__ __forceinline__ bool in_prim1(float a, float b) const {
+    if constexpr (SIG == kSigZY) {
+      return a < unif(p[1]);
     } else if constexpr (SIG == kSigZBox) {
-      const float z0 = unif(p[0]), y0 = unif(p[1]), y1 = unif(p[2]), zb0 = unif(p[3]), zb1 = unif(p[4]);
-      const float va = c0, vx = c1;
-      const bool in = (a >= y0) & (a < y1) & (b >= zb0) & (b < zb1);
-      const float c = in ? vx : vb;
-      return b < z0 ? va : c;
+      return (a >= unif(p[1])) & (a < unif(p[2])) & (b >= unif(p[3])) & (b < unif(p[4]));
     } else if constexpr (SIG == kSigZTri) {
       float q[10];
 #pragma unroll
-      for (int i = 0; i < 10; ++i) q[i] = unif(p[i]);
-      const float va = c0, vx = c1;
+      for (int i = 1; i < 10; ++i) q[i] = unif(p[i]);
       const float e0 = __builtin_fmaf(q[1], a, __builtin_fmaf(q[2], b, q[3]));
       const float e1 = __builtin_fmaf(q[4], a, __builtin_fmaf(q[5], b, q[6]));
       const float e2 = __builtin_fmaf(q[7], a, __builtin_fmaf(q[8], b, q[9]));
-      const bool in = (fminf(fminf(e0, e1), e2) >= 0.f) | (fmaxf(fmaxf(e0, e1), e2) <= 0.f);
-      const float c = in ? vx : vb;
-      return b < q[0] ? va : c;
+      return (fminf(fminf(e0, e1), e2) >= 0.f) | (fmaxf(fmaxf(e0, e1), e2) <= 0.f);
     } else {
-      return region_c_generic<float, 8>((int)Q.nprims, Q.kind, &Q.pf[0][0], Q.fc, a, b);
+      return false;
     }
+  }
+  __device__ __forceinline__ int index(const DevReq &Q, float a, float b) const {
+    if constexpr (SIG == kSigNone) {
+      return 2;
+    } else if constexpr (SIG == kSigGeneric) {
+      return region_index_generic<float, 8>((int)Q.nprims, Q.kind, &Q.pf[0][0], a, b);
+    } else {
+      if (b < unif(p[0])) return 0;
+      return in_prim1(a, b) ? 1 : 2;
+    }
+  }
+  // one full step ending at (a, b): add it to its region's count (every
+  // operand read and every test made before the adds, so that each add is
+  // one add-with-carry on the test's lane mask)
+  // The counts are g = steps outside primitive 0 (below the air) and
+  // m = those of them inside primitive 1.
+  __device__ __forceinline__ void count(float a, float b, uint32_t &g, uint32_t &m) const {
+    if constexpr (SIG != kSigNone && SIG != kSigGeneric) {
+      const float z0 = unif(p[0]);
+      const bool ground = b >= z0;
+      if constexpr (SIG != kSigZ) {
+        const bool in1 = in_prim1(a, b);
+        m += (uint32_t)(in1 & ground);
+      }
+      g += (uint32_t)ground;
+    }
+  }
+  // FP64 phase rate of region index k
+  __device__ __forceinline__ double rate(const DevReq &Q, int k) const {
+    if constexpr (SIG == kSigGeneric) return Q.c[k];
+    else return k == 2 ? Q.c[Q.nprims] : Q.c[k];
+  }
+  // phase of n full steps from the counts g, m
+  __device__ __forceinline__ double phase(const DevReq &Q, uint32_t g, uint32_t m, uint32_t n) const {
+    const double cb = unid(Q.c[Q.nprims]);
+    if constexpr (SIG == kSigNone) {
+      return cb * (double)n;
+    } else if constexpr (SIG == kSigZ) {
+      return unid(Q.c[0]) * (double)(n - g) + cb * (double)g;
+    } else {
+      return (unid(Q.c[0]) * (double)(n - g) + unid(Q.c[1]) * (double)m) + cb * (double)(g - m);
+    }
+  }
+  // generic signature: FP32 rate of the region containing (a, b)
+  __device__ __forceinline__ float rate32(const DevReq &Q, float a, float b) const {
+    return region_c_generic<float, 8>((int)Q.nprims, Q.kind, &Q.pf[0][0], Q.fc, a, b);
   }
 };
 
@@ -468,8 +512,8 @@ __device__ __forceinline__ int iterate64(const DevReq &Q, const U64<SIG> &U, W64
 struct W32 {
   float a, b;       // y - ymid, z - zmid
   float d0y, d0z;   // h - |a|, h - |b|
-  float shi, slo;   // phase S = shi + slo (compensated)
-  float cc;         // phase rate of the current region
+  uint32_t n0, n1;  // counted signatures: full steps below the air / those in primitive 1
+  float shi, slo;   // phase S = shi + slo (generic signature, compensated)
   uint32_t n, path, node;
   uint64_t rec;
   uint64_t P;
@@ -479,7 +523,7 @@ struct W32 {
 // Exit of an FP32 walker: everything its record needs.
 struct X32 {
   float f, t;       // fraction of the last step; tangential coordinate (centred)
-  float sh, sl;     // phase at the exit point: sh + sl
+  double S;         // phase at the exit point
   uint32_t n;       // index of the exit step
   int wall;         // 0 top, 1 right, 2 bottom, 3 left
 };
@@ -527,6 +571,8 @@ __device__ __forceinline__ void start32(const DevReq &Q, const U32<SIG> &U, W32 
   W.b = (float)(p.y - Q.zmid);
   W.d0y = U.hy - fabsf(W.a);
   W.d0z = U.hz - fabsf(W.b);
+  W.n0 = 0;
+  W.n1 = 0;
   W.shi = 0.f;
   W.slo = 0.f;
   W.n = 0;
@@ -535,13 +581,12 @@ __device__ __forceinline__ void start32(const DevReq &Q, const U32<SIG> &U, W32 
   W.rec = rec;
   W.P = 0;
   W.pp = philox_path(path, node, U.k0);
-  W.cc = U.reg.eval(Q, W.a, W.b);
 }
 
 // Exact exit logic for a lane the screen flagged (step index nstep).
 template <int SIG>
-__device__ __forceinline__ bool exit32(const U32<SIG> &U, const W32 &W, float an, float bn, uint32_t nstep,
-                                       X32 &X) {
+__device__ __forceinline__ bool exit32(const DevReq &Q, const U32<SIG> &U, const W32 &W, float an, float bn,
+                                       uint32_t nstep, X32 &X) {
   const bool upy = W.a > 0.f;   // a tie (a = 0) goes to the lower wall
   const bool upz = W.b > 0.f;
   const float d0y = W.d0y, d0z = W.d0z;
@@ -581,8 +626,11 @@ __device__ __forceinline__ bool exit32(const U32<SIG> &U, const W32 &W, float an
   }
   X.f = f;
   X.n = nstep;
-  X.sh = W.shi;
-  X.sl = __builtin_fmaf(W.cc, f, W.slo);   // partial step in the last inside region
+  // phase of the nstep full steps, plus the partial step charged to the
+  // region of the last inside point
+  const double S = Reg32<SIG>::kCounted ? U.reg.phase(Q, W.n0, W.n1, nstep)
+                                        : (double)W.shi + (double)W.slo;
+  X.S = S + U.reg.rate(Q, U.reg.index(Q, W.a, W.b)) * (double)f;
   return true;
 }
 
@@ -596,14 +644,18 @@ __device__ __forceinline__ bool step32(const DevReq &Q, const U32<SIG> &U, W32 &
   const float e1y = U.hy - fabsf(an);
   const float e1z = U.hz - fabsf(bn);
   bool ex = false;
-  if (live && fminf(W.d0y * e1y, W.d0z * e1z) <= U.scr) ex = exit32<SIG>(U, W, an, bn, nstep, X);
-  // phase of the full step (right-point rule), compensated (Fast2Sum: S_hi
-  // grows from 0 by increments c >= 0)
-  const float c = U.reg.eval(Q, an, bn);
-  const float s = W.shi + c;
-  W.slo += c - (s - W.shi);
-  W.shi = s;
-  W.cc = c;
+  if (live && fminf(W.d0y * e1y, W.d0z * e1z) <= U.scr) ex = exit32<SIG>(Q, U, W, an, bn, nstep, X);
+  // the full step's phase goes to the region of the proposal (right-point
+  // rule): a step count per region, or (generic signature) a compensated
+  // FP32 sum (Fast2Sum: S_hi grows from 0 by increments c >= 0)
+  if constexpr (Reg32<SIG>::kCounted) {
+    U.reg.count(an, bn, W.n0, W.n1);
+  } else {
+    const float c = U.reg.rate32(Q, an, bn);
+    const float s = W.shi + c;
+    W.slo += c - (s - W.shi);
+    W.shi = s;
+  }
   W.a = an;
   W.b = bn;
   W.d0y = e1y;
@@ -612,7 +664,7 @@ __device__ __forceinline__ bool step32(const DevReq &Q, const U32<SIG> &U, W32 &
 }
 
 __device__ __forceinline__ PathRec finish32(const DevReq &Q, const X32 &X) {
-  const double S = (double)X.sh + (double)X.sl;
+  const double S = X.S;
   const bool along_y = (X.wall == 0) || (X.wall == 2);
   double t = (double)X.t + (along_y ? Q.ymid : Q.zmid);
   const double lo = along_y ? Q.y_lo : Q.z_lo, hi = along_y ? Q.y_hi : Q.z_hi;
@@ -676,18 +728,25 @@ template <int SIG> struct F32 {
   static __device__ __forceinline__ PathRec finish(const DevReq &Q, const Walker &, const Exit &X) {
     return finish32(Q, X);
   }
+  // counts and FP32 values all widen to doubles exactly
   static __device__ __forceinline__ void save(const Walker &W, SuspRec &s) {
-    s.x = (double)W.a; s.y = (double)W.b; s.s_hi = (double)W.shi; s.s_lo = (double)W.slo; s.rec = W.rec;
-    s.n = W.n; s.path = W.path; s.node = W.node; s.pad = 0; s.pad1 = 0;
+    s.x = (double)W.a; s.y = (double)W.b;
+    s.s_hi = Reg32<SIG>::kCounted ? (double)W.n0 : (double)W.shi;
+    s.s_lo = Reg32<SIG>::kCounted ? (double)W.n1 : (double)W.slo;
+    s.rec = W.rec; s.n = W.n; s.path = W.path; s.node = W.node; s.pad = 0; s.pad1 = 0;
   }
   static __device__ __forceinline__ void resume(const DevReq &Q, const Uni &U, Walker &W, const SuspRec &s) {
-    W.a = (float)s.x; W.b = (float)s.y; W.shi = (float)s.s_hi; W.slo = (float)s.s_lo; W.rec = s.rec;
-    W.n = s.n; W.path = s.path; W.node = s.node;
+    W.a = (float)s.x; W.b = (float)s.y;
+    if constexpr (Reg32<SIG>::kCounted) {
+      W.n0 = (uint32_t)s.s_hi; W.n1 = (uint32_t)s.s_lo;
+    } else {
+      W.shi = (float)s.s_hi; W.slo = (float)s.s_lo;
+    }
+    W.rec = s.rec; W.n = s.n; W.path = s.path; W.node = s.node;
     W.d0y = U.hy - fabsf(W.a);
     W.d0z = U.hz - fabsf(W.b);
     W.P = (uint64_t)kM0 * (uint64_t)(W.n >> 1);
     W.pp = philox_path(W.path, W.node, U.k0);
-    W.cc = U.reg.eval(Q, W.a, W.b);
   }
 };
 
@@ -879,9 +938,7 @@ __device__ __forceinline__ bool run_request(const DevReq &Q, uint32_t budget, ui
       break;
     }
   }
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) finished += __shfl_xor(finished, m, 64);
-  if (lane == 0) atomicAdd(Q.done_counter, (unsigned long long)finished);
+  if (finished) atomicAdd(Q.done_counter, (unsigned long long)finished);
   return suspended;
 }
 
@@ -935,7 +992,7 @@ __global__ void __launch_bounds__(256) walk_persist_f64(const DevReq *__restrict
 }
 
 template <int SIG>
-__global__ void __launch_bounds__(256) walk_persist_f32(const DevReq *__restrict__ reqs, uint32_t n_req,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) walk_persist_f32(const DevReq *__restrict__ reqs, uint32_t n_req,
                                                         const uint32_t *__restrict__ wave_start, uint32_t budget,
                                                         uint32_t refill_mask) {
   persist_body<F32, SIG>(reqs, n_req, wave_start, budget, refill_mask);
