@@ -9,7 +9,10 @@ Legs besides the timed workload (each bounded, each can be switched off):
   --plain   the plain FP64 one-launch-per-node form and the FP64 persistent
             walker on a node subset (the comparison form);
   --served  a short Poisson stream of mixed requests through the served
-            mode, for p50/p99 latency;
+            mode, for p50/p99 latency, beside the same stream through
+            blocking solves in arrival order;
+  --mt      pointwise TE apparent resistivity and phase at the COMMEMI 2D-1
+            sites (Table 2 of the paper as context);
   cpu       the FP64 CPU oracle on a bounded sample of the same workload
             (rank 0 only), as a baseline.
 """
@@ -153,6 +156,39 @@ def served_leg(ctx, n_requests: int, rate_hz: float, paths: int):
             "fifo_blocking_baseline": fifo}
 
 
+# Table 2 of Sec. 4.3 (TE apparent resistivity, ohm m, COMMEMI 2D-1 at 10 Hz):
+# the COMMEMI mean and spread the paper quotes, and the paper's own pointwise
+# stochastic values; context for the mt leg, not a target.
+TABLE2_TE_COMMEMI = [(7.60, 1.04), (13.92, 1.82), (50.70, 2.48), (95.94, 2.75), (103.92, 0.80)]
+TABLE2_TE_STOCHASTIC = [6.70, 12.50, 50.84, 97.54, 103.77]
+
+
+def mt_leg(ctx, seeds: int = 4, paths: int = 1 << 20, h: float = 0.05, dt: float = 4e-4):
+    """Pointwise TE responses at the five COMMEMI 2D-1 sites (Sec. 4.3): the
+    field at three points per site (common random numbers), apparent
+    resistivity and phase from a centred difference; mean and spread over
+    independent seeds."""
+    from paper_1603_09311_amd import sdd as S
+    from paper_1603_09311_amd import workloads as W
+    rhos, phis, steps = [], [], 0.0
+    t0 = time.perf_counter()
+    for seed in range(seeds):
+        ps = W.commemi_te_points(paths=paths, seed=seed, dt=dt, h=h)
+        r = ctx.solve_batch(ps)
+        rho, phi = S.mt_te_response(*[x["mean"] for x in r], h, 1000.0, 10.0)
+        rhos.append(rho)
+        phis.append(phi)
+        steps += sum(float(x["steps"].sum()) for x in r)
+    wall = time.perf_counter() - t0
+    rhos, phis = np.array(rhos), np.array(phis)
+    return {"sites_m": [1000.0 * s for s in W.COMMEMI_SITES_KM], "freq_hz": 10.0, "paths_per_point": paths,
+            "seeds": seeds, "h_m": 1000.0 * h, "dt_km2": dt,
+            "rho_a_te": rhos.mean(0).round(3).tolist(), "rho_a_te_sd": rhos.std(0, ddof=1).round(3).tolist(),
+            "phase_te_deg": phis.mean(0).round(3).tolist(), "phase_te_sd": phis.std(0, ddof=1).round(3).tolist(),
+            "table2_commemi": TABLE2_TE_COMMEMI, "table2_stochastic": TABLE2_TE_STOCHASTIC,
+            "walk_steps": steps, "wall_s": wall, "walk_steps_per_s": steps / wall}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,6 +199,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-mt", action="store_true", help="skip the pointwise MT response leg")
     ap.add_argument("--served-requests", type=int, default=24)
     ap.add_argument("--served-rate", type=float, default=8.0)
     args = ap.parse_args()
@@ -262,6 +299,10 @@ def main():
         log(f"served: {out['served']}")
         out["p50_ms"] = out["served"]["p50_ms"]
         out["p99_ms"] = out["served"]["p99_ms"]
+
+    if not args.no_mt:
+        out["mt_response"] = mt_leg(ctx)
+        log(f"mt response: {out['mt_response']}")
 
     if not args.no_cpu:
         cb = cpu_baseline(p)

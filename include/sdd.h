@@ -216,7 +216,9 @@ sdd_status sdd_autotune(sdd_ctx_t ctx, const sdd_request *req, uint32_t sample_p
                         sdd_tune_trial *trials, uint32_t max_trials, uint32_t *n_trials);
 
 /* Timing of the most recent walk launch on this context, measured with HIP
- * events on the context's stream around the walk kernel alone. */
+ * events on the context's stream around the walk kernel alone (for a batch
+ * replay: around the whole replayed graph, of which the walks are all but a
+ * fraction of a percent). */
 typedef struct {
     double last_walk_ms;          /* duration of the last walk kernel (persistent or plain) */
     double last_reduce_ms;        /* duration of the last reduction kernel */
@@ -263,6 +265,22 @@ sdd_status sdd_batch_destroy(sdd_batch_t batch);
  * Errors: SDD_E_INVALID for the above, SDD_E_NOMEM, SDD_E_DEVICE. */
 sdd_status sdd_solve_multi_freq(sdd_ctx_t ctx, const sdd_request *req, uint32_t n_freq, const double *freqs,
                                 const double *const *g_tables, sdd_result *res);
+
+/* TE apparent resistivity and phase at n sites from the field at three
+ * points per site: (y, z - h), (y, z), (y, z + h), z positive down (Sec. 2.1,
+ * Eqs. 2-3): H^x = -(1 / (i omega mu0)) dE/dz with the centred difference
+ * (E(z + h) - E(z - h)) / (2 h L), then rho_a = |E / H^x|^2 / (omega mu0) in
+ * ohm m and phi = arg(E / H^x) in degrees, E = E(z).
+ *   e_minus, e_mid, e_plus  n x (re, im) each (host, caller-owned);
+ *   h                       offset in model length units (> 0);
+ *   length_unit_m           metres per model length unit (> 0);
+ *   freq_hz                 > 0;
+ *   rho_a, phase_deg        n each (host, caller-owned), written.
+ * Host arithmetic only (no device work).  SDD_E_INVALID for NULL arrays with
+ * n > 0 or a non-positive h, length unit or frequency.  A site whose
+ * difference is exactly zero gets rho_a = +inf and phase NaN. */
+sdd_status sdd_mt_te_response(uint32_t n, const double *e_minus, const double *e_mid, const double *e_plus, double h,
+                              double length_unit_m, double freq_hz, double *rho_a, double *phase_deg);
 
 /* Bytes of workspace a request needs (tables, nodes, tiles, records). */
 sdd_status sdd_request_footprint(sdd_ctx_t ctx, const sdd_request *req, uint64_t *bytes);

@@ -8,6 +8,7 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <complex>
 #include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
@@ -1335,6 +1336,31 @@ sdd_status sdd_solve_batch(sdd_ctx_t ctx, uint32_t n, const sdd_request *reqs, s
   return st;
 }
 
+sdd_status sdd_mt_te_response(uint32_t n, const double *e_minus, const double *e_mid, const double *e_plus, double h,
+                              double length_unit_m, double freq_hz, double *rho_a, double *phase_deg) {
+  if (n && (!e_minus || !e_mid || !e_plus || !rho_a || !phase_deg)) return fail(SDD_E_INVALID, "NULL array");
+  if (!(h > 0.0) || !(length_unit_m > 0.0) || !(freq_hz > 0.0))
+    return fail(SDD_E_INVALID, "h, length unit and frequency must be positive");
+  const double pi = 3.14159265358979323846;
+  const double wmu = 2.0 * pi * freq_hz * (4e-7 * pi);
+  for (uint32_t j = 0; j < n; ++j) {
+    const std::complex<double> em(e_minus[2 * j], e_minus[2 * j + 1]);
+    const std::complex<double> e0(e_mid[2 * j], e_mid[2 * j + 1]);
+    const std::complex<double> ep(e_plus[2 * j], e_plus[2 * j + 1]);
+    const std::complex<double> dedz = (ep - em) / (2.0 * h * length_unit_m);   // per metre
+    const std::complex<double> hx = -dedz / std::complex<double>(0.0, wmu);
+    if (hx == std::complex<double>(0.0, 0.0)) {
+      rho_a[j] = HUGE_VAL;
+      phase_deg[j] = NAN;
+      continue;
+    }
+    const std::complex<double> z = e0 / hx;
+    rho_a[j] = std::norm(z) / wmu;
+    phase_deg[j] = std::arg(z) * (180.0 / pi);
+  }
+  return SDD_OK;
+}
+
 sdd_status sdd_solve_multi_freq(sdd_ctx_t ctx, const sdd_request *req, uint32_t n_freq, const double *freqs,
                                 const double *const *g_tables, sdd_result *res) {
   if (!ctx || !req) return fail(SDD_E_INVALID, "NULL argument");
@@ -1659,6 +1685,7 @@ struct sdd_batch {
   unsigned long long *h_done = nullptr;    // pinned, one per request (group order)
   uint64_t total_nodes = 0;
   hipStream_t cap = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};   // around each replay, on the context's stream
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -1669,6 +1696,8 @@ static void batch_free(sdd_batch *b) {
   if (b->exec) hipGraphExecDestroy(b->exec);
   if (b->graph) hipGraphDestroy(b->graph);
   if (b->cap) hipStreamDestroy(b->cap);
+  for (auto &e : b->ev)
+    if (e) hipEventDestroy(e);
   if (b->h_out) hipHostFree(b->h_out);
   if (b->h_done) hipHostFree(b->h_done);
   for (auto &g : b->groups) {
@@ -1777,18 +1806,18 @@ sdd_status sdd_batch_create(sdd_ctx_t ctx, uint32_t n, const sdd_request *reqs, 
   // capture: counter reset (a kernel, not a memset), walks, reduction, copies
   if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess)
     return bail(fail(SDD_E_DEVICE, "capture stream"));
+  if (hipEventCreate(&b->ev[0]) != hipSuccess || hipEventCreate(&b->ev[1]) != hipSuccess)
+    return bail(fail(SDD_E_DEVICE, "batch events"));
   hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed);
   for (auto &g : b->groups)
     if (e == hipSuccess)
       e = launch_reset(reinterpret_cast<uint32_t *>(g.d_ctr), reinterpret_cast<unsigned long long *>(g.d_done),
                        (uint32_t)g.P.size(), b->cap);
-  if (e == hipSuccess) e = hipEventRecord(ctx->ev[0], b->cap);
   for (auto &g : b->groups)
     if (e == hipSuccess)
       e = launch_walk_persist(g.prec, g.sig, reinterpret_cast<const DevReq *>(g.d_reqs), (uint32_t)g.P.size(),
                               reinterpret_cast<const uint32_t *>(g.d_ws), 0u, refill_mask(ctx), g.blocks, g.threads,
                               b->cap);
-  if (e == hipSuccess) e = hipEventRecord(ctx->ev[1], b->cap);
   if (e == hipSuccess) e = launch_reduce(reinterpret_cast<const NodeJob *>(b->d_jobs), (uint32_t)b->total_nodes, b->cap);
   if (e == hipSuccess && b->total_nodes)
     e = hipMemcpyAsync(b->h_out, b->d_out, b->total_nodes * sizeof(NodeOut), hipMemcpyDeviceToHost, b->cap);
@@ -1812,11 +1841,19 @@ sdd_status sdd_batch_run(sdd_batch_t b, sdd_result *res) {
   sdd_ctx *ctx = b->ctx;
   ExecGuard ex(ctx);
   HIP_TRY(hipSetDevice(ctx->device));
+  // the replay is timed as a whole (counter reset, walks, reduction, result
+  // copies); the walks are all but a fraction of a percent of it
+  HIP_TRY(hipEventRecord(b->ev[0], ctx->stream));
   HIP_TRY(hipGraphLaunch(b->exec, ctx->stream));
+  HIP_TRY(hipEventRecord(b->ev[1], ctx->stream));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   float ms = 0.f;
-  if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]) == hipSuccess) ctx->stats.last_walk_ms = ms;
+  if (hipEventElapsedTime(&ms, b->ev[0], b->ev[1]) == hipSuccess) ctx->stats.last_walk_ms = ms;
   ctx->stats.launches += b->groups.size();
+  if (!b->groups.empty()) {
+    ctx->stats.last_blocks = b->groups.back().blocks;
+    ctx->stats.last_threads = b->groups.back().threads;
+  }
   uint64_t row = 0, steps = 0, paths = 0;
   for (uint32_t i = 0; i < n; ++i) {
     const Prepared &P = *b->Ps[i];

@@ -88,6 +88,9 @@ _PROTOS = [
     ("sdd_solve", C.c_int, [C.c_void_p, C.POINTER(sdd_request), C.POINTER(sdd_result)]),
     ("sdd_solve_batch", C.c_int, [C.c_void_p, C.c_uint32, C.POINTER(sdd_request), C.POINTER(sdd_result)]),
     ("sdd_solve_plain", C.c_int, [C.c_void_p, C.POINTER(sdd_request), C.POINTER(sdd_result)]),
+    ("sdd_mt_te_response", C.c_int, [C.c_uint32, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double), C.c_double, C.c_double, C.c_double,
+                                     C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     ("sdd_solve_multi_freq", C.c_int, [C.c_void_p, C.POINTER(sdd_request), C.c_uint32, C.POINTER(C.c_double),
                                        C.POINTER(C.POINTER(C.c_double)), C.POINTER(sdd_result)]),
     ("sdd_submit", C.c_int, [C.c_void_p, C.POINTER(sdd_request), C.POINTER(sdd_result), C.POINTER(C.c_uint64)]),
@@ -200,6 +203,21 @@ class _Res:
         if self.records is not None:
             d["records"] = self.records
         return d
+
+
+def mt_te_response(e_minus, e_mid, e_plus, h: float, length_unit_m: float, freq_hz: float):
+    """TE apparent resistivity (ohm m) and phase (degrees) per site from the
+    complex field at z - h, z, z + h (sdd_mt_te_response)."""
+    arrs = [np.ascontiguousarray(np.stack([np.asarray(e).real, np.asarray(e).imag], axis=-1), dtype=np.float64)
+            for e in (e_minus, e_mid, e_plus)]
+    n = arrs[0].shape[0]
+    if any(a.shape != (n, 2) for a in arrs):
+        raise ValueError("three arrays of the same length")
+    rho = np.zeros(max(n, 1))
+    phi = np.zeros(max(n, 1))
+    _check(lib().sdd_mt_te_response(n, *[_ptr(a, C.c_double) for a in arrs], h, length_unit_m, freq_hz,
+                                    _ptr(rho, C.c_double), _ptr(phi, C.c_double)))
+    return rho[:n], phi[:n]
 
 
 class Context:

@@ -339,6 +339,38 @@ def block_in_half_space(freq_hz: float, paths: int = 32768, dt: float = 4e-4, M:
                    name=f"block_f{freq_hz:g}")
 
 
+# COMMEMI 2D-1 geometry of Sec. 4.3, in kilometres: a 2 S/m block 1 km wide
+# and 2 km tall, its top 0.25 km below the surface, in a 0.01 S/m half-space
+# under air; response sites on the surface.
+COMMEMI_SITES_KM = (0.0, 0.5, 1.0, 2.0, 4.0)
+COMMEMI_WALLS = (-10.0, 10.0, -5.0, 10.0)
+
+
+def commemi_te_points(freq_hz: float = 10.0, paths: int = 65536, h: float = 0.01, dt: float = 1e-4,
+                      sites=COMMEMI_SITES_KM, walls=COMMEMI_WALLS, M: int = 16384, seed: int = 0,
+                      precision: int = FP32_MIXED, block: bool = True) -> List[Problem]:
+    """Three problems whose node j is site j at depth -h, 0 and +h (z down):
+    the field there gives the TE response of the site by a centred
+    difference.  The three share seed, stream and node order, so the three
+    points of a site walk on the same random numbers.  block=False gives the
+    plain half-space (apparent resistivity 100 ohm m, phase 45 degrees)."""
+    regions = [Region(HALF_Z_LT, (0.0,), 0.0)]
+    if block:
+        regions.append(Region(BOX, (-0.5, 0.5, 0.25, 2.25), 2.0))
+    g = column_tables(regions, 0.01, walls, freq_hz, 1000.0, 0.0, M)
+    ys = np.asarray(sites, dtype=np.float64)
+    out = []
+    for dz, tag in ((-h, "minus"), (0.0, "mid"), (h, "plus")):
+        nodes = np.stack([ys, np.full(ys.size, dz)], axis=1)
+        n = nodes.shape[0]
+        out.append(Problem(*walls, regions=regions, sigma_background=0.01, length_unit_m=1000.0,
+                           freq_hz=freq_hz, alpha_direct=0.0, g=g, nodes=nodes,
+                           path_begin=np.zeros(n, np.uint32), path_count=np.full(n, paths, np.uint32),
+                           dt=dt, seed=seed, stream=0, precision=precision,
+                           name=f"commemi_te_{tag}" if block else f"halfspace_te_{tag}"))
+    return out
+
+
 TRIANGLE_FREQS = tuple(float(x) for x in np.logspace(-2, 2, 8))
 
 

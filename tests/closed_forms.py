@@ -64,3 +64,23 @@ def zscores(mean, exact, se_re, se_im, bias=0.0):
     zr = np.maximum(np.abs(d.real) - bias, 0.0) / np.asarray(se_re)
     zi = np.maximum(np.abs(d.imag) - bias, 0.0) / np.asarray(se_im)
     return np.concatenate([np.atleast_1d(zr), np.atleast_1d(zi)])
+
+
+MU0 = 4e-7 * np.pi
+
+
+def halfspace_field(sigma, freq_hz, z_m):
+    """The TE field of a uniform half-space, exp(-k z), k = sqrt(i omega mu0
+    sigma) (principal root), z in metres positive down."""
+    k = np.sqrt(1j * 2.0 * np.pi * freq_hz * MU0 * sigma)
+    return np.exp(-k * np.asarray(z_m, dtype=np.float64))
+
+
+def mt_te_response(e_minus, e_mid, e_plus, h, length_unit_m, freq_hz):
+    """Eqs. 2-3 of Sec. 2.1 with a centred difference: H = -(1/(i omega mu0))
+    dE/dz, rho_a = |E/H|^2 / (omega mu0), phi = arg(E/H) in degrees."""
+    w = 2.0 * np.pi * freq_hz
+    dedz = (np.asarray(e_plus) - np.asarray(e_minus)) / (2.0 * h * length_unit_m)
+    hx = -dedz / (1j * w * MU0)
+    z = np.asarray(e_mid) / hx
+    return np.abs(z) ** 2 / (w * MU0), np.degrees(np.angle(z))
