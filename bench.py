@@ -13,6 +13,8 @@ Legs besides the timed workload (each bounded, each can be switched off):
             blocking solves in arrival order;
   --mt      pointwise TE apparent resistivity and phase at the COMMEMI 2D-1
             sites (Table 2 of the paper as context);
+  --sdd     domain decomposition of the quarter-space: walks on the
+            interfaces, RBF-FD in the sub-domains, surface responses;
   cpu       the FP64 CPU oracle on a bounded sample of the same workload
             (rank 0 only), as a baseline.
 """
@@ -189,6 +191,48 @@ def mt_leg(ctx, seeds: int = 4, paths: int = 1 << 20, h: float = 0.05, dt: float
             "walk_steps": steps, "wall_s": wall, "walk_steps_per_s": steps / wall}
 
 
+def sdd_leg(ctx, paths: int = 16384):
+    """Stochastic domain decomposition of the quarter-space workload (the
+    paper's Sec. 4.2 experiment in its structure): FP32 walks at every grid
+    node on the interfaces (the surface and the vertical contact), RBF-FD in
+    the air and the two ground quarters on a graded grid (cells from 0.02 to
+    0.2 skin depths, eps h = 0.05), and the TE apparent resistivity and phase
+    along the surface from the field one cell above and below it."""
+    from paper_1603_09311_amd import decompose as D
+    from paper_1603_09311_amd import sdd as S
+    from paper_1603_09311_amd import workloads as W
+    y = D.graded_axis(-8.0, 8.0, 0.02, 1.08, 0.2)
+    z = D.graded_axis(-6.0, 8.0, 0.02, 1.08, 0.2)
+    iz0, iy0 = int(np.argmin(abs(z))), int(np.argmin(abs(y)))
+    p = W.quarter_space(paths=paths, precision=W.FP32_MIXED, M=16384)
+    al = p.alphas()
+    subs = [D.SubDomain(0, y.size - 1, 0, iz0, float(al[0])), D.SubDomain(0, iy0, iz0, z.size - 1, float(al[1])),
+            D.SubDomain(iy0, y.size - 1, iz0, z.size - 1, float(al[2]))]
+    outer = W.column_field(p.regions, p.sigma_background, y, z, z[0], p.freq_hz, p.length_unit_m,
+                           boundary_only=True)
+    t0 = time.perf_counter()
+    ij = D.interface_nodes(y.size, z.size, subs)
+    nodes = np.stack([y[ij[:, 0]], z[ij[:, 1]]], axis=1)
+    q = p.replace(nodes=nodes, path_begin=np.zeros(len(nodes), np.uint32),
+                  path_count=np.full(len(nodes), paths, np.uint32))
+    r = ctx.solve(q)
+    t1 = time.perf_counter()
+    F = outer.copy()
+    F[ij[:, 1], ij[:, 0]] = r["mean"]
+    F = D.solve_subdomains(y, z, subs, F, -0.05)
+    t2 = time.perf_counter()
+    h = z[iz0 + 1] - z[iz0]
+    rho, phi = S.mt_te_response(F[iz0 - 1], F[iz0], F[iz0 + 1], h, p.length_unit_m, p.freq_hz)
+    sites = [-6.0, -3.0, -1.0, -0.5, 0.0, 0.5, 1.0, 3.0, 6.0]
+    idx = [int(np.argmin(abs(y - s))) for s in sites]
+    return {"grid": [int(y.size), int(z.size)], "interface_nodes": int(len(ij)), "paths_per_node": paths,
+            "walk_steps": float(r["steps"].sum()), "walk_s": t1 - t0, "rbffd_s": t2 - t1,
+            "max_interface_se": float(r["se"].max()),
+            "surface_sites_skin_depths": [float(y[i]) for i in idx],
+            "rho_a_te": [round(float(rho[i]), 3) for i in idx], "phase_te_deg": [round(float(phi[i]), 3) for i in idx],
+            "half_space_limits": {"left_rho_a": 100.0, "right_rho_a": 10.0, "phase_deg": 45.0}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -200,6 +244,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-mt", action="store_true", help="skip the pointwise MT response leg")
+    ap.add_argument("--no-sdd", action="store_true", help="skip the domain decomposition leg")
     ap.add_argument("--served-requests", type=int, default=24)
     ap.add_argument("--served-rate", type=float, default=8.0)
     args = ap.parse_args()
@@ -299,6 +344,10 @@ def main():
         log(f"served: {out['served']}")
         out["p50_ms"] = out["served"]["p50_ms"]
         out["p99_ms"] = out["served"]["p99_ms"]
+
+    if not args.no_sdd:
+        out["domain_decomposition"] = sdd_leg(ctx)
+        log(f"domain decomposition: {out['domain_decomposition']}")
 
     if not args.no_mt:
         out["mt_response"] = mt_leg(ctx)

@@ -282,6 +282,36 @@ sdd_status sdd_solve_multi_freq(sdd_ctx_t ctx, const sdd_request *req, uint32_t 
 sdd_status sdd_mt_te_response(uint32_t n, const double *e_minus, const double *e_mid, const double *e_plus, double h,
                               double length_unit_m, double freq_hz, double *rho_a, double *phase_deg);
 
+/* Sub-domain solver (Sec. 3.2): RBF-FD on a rectangular grid of ny x nz
+ * nodes (y[0..ny), z[0..nz) strictly increasing, model length units) with the
+ * multiquadric phi(r) = sqrt(1 + (eps r)^2) and, at every interior node, the
+ * 9-node stencil of the node and its 8 grid neighbours; separate weights for
+ * d2/dy2 and d2/dz2 (exact on phi centred at each stencil node).  Solves
+ * Laplace E = i alpha E (the TE equation in model units, alpha = omega mu0
+ * sigma L^2 of the sub-domain) for the interior values, the boundary values
+ * (the grid's first and last rows and columns: walk results on interfaces,
+ * Dirichlet data on the outer boundary) given.
+ *   field  ny * nz complex values, (re, im) interleaved, y fastest:
+ *          node (i, j) at field[2 (j ny + i)]; boundary entries are read,
+ *          interior entries are written.  Host memory, caller-owned.
+ *   eps    > 0: the shape parameter, in inverse model length units, at every
+ *          node (the paper's choice, 1/2000 per metre for 50-300 m cells);
+ *          < 0: eps h = |eps| at every node, h the largest grid spacing next
+ *          to it (for graded grids).  The stencil systems are solved in
+ *          extended precision; eps h below about 0.01 is ill-conditioned.
+ * Host only.  SDD_E_INVALID for a grid smaller than 3 x 3 or above 2^24
+ * interior nodes, non-increasing coordinates, a non-finite boundary value,
+ * alpha < 0, eps = 0 or not finite, or a singular system. */
+sdd_status sdd_rbffd_solve(uint32_t ny, uint32_t nz, const double *y, const double *z, double alpha, double eps,
+                           double *field);
+
+/* The stencil weights sdd_rbffd_solve uses: for interior node (i, j) (row
+ * r = (j - 1)(ny - 2) + (i - 1)) the 9 weights of d2/dy2 and of d2/dz2 at
+ * w[9 r + k], k = 3 (dj + 1) + (di + 1) for the neighbour (i + di, j + dj).
+ * Host only; errors as above. */
+sdd_status sdd_rbffd_weights(uint32_t ny, uint32_t nz, const double *y, const double *z, double eps, double *w_yy,
+                             double *w_zz);
+
 /* Bytes of workspace a request needs (tables, nodes, tiles, records). */
 sdd_status sdd_request_footprint(sdd_ctx_t ctx, const sdd_request *req, uint64_t *bytes);
 

@@ -56,6 +56,9 @@ static sdd_status fail(sdd_status st, const char *fmt, ...) {
   return st;
 }
 
+// for the host sub-domain solver (its own translation unit)
+sdd_status sdd_rbffd_fail(sdd_status st, const char *msg) { return fail(st, "%s", msg); }
+
 #define HIP_TRY(expr)                                                                         \
   do {                                                                                        \
     hipError_t e_ = (expr);                                                                   \

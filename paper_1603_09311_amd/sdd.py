@@ -91,6 +91,10 @@ _PROTOS = [
     ("sdd_mt_te_response", C.c_int, [C.c_uint32, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                      C.POINTER(C.c_double), C.c_double, C.c_double, C.c_double,
                                      C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    ("sdd_rbffd_solve", C.c_int, [C.c_uint32, C.c_uint32, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                  C.c_double, C.c_double, C.POINTER(C.c_double)]),
+    ("sdd_rbffd_weights", C.c_int, [C.c_uint32, C.c_uint32, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                    C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     ("sdd_solve_multi_freq", C.c_int, [C.c_void_p, C.POINTER(sdd_request), C.c_uint32, C.POINTER(C.c_double),
                                        C.POINTER(C.POINTER(C.c_double)), C.POINTER(sdd_result)]),
     ("sdd_submit", C.c_int, [C.c_void_p, C.POINTER(sdd_request), C.POINTER(sdd_result), C.POINTER(C.c_uint64)]),
@@ -218,6 +222,33 @@ def mt_te_response(e_minus, e_mid, e_plus, h: float, length_unit_m: float, freq_
     _check(lib().sdd_mt_te_response(n, *[_ptr(a, C.c_double) for a in arrs], h, length_unit_m, freq_hz,
                                     _ptr(rho, C.c_double), _ptr(phi, C.c_double)))
     return rho[:n], phi[:n]
+
+
+def rbffd_solve(y, z, alpha: float, eps: float, field):
+    """RBF-FD sub-domain solve (sdd_rbffd_solve): `field` is a complex
+    (nz, ny) array whose boundary rows and columns hold the Dirichlet values;
+    returns a copy with the interior solved."""
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    f = np.asarray(field, dtype=np.complex128)
+    if f.shape != (z.size, y.size):
+        raise ValueError(f"field of shape {f.shape}, the grid is {(z.size, y.size)}")
+    buf = np.ascontiguousarray(np.stack([f.real, f.imag], axis=-1), dtype=np.float64)
+    _check(lib().sdd_rbffd_solve(y.size, z.size, _ptr(y, C.c_double), _ptr(z, C.c_double), alpha, eps,
+                                 _ptr(buf, C.c_double)))
+    return buf[..., 0] + 1j * buf[..., 1]
+
+
+def rbffd_weights(y, z, eps: float):
+    """Stencil weights (sdd_rbffd_weights): two ((nz-2)(ny-2), 9) arrays."""
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    n = max(0, (y.size - 2) * (z.size - 2))
+    wy = np.zeros((max(n, 1), 9))
+    wz = np.zeros((max(n, 1), 9))
+    _check(lib().sdd_rbffd_weights(y.size, z.size, _ptr(y, C.c_double), _ptr(z, C.c_double), eps,
+                                   _ptr(wy, C.c_double), _ptr(wz, C.c_double)))
+    return wy[:n], wz[:n]
 
 
 class Context:

@@ -253,6 +253,26 @@ def column_tables(regions: Sequence[Region], sigma_bg: float, walls: Tuple[float
     return g
 
 
+def column_field(regions: Sequence[Region], sigma_bg: float, y: np.ndarray, z: np.ndarray, z_top: float,
+                 freq_hz: float, L: float, alpha_direct: float = 0.0, boundary_only: bool = False) -> np.ndarray:
+    """The layered 1-D solution of each vertical column y[i] at depths z
+    (normalised to 1 at z_top), as a complex (nz, ny) array; with
+    boundary_only, only the first and last rows and columns are filled (the
+    outer Dirichlet values of a grid) and the rest is zero."""
+    y = np.asarray(y, dtype=np.float64)
+    z = np.asarray(z, dtype=np.float64)
+    F = np.zeros((z.size, y.size), dtype=np.complex128)
+    cols = range(y.size) if not boundary_only else sorted({0, y.size - 1} | set(range(y.size)))
+    for i in cols:
+        tops, sig = column_layers(regions, sigma_bg, float(y[i]), z_top)
+        col = layered_1d(tops, _alpha_of(sig, freq_hz, L, alpha_direct), z)
+        if boundary_only and 0 < i < y.size - 1:
+            F[0, i], F[-1, i] = col[0], col[-1]
+        else:
+            F[:, i] = col
+    return F
+
+
 def wall_coords(y_lo: float, y_hi: float, z_lo: float, z_hi: float, M: int):
     """Sample coordinates of the tables: (points (4, M+1, 2))."""
     ys = y_lo + np.arange(M + 1) * ((y_hi - y_lo) / M)
@@ -422,7 +442,8 @@ def triangle_request(m: int, precision: int = FP32_MIXED, dt: float = 4e-4, M: i
 
 
 def layered_check(alpha_ground: float = 2.0, walls=(-2.0, 2.0, -1.0, 3.0), M: int = 4096,
-                  n_nodes: int = 8, paths: int = 4096, dt: float = 4e-4, seed: int = 7) -> Problem:
+                  n_nodes: int = 8, paths: int = 4096, dt: float = 4e-4, seed: int = 7,
+                  precision: int = FP64) -> Problem:
     """Air over a uniform half-space (alpha_ground), g from the same 1-D
     solution on all four walls, so the 2-D solution is the 1-D one."""
     regions = [Region(HALF_Z_LT, (0.0,), 0.0)]
@@ -433,7 +454,7 @@ def layered_check(alpha_ground: float = 2.0, walls=(-2.0, 2.0, -1.0, 3.0), M: in
                    freq_hz=0.0, alpha_direct=alpha_ground, g=g, nodes=nodes,
                    path_begin=np.zeros(n_nodes, np.uint32),
                    path_count=np.full(n_nodes, paths, np.uint32), dt=dt, seed=seed,
-                   name="layered_check")
+                   precision=precision, name="layered_check")
 
 
 def served_trace(n_requests: int, rate_hz: float, seed: int = 1, paths_cap: int = 1 << 20,

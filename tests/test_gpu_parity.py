@@ -465,3 +465,28 @@ def test_mt_response_half_space_physics(ctx):
     rho, phi = sdd.mt_te_response(*[g["mean"] for g in got], 0.05, 1000.0, 10.0)
     log(f"half-space rho_a {rho} phase {phi}")
     assert np.all(np.abs(rho - 100.0) < 12.0) and np.all(np.abs(phi - 45.0) < 2.5)
+
+
+def test_domain_decomposition_layered_model(ctx):
+    """Stochastic domain decomposition end to end: FP32 walks at the 138
+    interface nodes of air over a uniform half-space cut into three
+    sub-domains, then RBF-FD in each; the field everywhere matches the exact
+    1-D solution within the discretisation error (1.7e-4 at this grid) plus
+    five standard errors of the interface walks."""
+    from paper_1603_09311_amd import decompose as D
+    walls = (-2.0, 2.0, -1.0, 3.0)
+    h = 0.05
+    y = np.arange(walls[0], walls[1] + 1e-9, h)
+    z = np.arange(walls[2], walls[3] + 1e-9, h)
+    iz0, iy0 = int(np.argmin(abs(z))), int(np.argmin(abs(y)))
+    subs = [D.SubDomain(0, y.size - 1, 0, iz0, 0.0), D.SubDomain(0, iy0, iz0, z.size - 1, 2.0),
+            D.SubDomain(iy0, y.size - 1, iz0, z.size - 1, 2.0)]
+    p = W.layered_check(alpha_ground=2.0, walls=walls, paths=16384, precision=W.FP32_MIXED)
+    regions = [W.Region(W.HALF_Z_LT, (0.0,), 0.0)]
+    ex = W.column_field(regions, 1.0, y, z, walls[2], 0.0, 1.0, alpha_direct=2.0)
+    outer = W.column_field(regions, 1.0, y, z, walls[2], 0.0, 1.0, alpha_direct=2.0, boundary_only=True)
+    F, r = D.decompose(ctx, p, y, z, subs, outer, 1.0)
+    assert r["mean"].size == 138
+    err = np.abs(F - ex).max()
+    log(f"decomposition: max error {err:.3e}, max interface SE {r['se'].max():.3e}")
+    assert err <= 1.7e-4 + 5.0 * r["se"].max()

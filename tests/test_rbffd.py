@@ -1,0 +1,170 @@
+"""RBF-FD sub-domain solver (Sec. 3.2): the numpy oracle pinned to exact
+solutions and to polynomial consistency; the library's host solver against
+the oracle where double precision resolves the weights, and against a
+60-digit reference where it does not.  CPU only."""
+from decimal import Decimal, getcontext
+
+import numpy as np
+import pytest
+
+import closed_forms as CF
+from oracle import rbffd as R
+from paper_1603_09311_amd import sdd
+from paper_1603_09311_amd import workloads as W
+
+
+def _grid(n, lo=0.0, hi=1.0):
+    return np.linspace(lo, hi, n)
+
+
+# ---------------------------------------------------------------- oracle pins
+
+def test_oracle_weights_consistent_on_polynomials():
+    """Applied to 1, y, z, y^2, y z, z^2 on an uneven stencil the weights give
+    the exact second derivatives up to a shape-parameter error that falls
+    like eps^2 (the flat limit reproduces quadratics)."""
+    y = np.array([0.0, 0.11, 0.2]); z = np.array([1.0, 1.09, 1.21])
+    P = R.stencil(y, z, 1, 1)
+    f = [np.ones(9), P[:, 0], P[:, 1], P[:, 0] ** 2, P[:, 0] * P[:, 1], P[:, 1] ** 2]
+    d_yy = [0.0, 0.0, 0.0, 2.0, 0.0, 0.0]
+    d_zz = [0.0, 0.0, 0.0, 0.0, 0.0, 2.0]
+    errs = []
+    for eps in (1.0, 0.5, 0.25):
+        wy, wz = R.weights(y, z, eps)
+        errs.append(max(max(abs(wy[0] @ v - a), abs(wz[0] @ v - b)) for v, a, b in zip(f, d_yy, d_zz)))
+    assert errs[0] < 0.1 and errs[1] < errs[0] / 3 and errs[2] < errs[1] / 3
+
+
+def _convergence(solver, exact_fn, alpha, eps=1.0, sizes=(11, 21, 41)):
+    """Errors on three grids of the unit square (shifted to z in [0.5, 1.5])
+    with a fixed shape parameter, as in Sec. 3.2 (eps h = 0.1 to 0.025)."""
+    errs = []
+    for n in sizes:
+        y = _grid(n); z = _grid(n, 0.5, 1.5)
+        Y, Z = np.meshgrid(y, z)
+        ex = exact_fn(Y, Z)
+        F = np.zeros_like(ex)
+        F[0, :], F[-1, :], F[:, 0], F[:, -1] = ex[0, :], ex[-1, :], ex[:, 0], ex[:, -1]
+        got = solver(y, z, alpha, eps, F)
+        errs.append(np.abs(got - ex).max())
+    return errs
+
+
+@pytest.mark.parametrize("solver", [R.solve, sdd.rbffd_solve], ids=["oracle", "library"])
+def test_plane_wave_second_order(solver):
+    """E = exp(-sqrt(i alpha) z) solves Laplace E = i alpha E exactly; the
+    error falls by about 4 per halving of h."""
+    alpha = 20.0
+    errs = _convergence(solver, lambda Y, Z: CF.plane_wave(alpha, Z), alpha)
+    assert errs[0] < 1e-2
+    assert errs[1] < errs[0] / 3 and errs[2] < errs[1] / 3
+
+
+@pytest.mark.parametrize("solver", [R.solve, sdd.rbffd_solve], ids=["oracle", "library"])
+def test_harmonic_and_cosh_second_order(solver):
+    """Laplace: e^y cos z (alpha = 0); and the equal-kappa analytic model
+    (z + 1) cosh(sqrt(i alpha) y) of Sec. 4.1."""
+    errs = _convergence(solver, lambda Y, Z: np.exp(Y) * np.cos(Z) + 0j, 0.0)
+    assert errs[1] < errs[0] / 3 and errs[2] < errs[1] / 3
+    errs = _convergence(solver, lambda Y, Z: (Z + 1.0) * np.cosh(np.sqrt(10j) * Y), 10.0)
+    assert errs[1] < errs[0] / 3 and errs[2] < errs[1] / 3
+
+
+@pytest.mark.parametrize("solver", [R.solve, sdd.rbffd_solve], ids=["oracle", "library"])
+def test_layered_1d_reproduced(solver):
+    """A sub-domain inside a uniform layer of the quarter-space ground, with
+    the layered 1-D solution on its boundary: the solution everywhere inside
+    (the pin the survey names)."""
+    regions = [W.Region(W.HALF_Z_LT, (0.0,), 0.0)]
+    tops, sig = W.column_layers(regions, 0.01, 0.0, -6.0)
+    al = W._alpha_of(np.asarray(sig), 1.0, W.DELTA1, 0.0)
+    y = _grid(31, -1.0, 1.0); z = _grid(31, 0.0, 2.0)
+    ex = np.tile(W.layered_1d(np.asarray(tops), al, z)[:, None], (1, y.size))
+    F = np.zeros_like(ex)
+    F[0, :], F[-1, :], F[:, 0], F[:, -1] = ex[0, :], ex[-1, :], ex[:, 0], ex[:, -1]
+    got = solver(y, z, float(al[-1]), 1.0, F)
+    assert np.abs(got - ex).max() < 1e-3 * np.abs(ex).max()
+
+
+# ------------------------------------------------------- library vs references
+
+def test_library_matches_oracle_where_double_resolves_weights():
+    rng = np.random.default_rng(3)
+    y = np.cumsum(rng.uniform(0.5, 1.5, 14)); z = np.cumsum(rng.uniform(0.5, 1.5, 11))
+    for eps in (0.1, 0.3, 1.0):
+        wy, wz = R.weights(y, z, eps)
+        gy, gz = sdd.rbffd_weights(y, z, eps)
+        assert np.abs(gy - wy).max() <= 1e-6 * np.abs(wy).max()
+        assert np.abs(gz - wz).max() <= 1e-6 * np.abs(wz).max()
+        F = np.zeros((z.size, y.size), complex)
+        F[0, :] = rng.normal(size=y.size) + 1j * rng.normal(size=y.size)
+        F[-1, :] = rng.normal(size=y.size)
+        F[:, 0] = 1j
+        F[:, -1] = 2.0
+        a = R.solve(y, z, 0.7, eps, F)
+        b = sdd.rbffd_solve(y, z, 0.7, eps, F)
+        assert np.abs(a - b).max() <= 1e-6 * np.abs(a).max()
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[:, -1], b[:, -1])
+
+
+def _decimal_weights(P, x0, eps, digits=60):
+    """The 9x9 RBF system solved in 60-digit decimal arithmetic."""
+    getcontext().prec = digits
+    e2 = Decimal(repr(eps)) ** 2
+    Pd = [(Decimal(repr(float(a))), Decimal(repr(float(b)))) for a, b in P]
+    yd, zd = Decimal(repr(float(x0[0]))), Decimal(repr(float(x0[1])))
+
+    def phi(r2):
+        return (1 + e2 * r2).sqrt()
+
+    def phi_yy(dy, dz):
+        q = 1 + e2 * (dy * dy + dz * dz)
+        return e2 / q.sqrt() - e2 * e2 * dy * dy / (q * q.sqrt())
+
+    A = [[phi((a[0] - b[0]) ** 2 + (a[1] - b[1]) ** 2) for b in Pd] for a in Pd]
+    rhs = [[phi_yy(yd - a[0], zd - a[1]), phi_yy(zd - a[1], yd - a[0])] for a in Pd]
+    n = 9
+    for c in range(n):
+        p = max(range(c, n), key=lambda r: abs(A[r][c]))
+        A[c], A[p] = A[p], A[c]
+        rhs[c], rhs[p] = rhs[p], rhs[c]
+        for r in range(c + 1, n):
+            f = A[r][c] / A[c][c]
+            for k in range(c, n):
+                A[r][k] -= f * A[c][k]
+            for s in range(2):
+                rhs[r][s] -= f * rhs[c][s]
+    w = [[Decimal(0)] * 2 for _ in range(n)]
+    for r in range(n - 1, -1, -1):
+        for s in range(2):
+            v = rhs[r][s] - sum(A[r][k] * w[k][s] for k in range(r + 1, n))
+            w[r][s] = v / A[r][r]
+    return np.array([[float(v) for v in row] for row in w])
+
+
+@pytest.mark.parametrize("eps_h", [0.02, 0.05])
+def test_library_near_flat_weights_against_60_digits(eps_h):
+    """The shape parameter of Sec. 3.2 (1/2000 per metre on 50-300 m cells)
+    makes eps h ~ 0.02-0.15: there the 9x9 systems have condition numbers near
+    1e13 and the library's extended-precision solve must still give the
+    weights to 1e-5 (double precision gives about 1e-2)."""
+    h = 1.0
+    y = np.array([0.0, h, 2.1 * h]); z = np.array([0.0, 0.9 * h, 2.0 * h])
+    eps = eps_h / h
+    ref = _decimal_weights(R.stencil(y, z, 1, 1), (y[1], z[1]), eps)
+    gy, gz = sdd.rbffd_weights(y, z, eps)
+    assert np.abs(gy[0] - ref[:, 0]).max() <= 1e-5 * np.abs(ref[:, 0]).max()
+    assert np.abs(gz[0] - ref[:, 1]).max() <= 1e-5 * np.abs(ref[:, 1]).max()
+
+
+def test_library_rejects_bad_grids():
+    y = np.array([0.0, 1.0, 2.0]); z = np.array([0.0, 1.0, 2.0])
+    F = np.zeros((3, 3), complex)
+    for args in ((y[:2], z, 1.0, 1.0, F[:, :2]), (np.array([0.0, 2.0, 1.0]), z, 1.0, 1.0, F),
+                 (y, z, -1.0, 1.0, F), (y, z, 1.0, 0.0, F)):
+        with pytest.raises(sdd.SddError) as ex:
+            sdd.rbffd_solve(*args)
+        assert ex.value.status == sdd.SDD_E_INVALID
+    G = F.copy(); G[0, 0] = np.nan
+    with pytest.raises(sdd.SddError):
+        sdd.rbffd_solve(y, z, 1.0, 1.0, G)
