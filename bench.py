@@ -109,6 +109,57 @@ def cpu_baseline(p, budget_s: float = 15.0):
             "sample": f"{len(idx)} of {p.n_nodes} nodes x {paths} paths ({steps:.3e} steps, {dt:.1f} s), FP64"}
 
 
+def cpu_baseline_kappa(kp, budget_s: float = 5.0):
+    """The oracle's discontinuous-kappa walk on a bounded sample of the
+    kappa workload (every 150th node, paths sized to about budget_s)."""
+    from oracle import oracle as O
+    O.build(force=False)
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    idx = np.arange(0, kp.n_nodes, 150)
+    sub = kp.replace(nodes=kp.nodes[idx], path_begin=kp.path_begin[idx], path_count=kp.path_count[idx])
+    t0 = time.perf_counter()
+    O.ksolve(sub.with_paths(16), threads=threads)
+    t_cal = time.perf_counter() - t0
+    paths = int(max(16, min(int(kp.path_count[0]), 16 * budget_s / max(t_cal, 1e-3))))
+    t0 = time.perf_counter()
+    r, _ = O.ksolve(sub.with_paths(paths), threads=threads)
+    dt = time.perf_counter() - t0
+    steps = float(r["steps"].sum())
+    return {"value": steps / dt, "unit": "walk-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(idx)} of {kp.n_nodes} nodes x {paths} paths ({steps:.3e} steps, {dt:.1f} s), FP64"}
+
+
+def kappa_leg(ctx, n: int = 51, paths: int = 10000, dt: float = 1e-4, repeats: int = 3):
+    """The discontinuous-kappa walk (Secs. 2.2, 3.1) on the analytic test
+    model of Sec. 4.1 (kappa 1 | 10, lambda = 10 i) at every interior point
+    of the n x n mesh with `paths` paths each (the paper: 51 x 51, 10000),
+    FP64: walk kernel time and rate, and the error against the exact
+    solution next to the Monte-Carlo error."""
+    from paper_1603_09311_amd import workloads as W
+    kp = W.kappa_analytic_grid(n=n, paths=paths, dt=dt)
+    walls, kms = [], []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        r = ctx.solve_kappa(kp)
+        walls.append(time.perf_counter() - t0)
+        kms.append(ctx.stats()["last_walk_ms"])
+    steps = float(r["steps"].sum())
+    exact = W.kappa_model_field(kp.nodes[:, 0], kp.nodes[:, 1])
+    err = np.abs(r["mean"] - exact)
+    k_ms = float(np.median(kms))
+    i06 = int(np.argmin(np.hypot(kp.nodes[:, 0] - 0.6, kp.nodes[:, 1] - 0.6)))
+    st = ctx.stats()
+    return {"workload": kp.name, "nodes": kp.n_nodes, "paths_per_node": paths, "dt": dt,
+            "kappa": list(kp.kappa), "lambda": "10i", "walk_steps": steps, "walk_kernel_ms": k_ms,
+            "walk_steps_per_s": steps / (k_ms * 1e-3), "nodes_per_s": kp.n_nodes / (k_ms * 1e-3),
+            "solve_wall_s_from_host_buffers": float(np.median(walls)),
+            "launch": {"blocks": st["last_blocks"], "threads": st["last_threads"]},
+            "max_abs_error": float(err.max()), "median_error_over_se": float(np.median(err / r["se"])),
+            "error_at_0.6_0.6": [float(abs((r["mean"][i06] - exact[i06]).real)),
+                                 float(abs((r["mean"][i06] - exact[i06]).imag))],
+            "table1_error_at_0.6_0.6_N1e4": [0.0086, 0.0067], "_kp": kp}
+
+
 def served_leg(ctx, n_requests: int, rate_hz: float, paths: int):
     """A Poisson trace of mixed requests (unit square, quarter-space and block
     node subsets) through the served mode (continuous batching in time
@@ -245,6 +296,7 @@ def main():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-mt", action="store_true", help="skip the pointwise MT response leg")
     ap.add_argument("--no-sdd", action="store_true", help="skip the domain decomposition leg")
+    ap.add_argument("--no-kappa", action="store_true", help="skip the discontinuous-kappa leg")
     ap.add_argument("--served-requests", type=int, default=24)
     ap.add_argument("--served-rate", type=float, default=8.0)
     args = ap.parse_args()
@@ -353,10 +405,19 @@ def main():
         out["mt_response"] = mt_leg(ctx)
         log(f"mt response: {out['mt_response']}")
 
+    kp = None
+    if not args.no_kappa:
+        out["kappa_interface"] = kappa_leg(ctx)
+        kp = out["kappa_interface"].pop("_kp")
+        log(f"kappa interface: {out['kappa_interface']}")
+
     if not args.no_cpu:
         cb = cpu_baseline(p)
         out["cpu_baseline"] = cb
         log(f"cpu baseline: {cb}")
+        if kp is not None:
+            out["kappa_interface"]["cpu_oracle"] = cpu_baseline_kappa(kp)
+            log(f"kappa cpu oracle: {out['kappa_interface']['cpu_oracle']}")
     ctx.close()
     print(json.dumps(out), flush=True)
 

@@ -312,6 +312,55 @@ sdd_status sdd_rbffd_solve(uint32_t ny, uint32_t nz, const double *y, const doub
 sdd_status sdd_rbffd_weights(uint32_t ny, uint32_t nz, const double *y, const double *z, double eps, double *w_yy,
                              double *w_zz);
 
+/* Discontinuous kappa (Secs. 2.2 and 3.1): the walk for
+ *   (1/2) div(kappa grad u) - lambda u = 0 in Omega, u = g on its boundary
+ * (Eq. 9), kappa > 0 and lambda constant on each side of one vertical
+ * interface y = y_if (the configuration of Eqs. 10-12; with kappa = 2/sigma
+ * and lambda = i omega mu it is the TM mode, with kappa constant the TE mode
+ * in the form of Eq. 9).  FP64.  A step that reaches the interface resumes
+ * from a uniform point of a disc of radius h = sqrt(kappa_i dt), kappa_i of
+ * the side the step started on, that touches the interface from side i
+ * (probability kappa_i / (kappa_i + kappa_j), Eq. 12) or from side j; the
+ * step's time is split between the occupation times T_0, T_1 as in Sec. 3.1
+ * (shares summing to dt), and a path's value is
+ * g(exit point) exp(-(lambda_0 T_0 + lambda_1 T_1)).  A disc point outside
+ * Omega ends the walk at the nearest boundary point.  With equal kappa the
+ * proposal is kept and the step's time goes to the side of the proposal.
+ * Random numbers: Philox4x32-10 keyed by `seed`; step n of path p at node j
+ * takes its normals from counter (n/2, p, j, 4 stream) (words 0,1 for even
+ * n, 2,3 for odd n), its bridge and side uniforms from (n, p, j,
+ * 4 stream + 1) (outer bridge y, z: words 0, 1; interface bridge: word 2;
+ * side: word 3) and its disc point from (n, p, j, 4 stream + 2) (radius:
+ * word 0, angle: word 1). */
+typedef struct {
+    double y_lo, y_hi, z_lo, z_hi;  /* Omega; z_lo is the top wall */
+    double y_if;                    /* y_lo < y_if < y_hi */
+    double kappa[2];                /* side 0: y < y_if, side 1: y >= y_if; finite, > 0 */
+    double lambda_re[2];            /* finite, >= 0 */
+    double lambda_im[2];            /* finite */
+    const double *g_tables;         /* host: 4 walls x g_samples x (re, im), as in sdd_request */
+    uint32_t g_samples;             /* >= 2 */
+    uint32_t n_nodes;
+    const double *nodes_yz;         /* host: n_nodes x (y, z), strictly inside Omega */
+    const uint32_t *path_begin;     /* host, nullable: first path index per node (default 0) */
+    const uint32_t *path_count;     /* host, nullable: paths per node (default paths_uniform) */
+    uint32_t paths_uniform;
+    uint32_t max_steps;             /* steps before a path counts as unfinished; 0 = 2e9 */
+    double dt;                      /* 7 sqrt(max kappa dt) < half the shorter side */
+    uint64_t seed;
+    uint32_t stream;                /* < 2^30 */
+    uint32_t reserved;              /* 0 */
+} sdd_kappa_request;
+
+/* Solve a discontinuous-kappa request on the context's stream.  Results per
+ * node in `res` as for sdd_solve (path_records, when not NULL, receive every
+ * path's record: w = the path's value).  Inputs are host memory and are
+ * copied; the call returns when the results are on the host.
+ * Errors: SDD_E_INVALID (NULL pointers, a value outside the ranges above, a
+ * node not strictly inside Omega, a node with no paths or whose path range
+ * passes 2^32, more than 2^40 paths), SDD_E_NOMEM (workspace), SDD_E_DEVICE. */
+sdd_status sdd_solve_kappa(sdd_ctx_t ctx, const sdd_kappa_request *req, sdd_result *res);
+
 /* Bytes of workspace a request needs (tables, nodes, tiles, records). */
 sdd_status sdd_request_footprint(sdd_ctx_t ctx, const sdd_request *req, uint64_t *bytes);
 

@@ -78,6 +78,18 @@ NODE_DTYPE = np.dtype([("mean_re", "<f8"), ("mean_im", "<f8"), ("var_re", "<f8")
 assert PATH_DTYPE.itemsize == C.sizeof(Path_C)
 assert NODE_DTYPE.itemsize == C.sizeof(Node_C)
 
+class KProblem_C(C.Structure):
+    _fields_ = [
+        ("y_lo", C.c_double), ("y_hi", C.c_double), ("z_lo", C.c_double), ("z_hi", C.c_double),
+        ("y_if", C.c_double), ("kappa", C.c_double * 2),
+        ("lambda_re", C.c_double * 2), ("lambda_im", C.c_double * 2),
+        ("g_samples", C.c_int32), ("g", C.POINTER(C.c_double)),
+        ("n_nodes", C.c_int32), ("nodes", C.POINTER(C.c_double)),
+        ("path_begin", C.POINTER(C.c_uint32)), ("path_count", C.POINTER(C.c_uint32)),
+        ("dt", C.c_double), ("seed", C.c_uint64), ("stream", C.c_uint32), ("max_steps", C.c_uint32),
+    ]
+
+
 _lib = None
 
 
@@ -105,6 +117,12 @@ def lib():
         L.orc_box_muller.restype = None
         L.orc_node_stats.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(Node_C)]
         L.orc_node_stats.restype = C.c_int
+        L.orc_ksolve.argtypes = [C.POINTER(KProblem_C), C.c_int, C.c_void_p, C.c_void_p]
+        L.orc_ksolve.restype = C.c_int
+        L.orc_kwalk_path.argtypes = [C.POINTER(KProblem_C), C.c_int, C.c_uint32, C.POINTER(Path_C)]
+        L.orc_kwalk_path.restype = C.c_int
+        L.orc_kvalidate.argtypes = [C.POINTER(KProblem_C)]
+        L.orc_kvalidate.restype = C.c_int
         _lib = L
     return _lib
 
@@ -203,3 +221,71 @@ def node_stats(recs: np.ndarray):
     out = Node_C()
     lib().orc_node_stats(recs.ctypes.data, recs.size, C.byref(out))
     return {k: getattr(out, k) for k, _ in Node_C._fields_}
+
+
+class _KMarshalled:
+    """The discontinuous-kappa problem as the oracle's C struct."""
+
+    def __init__(self, p):
+        self.g = np.ascontiguousarray(np.stack([p.g.real, p.g.imag], axis=-1), dtype=np.float64).reshape(-1)
+        self.nodes = np.ascontiguousarray(p.nodes, dtype=np.float64).reshape(-1)
+        if self.nodes.size == 0:
+            self.nodes = np.zeros(2)
+        self.pb = np.ascontiguousarray(p.path_begin, dtype=np.uint32)
+        self.pc = np.ascontiguousarray(p.path_count, dtype=np.uint32)
+        if self.pb.size == 0:
+            self.pb = np.zeros(1, np.uint32)
+            self.pc = np.ones(1, np.uint32)
+        dp = C.POINTER(C.c_double)
+        lam = [complex(x) for x in p.lam]
+        self.s = KProblem_C(p.y_lo, p.y_hi, p.z_lo, p.z_hi, p.y_if, (C.c_double * 2)(*p.kappa),
+                            (C.c_double * 2)(*[x.real for x in lam]), (C.c_double * 2)(*[x.imag for x in lam]),
+                            p.g.shape[1], self.g.ctypes.data_as(dp), p.n_nodes, self.nodes.ctypes.data_as(dp),
+                            self.pb.ctypes.data_as(C.POINTER(C.c_uint32)),
+                            self.pc.ctypes.data_as(C.POINTER(C.c_uint32)), p.dt, p.seed, p.stream,
+                            min(int(p.max_steps), 0xFFFFFFFF))
+
+
+def ksolve(p, threads: Optional[int] = None, records: bool = False):
+    """The discontinuous-kappa walk (interface scheme of Secs. 2.2, 3.1)."""
+    m = _KMarshalled(p)
+    n = p.n_nodes
+    out = np.zeros(max(n, 1), dtype=NODE_DTYPE)
+    recs = np.zeros(p.total_paths, dtype=PATH_DTYPE) if records else None
+    rc = lib().orc_ksolve(C.byref(m.s), threads or default_threads(), out.ctypes.data,
+                          recs.ctypes.data if recs is not None and recs.size else None)
+    if rc != 0:
+        raise ValueError(f"oracle rejected the problem (code {rc})")
+    return out[:n], recs
+
+
+def kwalk_path(p, node: int, path: int):
+    m = _KMarshalled(p)
+    rec = Path_C()
+    rc = lib().orc_kwalk_path(C.byref(m.s), node, path, C.byref(rec))
+    if rc != 0:
+        raise ValueError(rc)
+    return {k: getattr(rec, k) for k, _ in Path_C._fields_}
+
+
+def kwalk_nodes(p, node_idx):
+    """Records of every path of the chosen nodes of p, walked with their own
+    node indices (the same realisations as in a solve of all of p)."""
+    m = _KMarshalled(p)
+    if lib().orc_kvalidate(C.byref(m.s)) != 0:
+        raise ValueError("oracle rejected the problem")
+    out = []
+    rec = Path_C()
+    for j in node_idx:
+        b, c = int(p.path_begin[j]), int(p.path_count[j])
+        r = np.zeros(c, dtype=PATH_DTYPE)
+        for k in range(c):
+            lib().orc_kwalk_path(C.byref(m.s), int(j), b + k, C.byref(rec))
+            r[k] = tuple(getattr(rec, f) for f, _ in Path_C._fields_)
+        out.append(r)
+    return out
+
+
+def kvalidate(p) -> int:
+    m = _KMarshalled(p)
+    return int(lib().orc_kvalidate(C.byref(m.s)))

@@ -510,3 +510,306 @@ int orc_solve(const orc_problem *P, int n_threads, orc_node *out_nodes,
     free(item_off);
     return ORC_OK;
 }
+
+/* ======================================================================== */
+/* Discontinuous kappa: the interface scheme of Secs. 2.2 and 3.1.          */
+/* ======================================================================== */
+/*
+ * (1/2) div(kappa grad u) - lambda u = 0 (Eq. 9) with kappa and lambda
+ * constant on each side of one vertical interface y = y_if (the case the
+ * paper derives, Eqs. 10-12), u = g on the rectangle's boundary.  In each
+ * side the process is sqrt(kappa_i) times Brownian motion (Eq. 10); a step
+ * that reaches the interface (crossing, or a bridge hit, Eq. 14 with
+ * kappa_i) resumes inside a disc of radius h on the side drawn with the
+ * probabilities of Eq. 12, and the step's time is split between the two
+ * occupation times as Sec. 3.1 describes.  The estimator is
+ * g(beta(tau)) exp(-(lambda_0 T_0 + lambda_1 T_1)).
+ *
+ * Readings (also in the design notes): both discs have the radius
+ * h = sqrt(kappa_i dt) of the step that reached the interface (kappa_i of the
+ * side it started on), so that the probabilities of Eq. (12), which hold for
+ * equal radii, are the consistent ones (with unequal radii they would make
+ * every visit of the interface O(h) wrong and the walk's limit biased); for
+ * the side change the second share is
+ * (1/2)(dt - t_gamma)(2 - p_j), so that the two shares sum to the step (the
+ * printed (1 + p_j) sums to dt only when p_j = 1/2); the interface point is
+ * the step's point at t_gamma (linear in the step); a point on the interface
+ * belongs to side 1; the disc of side i touches the interface from side i;
+ * a disc point outside the rectangle ends the walk at the nearest boundary
+ * point with f = 1; equal kappa: the proposal is kept and the step's time
+ * goes to the side of the proposal.
+ * Random numbers: counter (n/2, p, j, 4s) -> the normals of steps n, n+1
+ * (words 0,1 / 2,3); (n, p, j, 4s+1) -> outer bridge uniforms (words 0, 1),
+ * the interface bridge uniform (word 2), the side uniform (word 3);
+ * (n, p, j, 4s+2) -> the disc point (radius word 0, angle word 1).
+ */
+
+typedef struct {
+    double y_lo, y_hi, z_lo, z_hi;
+    double y_if;                  /* interface y = y_if */
+    double kappa[2];              /* side 0: y < y_if, side 1: y >= y_if */
+    double lambda_re[2], lambda_im[2];
+    int32_t g_samples;
+    const double *g;              /* 4 walls x g_samples x (re, im) */
+    int32_t n_nodes;
+    const double *nodes;
+    const uint32_t *path_begin;
+    const uint32_t *path_count;
+    double dt;
+    uint64_t seed;
+    uint32_t stream;
+    uint32_t max_steps;
+} orc_kproblem;
+
+static void kwords(const orc_kproblem *P, uint32_t c0, uint32_t p, int j,
+                   uint32_t domain, uint32_t w[4])
+{
+    uint32_t key[2] = {(uint32_t)(P->seed & 0xFFFFFFFFu), (uint32_t)(P->seed >> 32)};
+    uint32_t ctr[4] = {c0, p, (uint32_t)j, 4u * P->stream + domain};
+    orc_philox4x32_10(ctr, key, w);
+}
+
+static void ktable_g(const orc_kproblem *P, int wall, double t, double out[2])
+{
+    orc_problem Q;
+    memset(&Q, 0, sizeof(Q));
+    Q.y_lo = P->y_lo; Q.y_hi = P->y_hi; Q.z_lo = P->z_lo; Q.z_hi = P->z_hi;
+    Q.g_samples = P->g_samples;
+    Q.g = P->g;
+    orc_table_g(&Q, wall, t, out);
+}
+
+static void kfinish(const orc_kproblem *P, const double T[2], int wall, double t,
+                    double tau, uint32_t steps, orc_path *out)
+{
+    double g[2];
+    ktable_g(P, wall, t, g);
+    /* exp(-(lambda_0 T_0 + lambda_1 T_1)) */
+    double er = -(P->lambda_re[0] * T[0] + P->lambda_re[1] * T[1]);
+    double ei = -(P->lambda_im[0] * T[0] + P->lambda_im[1] * T[1]);
+    double m = exp(er);
+    double cr = m * cos(ei), ci = m * sin(ei);
+    out->w_re = g[0] * cr - g[1] * ci;
+    out->w_im = g[0] * ci + g[1] * cr;
+    out->S = -ei;
+    out->tau = tau;
+    out->exit_t = t;
+    out->steps = steps;
+    out->wall = wall;
+}
+
+/* The wall point nearest to (y, z) (outside or on the rectangle). */
+static void nearest_wall(const orc_kproblem *P, double y, double z, int *wall, double *t)
+{
+    double dl = y - P->y_lo, dr = P->y_hi - y, dt_ = z - P->z_lo, db = P->z_hi - z;
+    double m = dl; *wall = 3;
+    if (dr < m) { m = dr; *wall = 1; }
+    if (dt_ < m) { m = dt_; *wall = 0; }
+    if (db < m) { m = db; *wall = 2; }
+    double yy = fmin(fmax(y, P->y_lo), P->y_hi), zz = fmin(fmax(z, P->z_lo), P->z_hi);
+    *t = (*wall == 0 || *wall == 2) ? yy : zz;
+}
+
+int orc_kwalk_path(const orc_kproblem *P, int j, uint32_t p, orc_path *out)
+{
+    double y = P->nodes[2 * j], z = P->nodes[2 * j + 1];
+    double T[2] = {0.0, 0.0};
+    const double lo[2] = {P->y_lo, P->z_lo};
+    const double hi[2] = {P->y_hi, P->z_hi};
+    const double dt = P->dt;
+
+    for (uint32_t n = 0; n < P->max_steps; ++n) {
+        int si = (y < P->y_if) ? 0 : 1;           /* side of the current point */
+        double ki = P->kappa[si];
+        uint32_t w[4], u[4];
+        kwords(P, n >> 1, p, j, 0u, w);
+        double N[2];
+        if ((n & 1u) == 0u) orc_box_muller(orc_u01(w[0]), orc_u01(w[1]), N);
+        else                orc_box_muller(orc_u01(w[2]), orc_u01(w[3]), N);
+        double s = sqrt(ki * dt);                 /* Eq. (13) with kappa_i */
+        double yn = y + s * N[0], zn = z + s * N[1];
+        kwords(P, n, p, j, 1u, u);
+
+        /* outer boundary first: nearer wall per axis, crossing or bridge
+           (Eq. 14 with kappa_i) */
+        const double x[2] = {y, z}, xn[2] = {yn, zn};
+        int hit[2] = {0, 0}, upper[2] = {0, 0};
+        double f[2] = {0.0, 0.0};
+        for (int a = 0; a < 2; ++a) {
+            double dlo = x[a] - lo[a], dhi = hi[a] - x[a];
+            upper[a] = !(dlo <= dhi);
+            double d0 = upper[a] ? dhi : dlo;
+            double d1 = upper[a] ? (hi[a] - xn[a]) : (xn[a] - lo[a]);
+            if (d1 <= 0.0) {
+                hit[a] = 1;
+                f[a] = d0 / (d0 - d1);
+            } else {
+                double q = (2.0 * d0) * d1;
+                double L = -log(orc_u01(u[a]));
+                if (q <= ki * dt * L) { hit[a] = 1; f[a] = q / (ki * dt * L); }
+            }
+        }
+        if (hit[0] || hit[1]) {
+            int a = (hit[0] && (!hit[1] || f[0] <= f[1])) ? 0 : 1;
+            double fr = f[a], t;
+            int wall;
+            if (a == 0) {
+                wall = upper[0] ? 1 : 3;
+                t = fmin(fmax(z + fr * (zn - z), P->z_lo), P->z_hi);
+            } else {
+                wall = upper[1] ? 2 : 0;
+                t = fmin(fmax(y + fr * (yn - y), P->y_lo), P->y_hi);
+            }
+            T[si] += fr * dt;
+            kfinish(P, T, wall, t, ((double)n + fr) * dt, n + 1, out);
+            return ORC_OK;
+        }
+
+        /* the interface */
+        int sn = (yn < P->y_if) ? 0 : 1;
+        if (P->kappa[0] == P->kappa[1]) {
+            T[sn] += dt;                          /* no regime change */
+            y = yn; z = zn;
+            continue;
+        }
+        double d0 = fabs(y - P->y_if);
+        double tg;
+        int reached;
+        if (sn != si) {                           /* crossed: Eq. 14, 2nd case */
+            tg = dt * fabs(d0 / (yn - y));
+            reached = 1;
+        } else {                                  /* same side: bridge test */
+            double d1 = fabs(yn - P->y_if);
+            tg = -2.0 * d0 * d1 / (ki * log(orc_u01(u[2])));
+            reached = tg <= dt;
+        }
+        if (!reached) {
+            T[si] += dt;
+            y = yn; z = zn;
+            continue;
+        }
+        int sj = 1 - si;
+        double kj = P->kappa[sj];
+        /* Eq. (12): the probabilities of Eq. (11) for equal radii; both discs
+           get the radius of the step that reached the interface */
+        double pi_ = ki / (ki + kj), pj = 1.0 - pi_;
+        double h = sqrt(ki * dt);
+        double zg = z + (tg / dt) * (zn - z);            /* interface point */
+        double towards = (si == 0) ? 1.0 : -1.0;         /* c_ij(h) / h */
+        double cy;
+        if (orc_u01(u[3]) < pi_) {                       /* resume on side i */
+            cy = P->y_if - towards * h;
+            T[si] += dt - 0.5 * (dt - tg) * pi_;
+            T[sj] += 0.5 * (dt - tg) * pi_;
+        } else {                                         /* resume on side j */
+            cy = P->y_if + towards * h;
+            T[si] += tg + 0.5 * (dt - tg) * pj;
+            T[sj] += 0.5 * (dt - tg) * (2.0 - pj);
+        }
+        uint32_t d[4];
+        kwords(P, n, p, j, 2u, d);
+        const double two_pi = 6.283185307179586476925286766559;
+        double r = h * sqrt(orc_u01(d[0])), th = two_pi * orc_u01(d[1]);
+        y = cy + r * cos(th);
+        z = zg + r * sin(th);
+        if (!(y > P->y_lo && y < P->y_hi && z > P->z_lo && z < P->z_hi)) {
+            int wall;
+            double t;
+            nearest_wall(P, y, z, &wall, &t);
+            kfinish(P, T, wall, t, ((double)n + 1.0) * dt, n + 1, out);
+            return ORC_OK;
+        }
+    }
+    out->w_re = 0.0;
+    out->w_im = 0.0;
+    out->S = 0.0;
+    out->tau = -1.0;
+    out->exit_t = 0.0;
+    out->steps = P->max_steps;
+    out->wall = -1;
+    return ORC_OK;
+}
+
+int orc_kvalidate(const orc_kproblem *P)
+{
+    if (!(P->y_lo < P->y_if && P->y_if < P->y_hi) || !(P->z_lo < P->z_hi)) return ORC_E_INVALID;
+    if (!(P->dt > 0.0) || !isfinite(P->dt)) return ORC_E_INVALID;
+    for (int i = 0; i < 2; ++i) {
+        if (!(P->kappa[i] > 0.0) || !isfinite(P->kappa[i])) return ORC_E_INVALID;
+        if (!(P->lambda_re[i] >= 0.0) || !isfinite(P->lambda_re[i]) || !isfinite(P->lambda_im[i]))
+            return ORC_E_INVALID;
+    }
+    double kmax = fmax(P->kappa[0], P->kappa[1]);
+    double half = 0.5 * fmin(P->y_hi - P->y_lo, P->z_hi - P->z_lo);
+    if (!(7.0 * sqrt(kmax * P->dt) < half)) return ORC_E_INVALID;
+    if (P->g_samples < 2 || P->g == NULL || P->n_nodes < 0 || P->max_steps == 0) return ORC_E_INVALID;
+    if (P->stream >= 0x40000000u) return ORC_E_INVALID;
+    for (int j = 0; j < P->n_nodes; ++j) {
+        double y = P->nodes[2 * j], z = P->nodes[2 * j + 1];
+        if (!(y > P->y_lo && y < P->y_hi && z > P->z_lo && z < P->z_hi)) return ORC_E_INVALID;
+        if (P->path_count[j] < 1) return ORC_E_INVALID;
+        if ((uint64_t)P->path_begin[j] + P->path_count[j] > 0x100000000ull) return ORC_E_INVALID;
+    }
+    return ORC_OK;
+}
+
+typedef struct {
+    const orc_kproblem *P;
+    orc_path *recs;
+    const uint64_t *rec_off;
+    uint64_t n_items;
+    const uint64_t *item_off;
+    uint64_t next;
+} orc_kwork;
+
+static void *kworker(void *arg)
+{
+    orc_kwork *W = (orc_kwork *)arg;
+    const orc_kproblem *P = W->P;
+    for (;;) {
+        uint64_t item = __atomic_fetch_add(&W->next, 1, __ATOMIC_RELAXED);
+        if (item >= W->n_items) break;
+        int j = 0;
+        while (W->item_off[j + 1] <= item) ++j;
+        uint64_t k0 = (item - W->item_off[j]) * ORC_BLOCK;
+        uint64_t k1 = k0 + ORC_BLOCK;
+        if (k1 > P->path_count[j]) k1 = P->path_count[j];
+        for (uint64_t k = k0; k < k1; ++k)
+            orc_kwalk_path(P, j, P->path_begin[j] + (uint32_t)k, W->recs + W->rec_off[j] + k);
+    }
+    return NULL;
+}
+
+int orc_ksolve(const orc_kproblem *P, int n_threads, orc_node *out_nodes, orc_path *out_paths)
+{
+    int rc = orc_kvalidate(P);
+    if (rc != ORC_OK) return rc;
+    int n = P->n_nodes;
+    uint64_t *rec_off = (uint64_t *)calloc((size_t)n + 1, sizeof(uint64_t));
+    uint64_t *item_off = (uint64_t *)calloc((size_t)n + 1, sizeof(uint64_t));
+    if (!rec_off || !item_off) { free(rec_off); free(item_off); return ORC_E_NOMEM; }
+    for (int j = 0; j < n; ++j) {
+        rec_off[j + 1] = rec_off[j] + P->path_count[j];
+        item_off[j + 1] = item_off[j] + (P->path_count[j] + ORC_BLOCK - 1) / ORC_BLOCK;
+    }
+    orc_path *recs = out_paths;
+    if (recs == NULL && rec_off[n] > 0) {
+        recs = (orc_path *)malloc((size_t)rec_off[n] * sizeof(orc_path));
+        if (!recs) { free(rec_off); free(item_off); return ORC_E_NOMEM; }
+    }
+    orc_kwork W = {P, recs, rec_off, item_off[n], item_off, 0};
+    if (n_threads < 1) n_threads = 1;
+    if (n_threads > 512) n_threads = 512;
+    pthread_t tid[512];
+    int started = 0;
+    for (int t = 1; t < n_threads; ++t)
+        if (pthread_create(&tid[started], NULL, kworker, &W) == 0) ++started;
+    kworker(&W);
+    for (int t = 0; t < started; ++t) pthread_join(tid[t], NULL);
+    for (int j = 0; j < n; ++j)
+        orc_node_stats(recs + rec_off[j], P->path_count[j], out_nodes + j);
+    if (recs != out_paths) free(recs);
+    free(rec_off);
+    free(item_off);
+    return ORC_OK;
+}

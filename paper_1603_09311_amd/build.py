@@ -11,8 +11,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsdd.so")
-SOURCES = [os.path.join(CSRC, "sdd_kernels.hip"), os.path.join(CSRC, "sdd_runtime.cpp"),
-           os.path.join(CSRC, "sdd_rbffd.cpp")]
+SOURCES = [os.path.join(CSRC, "sdd_kernels.hip"), os.path.join(CSRC, "sdd_kappa.hip"),
+           os.path.join(CSRC, "sdd_runtime.cpp"), os.path.join(CSRC, "sdd_rbffd.cpp")]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

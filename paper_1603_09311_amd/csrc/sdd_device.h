@@ -150,4 +150,26 @@ struct DevReq {
   uint32_t *slice_ctl;              // SliceCtl words
 };
 
+
+// Request descriptor of the discontinuous-kappa walk (one vertical interface
+// y = y_if; side 0 is y < y_if, side 1 is y >= y_if).
+struct KReq {
+  double y_lo, y_hi, z_lo, z_hi, y_if;
+  double dt;
+  double kdt[2];       // kappa_i dt
+  double s[2];         // sqrt(kappa_i dt): step scale and interface disc radius
+  double thr[2];       // 22.9 kappa_i dt: draw a bridge uniform only if 2 d0 d1 <= thr
+  double p[2];         // kappa_i / (kappa_0 + kappa_1): resume on side i
+  double kappa[2];
+  double lre[2], lim[2];   // killing rate per side
+  const double *g;     // 4 x (M + 1) x (re, im)
+  const double *nodes; // n_nodes x (y, z)
+  const DevTile *tiles;
+  PathRec *recs;
+  uint32_t *tile_counter;
+  uint32_t n_tiles, M, key0, key1, ctr3, max_steps;
+  uint32_t equal_kappa;   // kappa_0 == kappa_1: no interface rule
+  uint32_t pad;
+};
+
 }  // namespace sdd

@@ -1,0 +1,310 @@
+// HIP kernel for gfx950: the walk of (1/2) div(kappa grad u) - lambda u = 0
+// (Eq. 9) when kappa and lambda are constant on each side of one vertical
+// interface y = y_if, in FP64 (Secs. 2.2 and 3.1).
+//
+// Away from the interface the process is sqrt(kappa_i) times Brownian motion
+// (Eq. 10): a step is the Euler-Maruyama proposal of Eq. (13) with kappa_i.
+// The outer boundary is tested first (crossing, or the Brownian-bridge test
+// of Eq. 14 with kappa_i on the nearer wall per axis).  Then the interface:
+// a crossing, or a same-side bridge hit whose time t_gamma (Eq. 14, first
+// case) is within the step, means the process reached it; it then resumes
+// from a uniform point of a disc of radius h = sqrt(kappa_i dt) that touches
+// the interface from side i (probability p_i of Eq. 12) or from side j, and
+// the step's time is split between the two occupation times (Sec. 3.1, with
+// the second share of a side change read as (1/2)(dt - t_gamma)(2 - p_j) so
+// that the shares sum to dt).  A disc point outside the rectangle ends the
+// walk at the nearest boundary point.  When kappa_0 == kappa_1 the proposal
+// is kept and the step's time goes to the side of the proposal.  The record
+// is g(exit) exp(-(lambda_0 T_0 + lambda_1 T_1)).
+//
+// Random numbers (Philox4x32-10 keyed by the seed): counter (n/2, p, j, 4s)
+// gives the normals of steps n, n + 1 (words 0,1 / 2,3); (n, p, j, 4s + 1)
+// the outer bridge uniforms (words 0, 1), the interface bridge uniform
+// (word 2) and the side uniform (word 3); (n, p, j, 4s + 2) the disc point
+// (radius word 0, angle word 1).  Uniforms are drawn only where the paper's
+// tests can use them, which changes no result.
+//
+// Scheduling: persistent waves; a wave claims tiles of one node's paths with
+// one atomic and refills every lane whose path has ended (ballot + mbcnt
+// rank), so a wave never waits for its longest path.  Each path writes its
+// own record: results are independent of the launch shape.
+//
+// Compiled with -ffp-contract=off: every operation rounds on its own, in the
+// order a plain FP64 reading of the scheme evaluates it.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sdd_device.h"
+#include "sdd_rng.h"
+
+namespace sdd {
+namespace {
+
+constexpr uint32_t kKappaThreads = 256;
+
+struct KWalker {
+  double y, z;
+  double T0, T1;     // occupation times of side 0 and side 1
+  uint32_t n;        // steps taken
+  uint64_t rec;      // record slot
+  PhiloxPath pp;
+};
+
+// The record of a path that ended at tangential coordinate t of `wall`.
+__device__ __forceinline__ PathRec kfinish(const KReq &Q, const KWalker &W, int wall, double t, double tau) {
+  double gre, gim;
+  g_table(Q.g, (int)Q.M, Q.y_lo, Q.y_hi, Q.z_lo, Q.z_hi, wall, t, gre, gim);
+  const double er = -(Q.lre[0] * W.T0 + Q.lre[1] * W.T1);
+  const double ei = -(Q.lim[0] * W.T0 + Q.lim[1] * W.T1);
+  const double m = exp(er);
+  const double cr = m * cos(ei), ci = m * sin(ei);
+  PathRec r;
+  r.w_re = gre * cr - gim * ci;
+  r.w_im = gre * ci + gim * cr;
+  r.tau = tau;
+  r.steps = W.n + 1u;
+  r.wall = wall;
+  return r;
+}
+
+// One step with normals (n0, n1).  Returns true when the path ends; its
+// record is then in `out`.
+__device__ __forceinline__ bool kstep(const KReq &Q, KWalker &W, double n0, double n1, PathRec &out) {
+  const bool s1 = !(W.y < Q.y_if);                 // side of the current point
+  const double kdt = s1 ? Q.kdt[1] : Q.kdt[0];
+  const double s = s1 ? Q.s[1] : Q.s[0];
+  const double thr = s1 ? Q.thr[1] : Q.thr[0];
+  const double yn = W.y + s * n0;
+  const double zn = W.z + s * n1;
+
+  // outer boundary: nearer wall per axis (a tie goes to the lower wall)
+  const double dly = W.y - Q.y_lo, dhy = Q.y_hi - W.y;
+  const bool upy = !(dly <= dhy);
+  const double d0y = upy ? dhy : dly;
+  const double d1y = upy ? (Q.y_hi - yn) : (yn - Q.y_lo);
+  const double dlz = W.z - Q.z_lo, dhz = Q.z_hi - W.z;
+  const bool upz = !(dlz <= dhz);
+  const double d0z = upz ? dhz : dlz;
+  const double d1z = upz ? (Q.z_hi - zn) : (zn - Q.z_lo);
+  const bool cy = d1y <= 0.0, cz = d1z <= 0.0;
+  const double qy = (2.0 * d0y) * d1y, qz = (2.0 * d0z) * d1z;
+  const bool by = !cy && (qy <= thr), bz = !cz && (qz <= thr);
+
+  // interface candidates
+  const bool sn1 = !(yn < Q.y_if);
+  const bool jump = !Q.equal_kappa;
+  const double e0 = fabs(W.y - Q.y_if);
+  const double e1 = fabs(yn - Q.y_if);
+  const bool crossed = jump && (sn1 != s1);
+  const bool bridge_if = jump && !crossed && ((2.0 * e0) * e1 <= thr);
+
+  uint4 u = make_uint4(0u, 0u, 0u, 0u);
+  if (by || bz || crossed || bridge_if) {
+    const uint64_t Pn = (uint64_t)kM0 * (uint64_t)W.n;
+    u = philox_pp(Pn, Q.ctr3 + 1u, W.pp, Q.key0, Q.key1);
+  }
+
+  bool hy = cy, hz = cz;
+  double fy = 0.0, fz = 0.0;
+  if (by) {
+    const double L = -log(u01_64(u.x));
+    if (qy <= kdt * L) { hy = true; fy = qy / (kdt * L); }
+  }
+  if (bz) {
+    const double L = -log(u01_64(u.y));
+    if (qz <= kdt * L) { hz = true; fz = qz / (kdt * L); }
+  }
+  if (hy || hz) {
+    if (cy) fy = d0y / (d0y - d1y);
+    if (cz) fz = d0z / (d0z - d1z);
+    int wall;
+    double f, t;
+    if (hy && (!hz || fy <= fz)) {
+      f = fy;
+      wall = upy ? 1 : 3;
+      t = fmin(fmax(W.z + fy * (zn - W.z), Q.z_lo), Q.z_hi);
+    } else {
+      f = fz;
+      wall = upz ? 2 : 0;
+      t = fmin(fmax(W.y + fz * (yn - W.y), Q.y_lo), Q.y_hi);
+    }
+    const double occ = f * Q.dt;
+    if (s1) W.T1 = W.T1 + occ; else W.T0 = W.T0 + occ;
+    out = kfinish(Q, W, wall, t, ((double)W.n + f) * Q.dt);
+    return true;
+  }
+
+  if (!jump) {                                     // equal kappa: no regime change
+    if (sn1) W.T1 = W.T1 + Q.dt; else W.T0 = W.T0 + Q.dt;
+    W.y = yn;
+    W.z = zn;
+    return false;
+  }
+  double tg = 0.0;
+  bool reached = crossed;
+  if (crossed) {
+    tg = Q.dt * fabs(e0 / (yn - W.y));
+  } else if (bridge_if) {
+    const double ki = s1 ? Q.kappa[1] : Q.kappa[0];
+    tg = ((-2.0 * e0) * e1) / (ki * log(u01_64(u.z)));
+    reached = tg <= Q.dt;
+  }
+  if (!reached) {
+    if (s1) W.T1 = W.T1 + Q.dt; else W.T0 = W.T0 + Q.dt;
+    W.y = yn;
+    W.z = zn;
+    return false;
+  }
+
+  // resume inside a disc touching the interface from side i or side j
+  const double pi = s1 ? Q.p[1] : Q.p[0];
+  const double pj = 1.0 - pi;
+  const double zg = W.z + (tg / Q.dt) * (zn - W.z);   // interface point
+  const double towards = s1 ? -1.0 : 1.0;             // from side i towards side j
+  const double half = 0.5 * (Q.dt - tg);
+  double cyc, add_i, add_j;
+  if (u01_64(u.w) < pi) {
+    cyc = Q.y_if - towards * s;
+    add_i = Q.dt - half * pi;
+    add_j = half * pi;
+  } else {
+    cyc = Q.y_if + towards * s;
+    add_i = tg + half * pj;
+    add_j = half * (2.0 - pj);
+  }
+  W.T0 = W.T0 + (s1 ? add_j : add_i);
+  W.T1 = W.T1 + (s1 ? add_i : add_j);
+  const uint64_t Pn = (uint64_t)kM0 * (uint64_t)W.n;
+  const uint4 d = philox_pp(Pn, Q.ctr3 + 2u, W.pp, Q.key0, Q.key1);
+  const double two_pi = 6.283185307179586476925286766559;
+  const double r = s * sqrt(u01_64(d.x));
+  const double th = two_pi * u01_64(d.y);
+  const double y = cyc + r * cos(th);
+  const double z = zg + r * sin(th);
+  if (!(y > Q.y_lo && y < Q.y_hi && z > Q.z_lo && z < Q.z_hi)) {
+    // the nearest boundary point (ties in the order left, right, top, bottom)
+    const double dl = y - Q.y_lo, dr = Q.y_hi - y, dtp = z - Q.z_lo, db = Q.z_hi - z;
+    double m = dl;
+    int wall = 3;
+    if (dr < m) { m = dr; wall = 1; }
+    if (dtp < m) { m = dtp; wall = 0; }
+    if (db < m) { m = db; wall = 2; }
+    const double yy = fmin(fmax(y, Q.y_lo), Q.y_hi), zz = fmin(fmax(z, Q.z_lo), Q.z_hi);
+    const double t = (wall == 0 || wall == 2) ? yy : zz;
+    out = kfinish(Q, W, wall, t, ((double)W.n + 1.0) * Q.dt);
+    return true;
+  }
+  W.y = y;
+  W.z = z;
+  return false;
+}
+
+__device__ __forceinline__ PathRec kunfinished(uint32_t steps) {
+  PathRec r;
+  r.w_re = 0.0;
+  r.w_im = 0.0;
+  r.tau = -1.0;
+  r.steps = steps;
+  r.wall = -1;
+  return r;
+}
+
+__global__ void __launch_bounds__(kKappaThreads) walk_kappa(const KReq *__restrict__ qp) {
+  const KReq &Q = *qp;
+  const uint32_t lane = __lane_id();
+  KWalker W;
+  bool active = false;
+  bool exhausted = false;
+  // wave-uniform tile cursor
+  uint32_t t_node = 0, t_p0 = 0, t_next = 0, t_end = 0;
+  uint64_t t_rec0 = 0;
+
+  for (;;) {
+    const uint64_t freemask = __builtin_amdgcn_ballot_w64(!active);
+    if (freemask != 0ull && !exhausted) {
+      const uint32_t nfree = (uint32_t)__popcll(freemask);
+      const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(freemask >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)freemask, 0u));
+      uint32_t given = 0;
+      while (given < nfree) {
+        if (t_next == t_end) {
+          uint32_t t = 0;
+          if (lane == 0) t = atomicAdd(Q.tile_counter, 1u);
+          t = uni(t);
+          if (t >= Q.n_tiles) { exhausted = true; break; }
+          const DevTile Tl = Q.tiles[t];
+          t_node = uni(Tl.node);
+          t_p0 = uni(Tl.p0);
+          t_next = t_p0;
+          t_end = t_p0 + uni(Tl.count);
+          t_rec0 = ((uint64_t)uni((uint32_t)(Tl.rec0 >> 32)) << 32) | uni((uint32_t)Tl.rec0);
+        }
+        const uint32_t take = min(t_end - t_next, nfree - given);
+        if (!active && rank >= given && rank < given + take) {
+          const uint32_t p = t_next + (rank - given);
+          const double2 xy = *reinterpret_cast<const double2 *>(Q.nodes + 2 * (size_t)t_node);
+          W.y = xy.x;
+          W.z = xy.y;
+          W.T0 = 0.0;
+          W.T1 = 0.0;
+          W.n = 0u;
+          W.rec = t_rec0 + (p - t_p0);
+          W.pp = philox_path(p, t_node, Q.key0);
+          active = true;
+        }
+        t_next += take;
+        given += take;
+      }
+    }
+    if (__builtin_amdgcn_ballot_w64(!active) == ~0ull) break;   // no work left for this wave
+
+    if (active) {
+      // two steps per normal draw; a walker is at an even step here
+      const uint64_t P = (uint64_t)kM0 * (uint64_t)(W.n >> 1);
+      const uint4 w = philox_pp(P, Q.ctr3, W.pp, Q.key0, Q.key1);
+      double a0, a1, b0, b1;
+      normals64(w.x, w.y, a0, a1);
+      normals64(w.z, w.w, b0, b1);
+      PathRec r;
+      bool end = kstep(Q, W, a0, a1, r);
+      if (!end) {
+        W.n += 1u;
+        if (W.n >= Q.max_steps) {
+          end = true;
+          r = kunfinished(W.n);
+        } else {
+          end = kstep(Q, W, b0, b1, r);
+          if (!end) {
+            W.n += 1u;
+            if (W.n >= Q.max_steps) {
+              end = true;
+              r = kunfinished(W.n);
+            }
+          }
+        }
+      }
+      if (end) {
+        Q.recs[W.rec] = r;
+        active = false;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_walk_kappa(const KReq *req_dev, uint32_t blocks, hipStream_t st) {
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(walk_kappa, dim3(blocks), dim3(kKappaThreads), 0, st, req_dev);
+  return hipGetLastError();
+}
+
+int kappa_blocks_per_cu() {
+  int nb = 0;
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_kappa, (int)kKappaThreads, 0);
+  return e == hipSuccess ? nb : 0;
+}
+
+uint32_t kappa_threads() { return kKappaThreads; }
+
+}  // namespace sdd

@@ -37,6 +37,9 @@ hipError_t launch_reduce_fanout(const FanJob *jobs_dev, uint32_t n_jobs, int M, 
                                 double z_hi, hipStream_t st);
 hipError_t launch_reset(uint32_t *tile_counters, unsigned long long *done, uint32_t n, hipStream_t st);
 int persist_blocks_per_cu(int precision, int sig, uint32_t threads);
+hipError_t launch_walk_kappa(const KReq *req_dev, uint32_t blocks, hipStream_t st);
+int kappa_blocks_per_cu();
+uint32_t kappa_threads();
 }  // namespace sdd
 
 using namespace sdd;
@@ -724,8 +727,7 @@ static void plan_extension(Prepared &P, const NodeOut *pilot_rows) {
   P.pass = 1;
 }
 
-static void scatter(const Prepared &P, const NodeOut *rows, sdd_result *res) {
-  const uint32_t n = (uint32_t)P.pbeg_all.size();
+static void scatter_rows(uint32_t n, const NodeOut *rows, sdd_result *res) {
   for (uint32_t j = 0; j < n; ++j) {
     const NodeOut &o = rows[j];
     if (res->mean) { res->mean[2 * j] = o.mean_re; res->mean[2 * j + 1] = o.mean_im; }
@@ -736,6 +738,10 @@ static void scatter(const Prepared &P, const NodeOut *rows, sdd_result *res) {
     if (res->unfinished) res->unfinished[j] = o.unfinished;
     if (res->mean_exit_time) res->mean_exit_time[j] = o.mean_exit_time;
   }
+}
+
+static void scatter(const Prepared &P, const NodeOut *rows, sdd_result *res) {
+  scatter_rows((uint32_t)P.pbeg_all.size(), rows, res);
 }
 
 static sdd_status copy_records(sdd_ctx *ctx, const Prepared &P, sdd_result *res) {
@@ -1538,6 +1544,171 @@ sdd_status sdd_cancel(sdd_ctx_t ctx, sdd_ticket_t t) {
     T->P.reset();
     ctx->done_cv.notify_all();
   }
+  return SDD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Discontinuous kappa: one vertical interface, FP64 walk (sdd_kappa.hip).
+// ---------------------------------------------------------------------------
+static sdd_status validate_kappa(const sdd_kappa_request *r) {
+  auto fin = [](double v) { return std::isfinite(v); };
+  if (!(fin(r->y_lo) && fin(r->y_hi) && fin(r->z_lo) && fin(r->z_hi) && r->y_lo < r->y_hi && r->z_lo < r->z_hi))
+    return fail(SDD_E_INVALID, "Omega must be a finite rectangle");
+  if (!(fin(r->y_if) && r->y_lo < r->y_if && r->y_if < r->y_hi))
+    return fail(SDD_E_INVALID, "the interface must lie strictly inside Omega");
+  for (int i = 0; i < 2; ++i) {
+    if (!(fin(r->kappa[i]) && r->kappa[i] > 0.0)) return fail(SDD_E_INVALID, "kappa must be finite and > 0");
+    if (!(fin(r->lambda_re[i]) && r->lambda_re[i] >= 0.0) || !fin(r->lambda_im[i]))
+      return fail(SDD_E_INVALID, "lambda must be finite with a real part >= 0");
+  }
+  if (!(fin(r->dt) && r->dt > 0.0)) return fail(SDD_E_INVALID, "dt must be finite and > 0");
+  const double half = 0.5 * std::min(r->y_hi - r->y_lo, r->z_hi - r->z_lo);
+  if (!(7.0 * std::sqrt(std::max(r->kappa[0], r->kappa[1]) * r->dt) < half))
+    return fail(SDD_E_INVALID, "dt too large: 7 sqrt(kappa dt) must be below half the shorter side");
+  if (r->stream >= (1u << 30)) return fail(SDD_E_INVALID, "stream must be < 2^30");
+  if (r->reserved != 0) return fail(SDD_E_INVALID, "reserved must be 0");
+  if (r->g_samples < 2 || !r->g_tables) return fail(SDD_E_INVALID, "g_tables need >= 2 samples per wall");
+  for (size_t k = 0; k < (size_t)8 * r->g_samples; ++k)
+    if (!fin(r->g_tables[k])) return fail(SDD_E_INVALID, "g_tables must be finite");
+  if (r->n_nodes && !r->nodes_yz) return fail(SDD_E_INVALID, "nodes_yz is NULL");
+  uint64_t total = 0;
+  for (uint32_t j = 0; j < r->n_nodes; ++j) {
+    const double y = r->nodes_yz[2 * j], z = r->nodes_yz[2 * j + 1];
+    if (!(y > r->y_lo && y < r->y_hi && z > r->z_lo && z < r->z_hi))
+      return fail(SDD_E_INVALID, "node %u is not strictly inside Omega", j);
+    const uint32_t b = r->path_begin ? r->path_begin[j] : 0u;
+    const uint32_t c = r->path_count ? r->path_count[j] : r->paths_uniform;
+    if (c == 0) return fail(SDD_E_INVALID, "node %u has no paths", j);
+    if ((uint64_t)b + c > (1ull << 32)) return fail(SDD_E_INVALID, "node %u: path range passes 2^32", j);
+    total += c;
+  }
+  if (total > (1ull << 40)) return fail(SDD_E_INVALID, "more than 2^40 paths");
+  return SDD_OK;
+}
+
+sdd_status sdd_solve_kappa(sdd_ctx_t ctx, const sdd_kappa_request *r, sdd_result *res) {
+  if (!ctx || !r || !res) return fail(SDD_E_INVALID, "NULL argument");
+  sdd_status st = validate_kappa(r);
+  if (st != SDD_OK) return st;
+  const uint32_t n = r->n_nodes;
+  if (n == 0) return SDD_OK;
+  if (!res->mean) return fail(SDD_E_INVALID, "result mean is NULL");
+
+  // tiles of one node's paths, record slots node-major in path order
+  const uint32_t tile_paths = ctx->tuning.tile_paths ? ctx->tuning.tile_paths : 512u;
+  std::vector<DevTile> tiles;
+  std::vector<uint64_t> rec_off(n + 1, 0);
+  uint64_t total = 0;
+  for (uint32_t j = 0; j < n; ++j) {
+    rec_off[j] = total;
+    const uint32_t b = r->path_begin ? r->path_begin[j] : 0u;
+    const uint32_t c = r->path_count ? r->path_count[j] : r->paths_uniform;
+    for (uint32_t k = 0; k < c; k += tile_paths) {
+      DevTile t{};
+      t.node = j;
+      t.p0 = b + k;
+      t.count = std::min(tile_paths, c - k);
+      t.rec0 = total + k;
+      tiles.push_back(t);
+      if (c - k <= tile_paths) break;
+    }
+    total += c;
+  }
+  rec_off[n] = total;
+  if (tiles.size() >= (1ull << 32)) return fail(SDD_E_INVALID, "too many tiles");
+
+  KReq K{};
+  K.y_lo = r->y_lo; K.y_hi = r->y_hi; K.z_lo = r->z_lo; K.z_hi = r->z_hi; K.y_if = r->y_if;
+  K.dt = r->dt;
+  for (int i = 0; i < 2; ++i) {
+    K.kdt[i] = r->kappa[i] * r->dt;
+    K.s[i] = std::sqrt(K.kdt[i]);
+    // -log u <= 22.87 for every uniform ((w + 1/2) 2^-32), so a bridge can
+    // only hit when 2 d0 d1 <= 22.87 kappa dt
+    K.thr[i] = 22.9 * K.kdt[i];
+    K.p[i] = r->kappa[i] / (r->kappa[0] + r->kappa[1]);
+    K.kappa[i] = r->kappa[i];
+    K.lre[i] = r->lambda_re[i];
+    K.lim[i] = r->lambda_im[i];
+  }
+  K.M = r->g_samples - 1u;
+  K.n_tiles = (uint32_t)tiles.size();
+  K.key0 = (uint32_t)(r->seed & 0xFFFFFFFFull);
+  K.key1 = (uint32_t)(r->seed >> 32);
+  K.ctr3 = 4u * r->stream;
+  K.max_steps = r->max_steps ? r->max_steps : kDefaultMaxSteps;
+  K.equal_kappa = r->kappa[0] == r->kappa[1] ? 1u : 0u;
+
+  ExecGuard ex(ctx);
+  HIP_TRY(hipSetDevice(ctx->device));
+  const size_t g_bytes = (size_t)8 * r->g_samples * sizeof(double);
+  char *d_g = ctx->alloc(g_bytes);
+  char *d_nodes = ctx->alloc((size_t)2 * n * sizeof(double));
+  char *d_tiles = ctx->alloc(tiles.size() * sizeof(DevTile));
+  char *d_recs = ctx->alloc(total * sizeof(PathRec));
+  char *d_req = ctx->alloc(sizeof(KReq) + sizeof(uint32_t) * 64);
+  char *d_out = ctx->alloc((size_t)n * sizeof(NodeOut));
+  char *d_jobs = ctx->alloc((size_t)n * sizeof(NodeJob));
+  auto release = [&]() {
+    for (char *p : {d_g, d_nodes, d_tiles, d_recs, d_req, d_out, d_jobs}) ctx->release(p);
+  };
+  if (!d_g || !d_nodes || !d_tiles || !d_recs || !d_req || !d_out || !d_jobs) {
+    release();
+    return fail(SDD_E_NOMEM, "workspace too small for %llu paths", (unsigned long long)total);
+  }
+  uint32_t *d_ctr = reinterpret_cast<uint32_t *>(d_req + sizeof(KReq));   // the tile counter
+  K.g = reinterpret_cast<const double *>(d_g);
+  K.nodes = reinterpret_cast<const double *>(d_nodes);
+  K.tiles = reinterpret_cast<const DevTile *>(d_tiles);
+  K.recs = reinterpret_cast<PathRec *>(d_recs);
+  K.tile_counter = d_ctr;
+
+  std::vector<NodeJob> jobs(n);
+  for (uint32_t j = 0; j < n; ++j) {
+    jobs[j] = NodeJob{};
+    jobs[j].recs0 = reinterpret_cast<const PathRec *>(d_recs) + rec_off[j];
+    jobs[j].count0 = rec_off[j + 1] - rec_off[j];
+    jobs[j].out = reinterpret_cast<NodeOut *>(d_out) + j;
+  }
+  const uint32_t threads = kappa_threads();
+  const uint32_t waves_per_block = threads / 64u;
+  const int bpc = std::max(kappa_blocks_per_cu(), 1);
+  uint32_t blocks = (uint32_t)std::max(ctx->cus, 1) * (uint32_t)bpc;
+  blocks = std::max<uint32_t>(1u, std::min<uint32_t>(blocks, (K.n_tiles + waves_per_block - 1) / waves_per_block));
+  const uint32_t zero = 0u;
+  std::vector<NodeOut> rows(n);
+  hipStream_t s = ctx->stream;
+  hipError_t e = hipMemcpyAsync(d_g, r->g_tables, g_bytes, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_nodes, r->nodes_yz, (size_t)2 * n * sizeof(double), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_tiles, tiles.data(), tiles.size() * sizeof(DevTile), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_req, &K, sizeof(KReq), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_ctr, &zero, sizeof(zero), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_jobs, jobs.data(), jobs.size() * sizeof(NodeJob), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipEventRecord(ctx->ev[0], s);
+  if (e == hipSuccess) e = launch_walk_kappa(reinterpret_cast<const KReq *>(d_req), blocks, s);
+  if (e == hipSuccess) e = hipEventRecord(ctx->ev[1], s);
+  if (e == hipSuccess) e = launch_reduce(reinterpret_cast<const NodeJob *>(d_jobs), n, s);
+  if (e == hipSuccess) e = hipEventRecord(ctx->ev[2], s);
+  if (e == hipSuccess) e = hipMemcpyAsync(rows.data(), d_out, (size_t)n * sizeof(NodeOut), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && res->path_records)
+    e = hipMemcpyAsync(res->path_records, d_recs, total * sizeof(PathRec), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    release();
+    return fail(SDD_E_DEVICE, "kappa walk: %s", hipGetErrorString(e));
+  }
+  float ms = 0.f, rms = 0.f;
+  if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]) == hipSuccess) ctx->stats.last_walk_ms = ms;
+  if (hipEventElapsedTime(&rms, ctx->ev[1], ctx->ev[2]) == hipSuccess) ctx->stats.last_reduce_ms = rms;
+  uint64_t steps = 0;
+  for (const NodeOut &o : rows) steps += o.steps;
+  ctx->stats.last_walk_steps = steps;
+  ctx->stats.last_walk_paths = total;
+  ctx->stats.last_blocks = blocks;
+  ctx->stats.last_threads = threads;
+  ctx->stats.launches += 1;
+  scatter_rows(n, rows.data(), res);
+  release();
   return SDD_OK;
 }
 

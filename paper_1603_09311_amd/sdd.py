@@ -48,6 +48,16 @@ class sdd_request(C.Structure):
                 ("reserved", C.c_uint32), ("target_rel_se", C.c_double)]
 
 
+class sdd_kappa_request(C.Structure):
+    _fields_ = [("y_lo", C.c_double), ("y_hi", C.c_double), ("z_lo", C.c_double), ("z_hi", C.c_double),
+                ("y_if", C.c_double), ("kappa", C.c_double * 2), ("lambda_re", C.c_double * 2),
+                ("lambda_im", C.c_double * 2), ("g_tables", C.POINTER(C.c_double)), ("g_samples", C.c_uint32),
+                ("n_nodes", C.c_uint32), ("nodes_yz", C.POINTER(C.c_double)),
+                ("path_begin", C.POINTER(C.c_uint32)), ("path_count", C.POINTER(C.c_uint32)),
+                ("paths_uniform", C.c_uint32), ("max_steps", C.c_uint32), ("dt", C.c_double),
+                ("seed", C.c_uint64), ("stream", C.c_uint32), ("reserved", C.c_uint32)]
+
+
 class sdd_path_record(C.Structure):
     _fields_ = [("w_re", C.c_double), ("w_im", C.c_double), ("tau", C.c_double),
                 ("steps", C.c_uint32), ("wall", C.c_int32)]
@@ -97,6 +107,7 @@ _PROTOS = [
                                     C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     ("sdd_solve_multi_freq", C.c_int, [C.c_void_p, C.POINTER(sdd_request), C.c_uint32, C.POINTER(C.c_double),
                                        C.POINTER(C.POINTER(C.c_double)), C.POINTER(sdd_result)]),
+    ("sdd_solve_kappa", C.c_int, [C.c_void_p, C.POINTER(sdd_kappa_request), C.POINTER(sdd_result)]),
     ("sdd_submit", C.c_int, [C.c_void_p, C.POINTER(sdd_request), C.POINTER(sdd_result), C.POINTER(C.c_uint64)]),
     ("sdd_poll", C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(C.c_int)]),
     ("sdd_wait", C.c_int, [C.c_void_p, C.c_uint64, C.c_int64]),
@@ -178,6 +189,25 @@ class _Req:
                              p.g.shape[1], p.n_nodes, _ptr(self.nodes, C.c_double), _ptr(self.pb, C.c_uint32),
                              _ptr(self.pc, C.c_uint32), 0, p.dt, p.seed, p.stream,
                              min(int(p.max_steps), 0xFFFFFFFF), 0, 0, target_rel_se)
+        self.n = p.n_nodes
+        self.total = int(self.pc.astype(np.uint64).sum())
+
+
+class _KReq:
+    """An sdd_kappa_request (discontinuous kappa) and the numpy buffers it points into."""
+
+    def __init__(self, p):
+        self.g = np.ascontiguousarray(np.stack([p.g.real, p.g.imag], axis=-1).reshape(-1), dtype=np.float64)
+        self.nodes = np.ascontiguousarray(p.nodes, dtype=np.float64).reshape(-1)
+        self.pb = np.ascontiguousarray(p.path_begin, dtype=np.uint32)
+        self.pc = np.ascontiguousarray(p.path_count, dtype=np.uint32)
+        lam = [complex(x) for x in p.lam]
+        d2 = C.c_double * 2
+        self.s = sdd_kappa_request(p.y_lo, p.y_hi, p.z_lo, p.z_hi, p.y_if, d2(*p.kappa),
+                                   d2(*[x.real for x in lam]), d2(*[x.imag for x in lam]),
+                                   _ptr(self.g, C.c_double), p.g.shape[1], p.n_nodes, _ptr(self.nodes, C.c_double),
+                                   _ptr(self.pb, C.c_uint32), _ptr(self.pc, C.c_uint32), 0,
+                                   min(int(p.max_steps), 0xFFFFFFFF), p.dt, p.seed, p.stream, 0)
         self.n = p.n_nodes
         self.total = int(self.pc.astype(np.uint64).sum())
 
@@ -356,6 +386,14 @@ class Context:
         ress = (sdd_result * max(1, len(rs)))(*[r.s for r in rs])
         _check(lib().sdd_solve_multi_freq(self.h, C.byref(q.s), len(tabs), _ptr(fr, C.c_double), ptrs, ress))
         return [r.as_dict() for r in rs]
+
+    def solve_kappa(self, p, records: bool = False):
+        """The discontinuous-kappa walk of a workloads.KappaProblem (one
+        vertical interface; Secs. 2.2 and 3.1), FP64."""
+        q = _KReq(p)
+        r = _Res(q.n, q.total if records else 0)
+        _check(lib().sdd_solve_kappa(self.h, C.byref(q.s), C.byref(r.s)))
+        return r.as_dict()
 
     def solve_plain(self, p, records: bool = False):
         q = _Req(p, self.model(p), SDD_FP64)

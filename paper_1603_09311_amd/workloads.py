@@ -487,3 +487,81 @@ def served_trace(n_requests: int, rate_hz: float, seed: int = 1, paths_cap: int 
             q = q.with_paths(paths_override)
         out.append((t, q))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Discontinuous kappa (the interface scheme of Secs. 2.2, 3.1): one vertical
+# interface, (1/2) div(kappa grad u) - lambda u = 0 with kappa, lambda constant
+# on each side.
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class KappaProblem:
+    y_lo: float
+    y_hi: float
+    z_lo: float
+    z_hi: float
+    y_if: float
+    kappa: Tuple[float, float]            # y < y_if, y >= y_if
+    lam: Tuple[complex, complex]          # killing rate per side
+    g: np.ndarray                         # (4, M+1) complex, walls top, right, bottom, left
+    nodes: np.ndarray
+    path_begin: np.ndarray
+    path_count: np.ndarray
+    dt: float
+    seed: int = 0
+    stream: int = 0
+    max_steps: int = 2_000_000_000
+    name: str = ""
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.nodes.shape[0])
+
+    @property
+    def total_paths(self) -> int:
+        return int(np.sum(self.path_count, dtype=np.int64))
+
+    def replace(self, **kw) -> "KappaProblem":
+        return dataclasses.replace(self, **kw)
+
+    def with_paths(self, paths: int) -> "KappaProblem":
+        n = self.n_nodes
+        return self.replace(path_begin=np.zeros(n, np.uint32), path_count=np.full(n, paths, np.uint32))
+
+
+def kappa_model_field(y, z, lam: complex = 10j, kappa=(1.0, 10.0)):
+    """The analytic test model of Sec. 4.1 (reading: div(kappa grad u) =
+    lambda u, principal roots): (z + 1) cosh(sqrt(lambda / kappa_i) y) on side
+    i of y = 0."""
+    y = np.asarray(y, dtype=np.float64)
+    z = np.asarray(z, dtype=np.float64)
+    k = np.where(y < 0.0, kappa[0], kappa[1])
+    return (z + 1.0) * np.cosh(np.sqrt(lam / k) * y)
+
+
+def kappa_analytic(paths: int = 10000, dt: float = 1e-4, M: int = 4096, seed: int = 0,
+                   nodes: Optional[np.ndarray] = None, lam: complex = 10j, kappa=(1.0, 10.0)) -> KappaProblem:
+    """Sec. 4.1: Omega = [-1, 1]^2, kappa 1 (y < 0) and 10 (y >= 0),
+    div(kappa grad u) = lambda u with lambda = 10 i, i.e. the Eq. (9) form
+    with killing rate lambda / 2 on both sides; g = the exact solution.
+    Default node: (0.6, 0.6), the point of Table 1."""
+    walls = (-1.0, 1.0, -1.0, 1.0)
+    g = tables_from_function(lambda yy, zz: kappa_model_field(yy, zz, lam, kappa), walls, M)
+    if nodes is None:
+        nodes = np.array([[0.6, 0.6]])
+    n = nodes.shape[0]
+    return KappaProblem(*walls, y_if=0.0, kappa=tuple(kappa), lam=(lam / 2.0, lam / 2.0), g=g, nodes=nodes,
+                        path_begin=np.zeros(n, np.uint32), path_count=np.full(n, paths, np.uint32),
+                        dt=dt, seed=seed, name="kappa_analytic")
+
+
+def kappa_analytic_grid(n: int = 51, paths: int = 10000, dt: float = 1e-4, seed: int = 0, M: int = 4096,
+                        lam: complex = 10j, kappa=(1.0, 10.0)) -> KappaProblem:
+    """Sec. 4.1 at every interior point of the uniform n x n mesh of
+    [-1, 1]^2 (the paper: 51 x 51 points, N = 10000 paths per point);
+    nodes y fastest."""
+    y = np.linspace(-1.0, 1.0, n)[1:-1]
+    yy, zz = np.meshgrid(y, y)
+    nodes = np.stack([yy.ravel(), zz.ravel()], axis=1)
+    return kappa_analytic(paths=paths, dt=dt, M=M, seed=seed, nodes=nodes, lam=lam, kappa=kappa).replace(
+        name=f"kappa_analytic_grid_{n}x{n}")

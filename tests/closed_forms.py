@@ -84,3 +84,22 @@ def mt_te_response(e_minus, e_mid, e_plus, h, length_unit_m, freq_hz):
     hx = -dedz / (1j * w * MU0)
     z = np.asarray(e_mid) / hx
     return np.abs(z) ** 2 / (w * MU0), np.degrees(np.angle(z))
+
+
+def kappa_two_sided(lam, kappa, y, z, y_if=0.0):
+    """(1/2) div(kappa grad u) - lam_i u = 0 with kappa_i, lam_i constant on
+    the sides y < y_if (i = 0) and y >= y_if (i = 1): u = (z + 1) f(y) with
+    f = cosh(k_i (y - y_if)) + B_i sinh(k_i (y - y_if)), k_i = sqrt(2 lam_i /
+    kappa_i), B_0 = 1 and B_1 = kappa_0 k_0 / (kappa_1 k_1) (u and the flux
+    kappa du/dy continuous at the interface).  lam = 0 on both sides gives the
+    piecewise-linear f = 1 + (y - y_if) / kappa_i."""
+    y = np.asarray(y, dtype=np.float64) - y_if
+    z = np.asarray(z, dtype=np.float64)
+    lam = [complex(v) for v in lam]
+    if lam[0] == 0 and lam[1] == 0:
+        f = np.where(y < 0, 1.0 + y / kappa[0], 1.0 + y / kappa[1]) + 0j
+    else:
+        k = [np.sqrt(2.0 * lam[i] / kappa[i]) for i in range(2)]
+        b1 = kappa[0] * k[0] / (kappa[1] * k[1])
+        f = np.where(y < 0, np.cosh(k[0] * y) + np.sinh(k[0] * y), np.cosh(k[1] * y) + b1 * np.sinh(k[1] * y))
+    return (z + 1.0) * f

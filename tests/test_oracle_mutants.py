@@ -11,7 +11,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(ROOT, "oracle", "sdd_oracle.c")
 
-# (name, original text, mutated text, pins expected to fail)
+PINS = "test_oracle_pins.py"
+KPINS = "test_kappa_pins.py"
+
+# (name, original text, mutated text, pins expected to fail[, pin file])
 MUTANTS = [
     ("no_bridge", "if (q <= P->dt * L) {", "if (0) {", ["test_mean_exit_time_series"]),
     ("phase_sign", "out->w_im = g[1] * cs - g[0] * sn;", "out->w_im = g[1] * cs + g[0] * sn;",
@@ -31,11 +34,27 @@ MUTANTS = [
      ["test_layered_halfspace_is_1d"]),
     ("region_order", "for (int r = 0; r < P->n_regions; ++r)\n        if (in_primitive",
      "for (int r = P->n_regions - 1; r >= 0; --r)\n        if (in_primitive", ["test_region_predicate"]),
+    # the discontinuous-kappa walk
+    ("kappa_p_swapped", "double pi_ = ki / (ki + kj), pj = 1.0 - pi_;", "double pi_ = kj / (ki + kj), pj = 1.0 - pi_;",
+     ["test_piecewise_linear_harmonic_is_unbiased"], KPINS),
+    ("kappa_side_flipped", "double towards = (si == 0) ? 1.0 : -1.0;", "double towards = (si == 0) ? -1.0 : 1.0;",
+     ["test_piecewise_linear_harmonic_is_unbiased"], KPINS),
+    ("kappa_unequal_radii", "cy = P->y_if + towards * h;", "h = sqrt(kj * dt);\n            cy = P->y_if + towards * h;",
+     ["test_piecewise_linear_harmonic_is_unbiased"], KPINS),
+    ("kappa_printed_share", "T[sj] += 0.5 * (dt - tg) * (2.0 - pj);", "T[sj] += 0.5 * (dt - tg) * (1.0 + pj);",
+     ["test_occupation_shares_sum_to_the_step"], KPINS),
+    ("kappa_rates_swapped", "double ei = -(P->lambda_im[0] * T[0] + P->lambda_im[1] * T[1]);",
+     "double ei = -(P->lambda_im[1] * T[0] + P->lambda_im[0] * T[1]);",
+     ["test_equal_kappa_unequal_lambda_two_sided_closed_form"], KPINS),
+    ("kappa_step_scale", "double s = sqrt(ki * dt);", "double s = sqrt(dt);",
+     ["test_equal_kappa_is_the_constant_coefficient_walk"], KPINS),
+    ("kappa_exit_share", "T[si] += fr * dt;", "T[si] += dt;", ["test_occupation_shares_sum_to_the_step"], KPINS),
 ]
 
 
-@pytest.mark.parametrize("name,orig,mut,pins", MUTANTS, ids=[m[0] for m in MUTANTS])
-def test_mutant_is_caught(name, orig, mut, pins, tmp_path):
+@pytest.mark.parametrize("name,orig,mut,pins,pin_file", [m if len(m) == 5 else (*m, PINS) for m in MUTANTS],
+                         ids=[m[0] for m in MUTANTS])
+def test_mutant_is_caught(name, orig, mut, pins, pin_file, tmp_path):
     src = open(SRC).read()
     assert src.count(orig) == 1, name
     msrc = tmp_path / "mut.c"
@@ -46,6 +65,6 @@ def test_mutant_is_caught(name, orig, mut, pins, tmp_path):
     env = dict(os.environ, SDD_ORACLE_LIB=str(lib))
     sel = " or ".join(pins)
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
-                        os.path.join(HERE, "test_oracle_pins.py"), "-k", sel],
+                        os.path.join(HERE, pin_file), "-k", sel],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode == 1 and " failed" in r.stdout, (name, r.stdout[-2000:])
