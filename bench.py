@@ -58,7 +58,7 @@ OPS_PER_STEP = 18.5 + 3 + 7 + 6 + 4 + 1   # = 39.5
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("sdd_kernels.hip", "sdd_device.h"):
+    for f in ("sdd_kernels.hip", "sdd_device.h", "sdd_rng.h"):
         with open(os.path.join(ROOT, "paper_1603_09311_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

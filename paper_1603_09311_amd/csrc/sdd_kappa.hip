@@ -50,10 +50,18 @@ struct KWalker {
   PhiloxPath pp;
 };
 
-// The record of a path that ended at tangential coordinate t of `wall`.
-__device__ __forceinline__ PathRec kfinish(const KReq &Q, const KWalker &W, int wall, double t, double tau) {
+// Where and when a path ended.
+struct KExit {
+  double t;          // tangential coordinate on the wall
+  double tau;        // exit time
+  int wall;          // 0 top, 1 right, 2 bottom, 3 left; -1 unfinished
+};
+
+// The record of a finished path: g at the exit point times
+// exp(-(lambda_0 T_0 + lambda_1 T_1)).
+__device__ __forceinline__ PathRec kfinish(const KReq &Q, const KWalker &W, const KExit &X) {
   double gre, gim;
-  g_table(Q.g, (int)Q.M, Q.y_lo, Q.y_hi, Q.z_lo, Q.z_hi, wall, t, gre, gim);
+  g_table(Q.g, (int)Q.M, Q.y_lo, Q.y_hi, Q.z_lo, Q.z_hi, X.wall, X.t, gre, gim);
   const double er = -(Q.lre[0] * W.T0 + Q.lre[1] * W.T1);
   const double ei = -(Q.lim[0] * W.T0 + Q.lim[1] * W.T1);
   const double m = exp(er);
@@ -61,15 +69,15 @@ __device__ __forceinline__ PathRec kfinish(const KReq &Q, const KWalker &W, int 
   PathRec r;
   r.w_re = gre * cr - gim * ci;
   r.w_im = gre * ci + gim * cr;
-  r.tau = tau;
+  r.tau = X.tau;
   r.steps = W.n + 1u;
-  r.wall = wall;
+  r.wall = X.wall;
   return r;
 }
 
-// One step with normals (n0, n1).  Returns true when the path ends; its
-// record is then in `out`.
-__device__ __forceinline__ bool kstep(const KReq &Q, KWalker &W, double n0, double n1, PathRec &out) {
+// One step with normals (n0, n1).  Returns true when the path ends at the
+// boundary; where and when is then in `X`.
+__device__ __forceinline__ bool kstep(const KReq &Q, KWalker &W, double n0, double n1, KExit &X) {
   const bool s1 = !(W.y < Q.y_if);                 // side of the current point
   const double kdt = s1 ? Q.kdt[1] : Q.kdt[0];
   const double s = s1 ? Q.s[1] : Q.s[0];
@@ -117,20 +125,19 @@ __device__ __forceinline__ bool kstep(const KReq &Q, KWalker &W, double n0, doub
   if (hy || hz) {
     if (cy) fy = d0y / (d0y - d1y);
     if (cz) fz = d0z / (d0z - d1z);
-    int wall;
-    double f, t;
+    double f;
     if (hy && (!hz || fy <= fz)) {
       f = fy;
-      wall = upy ? 1 : 3;
-      t = fmin(fmax(W.z + fy * (zn - W.z), Q.z_lo), Q.z_hi);
+      X.wall = upy ? 1 : 3;
+      X.t = fmin(fmax(W.z + fy * (zn - W.z), Q.z_lo), Q.z_hi);
     } else {
       f = fz;
-      wall = upz ? 2 : 0;
-      t = fmin(fmax(W.y + fz * (yn - W.y), Q.y_lo), Q.y_hi);
+      X.wall = upz ? 2 : 0;
+      X.t = fmin(fmax(W.y + fz * (yn - W.y), Q.y_lo), Q.y_hi);
     }
     const double occ = f * Q.dt;
     if (s1) W.T1 = W.T1 + occ; else W.T0 = W.T0 + occ;
-    out = kfinish(Q, W, wall, t, ((double)W.n + f) * Q.dt);
+    X.tau = ((double)W.n + f) * Q.dt;
     return true;
   }
 
@@ -190,8 +197,9 @@ __device__ __forceinline__ bool kstep(const KReq &Q, KWalker &W, double n0, doub
     if (dtp < m) { m = dtp; wall = 0; }
     if (db < m) { m = db; wall = 2; }
     const double yy = fmin(fmax(y, Q.y_lo), Q.y_hi), zz = fmin(fmax(z, Q.z_lo), Q.z_hi);
-    const double t = (wall == 0 || wall == 2) ? yy : zz;
-    out = kfinish(Q, W, wall, t, ((double)W.n + 1.0) * Q.dt);
+    X.wall = wall;
+    X.t = (wall == 0 || wall == 2) ? yy : zz;
+    X.tau = ((double)W.n + 1.0) * Q.dt;
     return true;
   }
   W.y = y;
@@ -199,15 +207,6 @@ __device__ __forceinline__ bool kstep(const KReq &Q, KWalker &W, double n0, doub
   return false;
 }
 
-__device__ __forceinline__ PathRec kunfinished(uint32_t steps) {
-  PathRec r;
-  r.w_re = 0.0;
-  r.w_im = 0.0;
-  r.tau = -1.0;
-  r.steps = steps;
-  r.wall = -1;
-  return r;
-}
 
 __global__ void __launch_bounds__(kKappaThreads) walk_kappa(const KReq *__restrict__ qp) {
   const KReq &Q = *qp;
@@ -265,25 +264,31 @@ __global__ void __launch_bounds__(kKappaThreads) walk_kappa(const KReq *__restri
       double a0, a1, b0, b1;
       normals64(w.x, w.y, a0, a1);
       normals64(w.z, w.w, b0, b1);
-      PathRec r;
-      bool end = kstep(Q, W, a0, a1, r);
+      KExit X;
+      X.wall = -1;
+      bool end = kstep(Q, W, a0, a1, X);
       if (!end) {
         W.n += 1u;
-        if (W.n >= Q.max_steps) {
-          end = true;
-          r = kunfinished(W.n);
-        } else {
-          end = kstep(Q, W, b0, b1, r);
+        end = W.n >= Q.max_steps;
+        if (!end) {
+          end = kstep(Q, W, b0, b1, X);
           if (!end) {
             W.n += 1u;
-            if (W.n >= Q.max_steps) {
-              end = true;
-              r = kunfinished(W.n);
-            }
+            end = W.n >= Q.max_steps;
           }
         }
       }
       if (end) {
+        PathRec r;
+        if (X.wall >= 0) {
+          r = kfinish(Q, W, X);
+        } else {   // step cap: W.n == max_steps steps drawn
+          r.w_re = 0.0;
+          r.w_im = 0.0;
+          r.tau = -1.0;
+          r.steps = W.n;
+          r.wall = -1;
+        }
         Q.recs[W.rec] = r;
         active = false;
       }

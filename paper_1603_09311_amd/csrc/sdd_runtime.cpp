@@ -419,35 +419,74 @@ static sdd_status prepare(sdd_ctx *ctx, const sdd_request *r, std::unique_ptr<Pr
   return SDD_OK;
 }
 
-static void build_tiles(Prepared &P, uint32_t tile_paths) {
+// Waves of a typical launch: 4 SIMDs per CU, 4 waves each.
+static uint64_t launch_waves_estimate(sdd_ctx *ctx) { return (uint64_t)std::max(ctx->cus, 1) * 4 * 4; }
+
+// Expected exit time of standard Brownian motion from the rectangle, up to a
+// factor below 2: the harmonic mean of the two 1-D exit times (y - y_lo)
+// (y_hi - y) and (z - z_lo)(z_hi - z).  Used only to order work.
+static double exit_time_estimate(const DevReq &q, double y, double z) {
+  const double a = (y - q.y_lo) * (q.y_hi - y), b = (z - q.z_lo) * (q.z_hi - z);
+  return (a > 0.0 && b > 0.0) ? a * b / (a + b) : 0.0;
+}
+
+// Paths per tile near the end of a request's work: the share of the paths
+// still unclaimed that keeps every wave of a launch (about `waves` of them)
+// busy, down to one path per lane, so the waves run out of work together
+// instead of a few of them finishing whole tiles alone.
+static uint32_t guided_tile(uint64_t remaining, uint64_t waves, uint32_t cap) {
+  uint64_t want = remaining / (2 * std::max<uint64_t>(waves, 1));
+  want = std::max<uint64_t>(want / 64 * 64, 64);
+  return (uint32_t)std::min<uint64_t>(want, std::max<uint32_t>(cap, 1u));
+}
+
+// Tiles of each node's paths (record slots node-major in path order), in the
+// order waves claim them: nodes with the longest expected paths first, so the
+// last tiles of a launch hold short paths, and tile sizes shrink (guided) as
+// the request's paths run out.  Results do not depend on the order or sizes.
+static void build_tiles(Prepared &P, uint32_t cap, uint64_t waves) {
   const uint32_t n = (uint32_t)P.pbeg.size();
   P.tiles.clear();
   P.rec_off.assign(n + 1, 0);
   uint64_t off = 0;
   for (uint32_t j = 0; j < n; ++j) {
     P.rec_off[j] = off;
-    const uint32_t b = P.pbeg[j], c = P.pcnt[j];
-    for (uint32_t k = 0; k < c; k += tile_paths) {
-      DevTile t{};
-      t.node = j;
-      t.p0 = b + k;
-      t.count = std::min(tile_paths, c - k);
-      t.rec0 = off + k;
-      P.tiles.push_back(t);
-    }
-    off += c;
+    off += P.pcnt[j];
   }
   P.rec_off[n] = off;
   P.n_paths = off;
+  std::vector<uint32_t> order(n);
+  std::vector<double> key(n);
+  for (uint32_t j = 0; j < n; ++j) {
+    order[j] = j;
+    key[j] = exit_time_estimate(P.dreq, P.nodes[2 * j], P.nodes[2 * j + 1]);
+  }
+  std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return key[a] > key[b]; });
+  uint64_t remaining = off;
+  for (uint32_t j : order) {
+    const uint32_t b = P.pbeg[j], c = P.pcnt[j];
+    uint32_t k = 0;
+    while (k < c) {
+      const uint32_t cnt = std::min(guided_tile(remaining, waves, cap), c - k);
+      DevTile t{};
+      t.node = j;
+      t.p0 = b + k;
+      t.count = cnt;
+      t.rec0 = P.rec_off[j] + k;
+      P.tiles.push_back(t);
+      k += cnt;
+      remaining -= cnt;
+    }
+  }
 }
 
-// Paths per tile: the tuned size, lowered for a small request so that its
-// tiles reach every wave of a launch instead of queueing behind a few.
+// Largest paths per tile: the tuned size, lowered for a small request so that
+// its tiles reach every wave of a launch instead of queueing behind a few.
 static uint32_t tile_size(sdd_ctx *ctx, const Prepared &P) {
   const uint32_t cap = ctx->tuning.tile_paths ? ctx->tuning.tile_paths : 512u;
   uint64_t total = 0;
   for (uint32_t c : P.pcnt) total += c;
-  const uint64_t waves = (uint64_t)std::max(ctx->cus, 1) * 4 * 4;
+  const uint64_t waves = launch_waves_estimate(ctx);
   const uint64_t per = ((total + waves - 1) / waves + 63) / 64 * 64;
   return (uint32_t)std::min<uint64_t>(cap, std::max<uint64_t>(per, 64));
 }
@@ -473,7 +512,7 @@ static void release_all(sdd_ctx *ctx, Prepared &P) {
 
 // Allocate and upload one pass's inputs (caller holds ctx->mu).
 static sdd_status upload_pass(sdd_ctx *ctx, Prepared &P) {
-  build_tiles(P, tile_size(ctx, P));
+  build_tiles(P, tile_size(ctx, P), launch_waves_estimate(ctx));
   P.d_g = ctx->alloc(P.g.size() * 8);
   P.d_nodes = ctx->alloc(P.nodes.size() * 8 + 16);
   P.d_tiles = ctx->alloc(P.tiles.size() * sizeof(DevTile) + 16);
@@ -810,7 +849,7 @@ static sdd_status execute(sdd_ctx *ctx, std::vector<Prepared *> &Ps, std::vector
 // Workspace a request needs while it runs (upper bound for target-SE
 // requests, whose extension size is known only after the pilot).
 static uint64_t footprint(sdd_ctx *ctx, Prepared &P) {
-  build_tiles(P, tile_size(ctx, P));
+  build_tiles(P, tile_size(ctx, P), launch_waves_estimate(ctx));
   const uint64_t n = P.pbeg.size();
   uint64_t b = pass_bytes(P) + Arena::round(n * (sizeof(NodeOut) + sizeof(NodeJob))) + 4 * 1024 +
                Arena::round(sizeof(DevReq) * 2);
@@ -1594,27 +1633,47 @@ sdd_status sdd_solve_kappa(sdd_ctx_t ctx, const sdd_kappa_request *r, sdd_result
   if (n == 0) return SDD_OK;
   if (!res->mean) return fail(SDD_E_INVALID, "result mean is NULL");
 
-  // tiles of one node's paths, record slots node-major in path order
+  // tiles of one node's paths, record slots node-major in path order; claimed
+  // longest expected paths first, sizes guided as for sdd_solve
   const uint32_t tile_paths = ctx->tuning.tile_paths ? ctx->tuning.tile_paths : 512u;
   std::vector<DevTile> tiles;
   std::vector<uint64_t> rec_off(n + 1, 0);
   uint64_t total = 0;
   for (uint32_t j = 0; j < n; ++j) {
     rec_off[j] = total;
-    const uint32_t b = r->path_begin ? r->path_begin[j] : 0u;
-    const uint32_t c = r->path_count ? r->path_count[j] : r->paths_uniform;
-    for (uint32_t k = 0; k < c; k += tile_paths) {
-      DevTile t{};
-      t.node = j;
-      t.p0 = b + k;
-      t.count = std::min(tile_paths, c - k);
-      t.rec0 = total + k;
-      tiles.push_back(t);
-      if (c - k <= tile_paths) break;
-    }
-    total += c;
+    total += r->path_count ? r->path_count[j] : r->paths_uniform;
   }
   rec_off[n] = total;
+  {
+    DevReq walls{};
+    walls.y_lo = r->y_lo; walls.y_hi = r->y_hi; walls.z_lo = r->z_lo; walls.z_hi = r->z_hi;
+    std::vector<uint32_t> order(n);
+    std::vector<double> key(n);
+    for (uint32_t j = 0; j < n; ++j) {
+      const double y = r->nodes_yz[2 * j], z = r->nodes_yz[2 * j + 1];
+      order[j] = j;
+      key[j] = exit_time_estimate(walls, y, z) / r->kappa[y < r->y_if ? 0 : 1];
+    }
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return key[a] > key[b]; });
+    const uint64_t waves = launch_waves_estimate(ctx);
+    uint64_t remaining = total;
+    for (uint32_t j : order) {
+      const uint32_t b = r->path_begin ? r->path_begin[j] : 0u;
+      const uint32_t c = r->path_count ? r->path_count[j] : r->paths_uniform;
+      uint32_t k = 0;
+      while (k < c) {
+        const uint32_t cnt = std::min(guided_tile(remaining, waves, tile_paths), c - k);
+        DevTile t{};
+        t.node = j;
+        t.p0 = b + k;
+        t.count = cnt;
+        t.rec0 = rec_off[j] + k;
+        tiles.push_back(t);
+        k += cnt;
+        remaining -= cnt;
+      }
+    }
+  }
   if (tiles.size() >= (1ull << 32)) return fail(SDD_E_INVALID, "too many tiles");
 
   KReq K{};
