@@ -118,7 +118,11 @@ struct DevReq {
   // weight (w_re = S at this request's frequency, w_im = tangential exit
   // coordinate), for weights at other frequencies computed afterwards
   uint32_t fanout;
-  int32_t sig_pad[2];
+  // step caps of the FP32 walk, which starts every pair of steps at an even
+  // step index n: the pair is the last one when n >= cap2 (max_steps - 2, or
+  // 0), and then its first step is the last allowed iff max_steps is odd
+  uint32_t cap2;
+  uint32_t cap_odd;
   float sigp[12];
   // streams and limits
   uint32_t key0, key1;  // Philox key (seed low, high)

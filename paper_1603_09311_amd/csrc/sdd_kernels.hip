@@ -434,13 +434,14 @@ struct X32 {
 
 template <int SIG> struct U32 {
   float hy, hz, K, dt, thr, scr;
-  uint32_t k0, k1, ctr3, max_steps, cap1, cap2;
+  uint32_t k0, k1, ctr3, max_steps, cap2;
+  bool cap_odd;
   Reg32<SIG> reg;
   __device__ __forceinline__ void load(const DevReq &Q) {
     hy = Q.fhy; hz = Q.fhz; K = Q.fK; dt = Q.fdt; thr = Q.fthr; scr = Q.fscr;
     k0 = Q.key0; k1 = Q.key1; ctr3 = Q.ctr3; max_steps = Q.max_steps;
-    cap1 = max_steps - 1u;                          // n >= cap1: step n is the last allowed
-    cap2 = max_steps >= 2u ? max_steps - 2u : 0u;   // n >= cap2: step n + 1 is
+    cap2 = Q.cap2;
+    cap_odd = Q.cap_odd != 0u;
     reg.load(Q);
   }
 };
@@ -587,12 +588,15 @@ __device__ __forceinline__ int iterate32(const DevReq &Q, const U32<SIG> &U, W32
   const uint4 w = philox_pp(W.P, U.ctr3, W.pp, U.k0, U.k1);
   const uint32_t n = W.n;
   const bool exA = step32<SIG>(Q, U, W, w.x, w.y, true, n, X);
-  const bool capA = n >= U.cap1;
+  // step caps (n is even here): the pair is the last one when n >= cap2, and
+  // its first step is then the last allowed iff max_steps is odd
+  const bool near = n >= U.cap2;
+  const bool capA = near && U.cap_odd;
   const bool exB = step32<SIG>(Q, U, W, w.z, w.w, !exA && !capA, n + 1u, X);
   W.n = n + 2u;
   W.P += (uint64_t)kM0;
   if (exA || exB) return 1;
-  return (capA || n >= U.cap2) ? 2 : 0;
+  return near ? 2 : 0;
 }
 
 // Precision traits for the persistent loop.
@@ -739,66 +743,68 @@ __device__ __forceinline__ bool run_request(const DevReq &Q, uint32_t budget, ui
     // refill every (refill_mask + 1) iterations, and whenever every lane is idle
     const bool refill = ((iters & refill_mask) == 0u) || (freemask == ~0ull);
     if (!refill) freemask = 0ull;
-    // resume walkers suspended by the previous slice first
-    if (freemask != 0ull && !pool_done) {
-      const uint32_t nfree = (uint32_t)__popcll(freemask);
-      const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(freemask >> 32),
-                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)freemask, 0u));
-      uint32_t base = 0;
-      if (lane == 0) base = atomicAdd(ctl + kPoolCursor, nfree);
-      base = uni(base);
-      const uint32_t avail = base < Q.pool_in_n ? min(nfree, Q.pool_in_n - base) : 0u;
-      if (avail < nfree) pool_done = true;
-      if (!active && rank < avail) {
-        T::resume(Q, U, W, Q.pool_in[base + rank]);
-        active = true;
-      }
-      freemask = __builtin_amdgcn_ballot_w64(!active);
-    }
-    // then refill free lanes in rank order from the wave's tile, claiming
-    // tile remainders of the previous slice before new tiles
-    if (freemask != 0ull && !exhausted) {
-      const uint32_t nfree = (uint32_t)__popcll(freemask);
-      const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(freemask >> 32),
-                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)freemask, 0u));
-      uint32_t given = 0;
-      while (given < nfree) {
-        if (t_next == t_end) {
-          const DevTile *src = nullptr;
-          if (!extra_done) {
-            uint32_t e = 0;
-            if (lane == 0) e = atomicAdd(ctl + kExtraCursor, 1u);
-            e = uni(e);
-            if (e < Q.extra_in_n) src = Q.extra_in + e;
-            else extra_done = true;
-          }
-          if (src == nullptr) {
-            uint32_t t = 0;
-            if (lane == 0) t = atomicAdd(Q.tile_counter, 1u);
-            t = uni(t);
-            if (t >= n_tiles) { exhausted = true; break; }
-            src = Q.tiles + t;
-          }
-          const DevTile Tl = *src;
-          t_node = uni(Tl.node);
-          t_p0 = uni(Tl.p0);
-          t_next = t_p0;
-          t_end = t_p0 + uni(Tl.count);
-          t_rec0 = ((uint64_t)uni((uint32_t)(Tl.rec0 >> 32)) << 32) | uni((uint32_t)Tl.rec0);
-        }
-        const uint32_t take = min(t_end - t_next, nfree - given);
-        if (!active && rank >= given && rank < given + take) {
-          const uint32_t p = t_next + (rank - given);
-          T::start(Q, U, W, t_node, p, t_rec0 + (p - t_p0));
+    // (with every lane busy, or between refills, nothing below changes `active`)
+    if (freemask != 0ull) {
+      // resume walkers suspended by the previous slice first
+      if (!pool_done) {
+        const uint32_t nfree = (uint32_t)__popcll(freemask);
+        const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(freemask >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)freemask, 0u));
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(ctl + kPoolCursor, nfree);
+        base = uni(base);
+        const uint32_t avail = base < Q.pool_in_n ? min(nfree, Q.pool_in_n - base) : 0u;
+        if (avail < nfree) pool_done = true;
+        if (!active && rank < avail) {
+          T::resume(Q, U, W, Q.pool_in[base + rank]);
           active = true;
         }
-        t_next += take;
-        given += take;
+        freemask = __builtin_amdgcn_ballot_w64(!active);
       }
+      // then refill free lanes in rank order from the wave's tile, claiming
+      // tile remainders of the previous slice before new tiles
+      if (freemask != 0ull && !exhausted) {
+        const uint32_t nfree = (uint32_t)__popcll(freemask);
+        const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(freemask >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)freemask, 0u));
+        uint32_t given = 0;
+        while (given < nfree) {
+          if (t_next == t_end) {
+            const DevTile *src = nullptr;
+            if (!extra_done) {
+              uint32_t e = 0;
+              if (lane == 0) e = atomicAdd(ctl + kExtraCursor, 1u);
+              e = uni(e);
+              if (e < Q.extra_in_n) src = Q.extra_in + e;
+              else extra_done = true;
+            }
+            if (src == nullptr) {
+              uint32_t t = 0;
+              if (lane == 0) t = atomicAdd(Q.tile_counter, 1u);
+              t = uni(t);
+              if (t >= n_tiles) { exhausted = true; break; }
+              src = Q.tiles + t;
+            }
+            const DevTile Tl = *src;
+            t_node = uni(Tl.node);
+            t_p0 = uni(Tl.p0);
+            t_next = t_p0;
+            t_end = t_p0 + uni(Tl.count);
+            t_rec0 = ((uint64_t)uni((uint32_t)(Tl.rec0 >> 32)) << 32) | uni((uint32_t)Tl.rec0);
+          }
+          const uint32_t take = min(t_end - t_next, nfree - given);
+          if (!active && rank >= given && rank < given + take) {
+            const uint32_t p = t_next + (rank - given);
+            T::start(Q, U, W, t_node, p, t_rec0 + (p - t_p0));
+            active = true;
+          }
+          t_next += take;
+          given += take;
+        }
+      }
+      // every lane idle after a refill: this wave can get no more work here
+      if (__builtin_amdgcn_ballot_w64(!active) == ~0ull) break;
     }
-    // every lane idle after a refill: this wave can get no more work here
-    const uint64_t freemask_after_refill = __builtin_amdgcn_ballot_w64(!active);
-    if (freemask_after_refill == ~0ull) break;
 
     if (active) {
       typename T::Exit X;

@@ -379,6 +379,8 @@ static void fill_devreq(Prepared &P) {
   q.key1 = (uint32_t)(r.seed >> 32);
   q.ctr3 = 2u * r.stream;
   q.max_steps = r.max_steps ? r.max_steps : kDefaultMaxSteps;
+  q.cap2 = q.max_steps >= 2u ? q.max_steps - 2u : 0u;
+  q.cap_odd = q.max_steps & 1u;
   q.precision = (uint32_t)r.precision;
   q.M = r.g_samples - 1;
   q.model = reinterpret_cast<const DevModel *>(m.dev);
