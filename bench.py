@@ -49,11 +49,12 @@ VALU_PEAK = CUS * SIMDS * LANES * CLOCK
 # 1 product + 2 xors = 3; round 1, 1 xor = 1; counter product update = 1.
 #   Philox4x32-10, half a call                                 37/2 = 18.5
 #   uniforms: radius (align + exact subtract), angle (align)         =  3
-#   Box-Muller + proposal (log2, sqrt, mul, cos, sin, 2 fma)         =  7
+#   Box-Muller + proposal (log2, sqrt, cos, sin, 2 fma; positions in
+#   units of the step scale, so no multiply)                          =  6
 #   exit screen, both axes (2 sub |.|, 2 mul, min, compare)          =  6
 #   region of the proposal: 2 tests, 2 count increments              =  4
 #   step counter and cap (one add and one compare per two steps)     =  1
-OPS_PER_STEP = 18.5 + 3 + 7 + 6 + 4 + 1   # = 39.5
+OPS_PER_STEP = 18.5 + 3 + 6 + 6 + 4 + 1   # = 38.5
 
 
 def kernel_source_hash() -> str:

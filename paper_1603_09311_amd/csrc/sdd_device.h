@@ -98,17 +98,18 @@ struct DevReq {
   double dt;
   double thr;          // bridge pre-filter: draw U only if 2 d0 d1 <= thr
   double ymid, zmid;   // centre of the domain (origin of the FP32 walk)
+  double kscale;       // K = sqrt(dt) sqrt(2 ln 2), the FP32 walk's length unit
+  double kinv;         // 1 / K
   double c[kMaxRegions + 1];   // phase per full step: alpha_r dt / 2 (background at [nprims])
-  // FP32-mixed walk: coordinates relative to (ymid, zmid), walls at +-h
-  float fhy, fhz;      // half-widths
-  float fs, fdt;       // sqrt(dt), dt
-  float fthr;          // 16.7 dt, compared with 2 d0 d1 (FP32 uniforms are >= 2^-24)
+  // FP32-mixed walk: coordinates relative to (ymid, zmid) in units of K, so a
+  // step is sqrt(-log2 u) (cos, sin) and the bridge test 2 d0 d1 <= dt (-ln U)
+  // reads 2 d0 d1 <= -log2(U) / 2; walls at +-h
+  float fhy, fhz;      // half-widths / K
+  float fthr;          // 12.05 > 24 / 2, compared with 2 d0 d1 (FP32 uniforms are >= 2^-24)
   float fscr;          // fthr / 2, compared with d0 d1' in the per-step screen
-  float fK;            // sqrt(dt) sqrt(2 ln 2): step length per sqrt(-log2 u)
-  float fpad;
   float fc[kMaxRegions + 3];
   // model signature (which specialised region lookup the walkers use) and its
-  // FP32 parameters in centred coordinates:
+  // FP32 parameters in centred coordinates (units of K):
   //   kSigZ:    [z0]                      air above z0
   //   kSigZY:   [z0, y1]                  + half-space y < y1
   //   kSigZBox: [z0, y0, y1, zb0, zb1]    + box

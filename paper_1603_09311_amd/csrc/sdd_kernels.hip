@@ -433,12 +433,12 @@ struct X32 {
 };
 
 template <int SIG> struct U32 {
-  float hy, hz, K, dt, thr, scr;
+  float hy, hz, thr, scr;
   uint32_t k0, k1, ctr3, max_steps, cap2;
   bool cap_odd;
   Reg32<SIG> reg;
   __device__ __forceinline__ void load(const DevReq &Q) {
-    hy = Q.fhy; hz = Q.fhz; K = Q.fK; dt = Q.fdt; thr = Q.fthr; scr = Q.fscr;
+    hy = Q.fhy; hz = Q.fhz; thr = Q.fthr; scr = Q.fscr;
     k0 = Q.key0; k1 = Q.key1; ctr3 = Q.ctr3; max_steps = Q.max_steps;
     cap2 = Q.cap2;
     cap_odd = Q.cap_odd != 0u;
@@ -453,16 +453,16 @@ __device__ __forceinline__ float one_frac32(uint32_t w) {
 // (2 (w >> 9) + 1) 2^-24: exact in FP32 (the subtraction is exact), in (0, 1).
 __device__ __forceinline__ float u01_32(uint32_t w) { return one_frac32(w) - 0x1.fffffep-1f; }
 
-__device__ __forceinline__ float neglog32(uint32_t w) {
-  return -0.69314718055994531f * __builtin_amdgcn_logf(u01_32(w));
-}
+// dt (-ln U) in the FP32 walk's squared length unit K^2 = 2 ln 2 dt:
+// -log2(U) / 2.
+__device__ __forceinline__ float bridge_len32(uint32_t w) { return -0.5f * __builtin_amdgcn_logf(u01_32(w)); }
 
 // Box-Muller and the Euler-Maruyama proposal in one: with the hardware log2,
-// sqrt(-2 ln u) sqrt(dt) = K sqrt(-log2 u), K = sqrt(dt) sqrt(2 ln 2); the
-// angle is in revolutions (v_sin/v_cos_f32), and 1 + k 2^-23 is the same
-// angle as k 2^-23.
-__device__ __forceinline__ void propose32(float K, float a, float b, uint32_t wa, uint32_t wb, float &an, float &bn) {
-  const float rk = K * __builtin_amdgcn_sqrtf(-__builtin_amdgcn_logf(u01_32(wa)));
+// sqrt(-2 ln u) sqrt(dt) = K sqrt(-log2 u), K = sqrt(dt) sqrt(2 ln 2), and
+// positions are in units of K; the angle is in revolutions (v_sin/v_cos_f32),
+// and 1 + k 2^-23 is the same angle as k 2^-23.
+__device__ __forceinline__ void propose32(float a, float b, uint32_t wa, uint32_t wb, float &an, float &bn) {
+  const float rk = __builtin_amdgcn_sqrtf(-__builtin_amdgcn_logf(u01_32(wa)));
   const float ang = one_frac32(wb);
   an = __builtin_fmaf(__builtin_amdgcn_cosf(ang), rk, a);
   bn = __builtin_fmaf(__builtin_amdgcn_sinf(ang), rk, b);
@@ -472,8 +472,8 @@ template <int SIG>
 __device__ __forceinline__ void start32(const DevReq &Q, const U32<SIG> &U, W32 &W, uint32_t node, uint32_t path,
                                         uint64_t rec) {
   const double2 p = *reinterpret_cast<const double2 *>(Q.nodes + 2 * (size_t)node);
-  W.a = (float)(p.x - Q.ymid);
-  W.b = (float)(p.y - Q.zmid);
+  W.a = (float)((p.x - Q.ymid) * Q.kinv);
+  W.b = (float)((p.y - Q.zmid) * Q.kinv);
   W.d0y = U.hy - fabsf(W.a);
   W.d0z = U.hz - fabsf(W.b);
   W.n0 = 0;
@@ -507,11 +507,11 @@ __device__ __forceinline__ bool exit32(const DevReq &Q, const U32<SIG> &U, const
     const uint64_t Pn = (W.P << 1) + ((nstep & 1u) ? (uint64_t)kM0 : 0ull);
     const uint4 u = philox_pp(Pn, U.ctr3 + 1u, W.pp, U.k0, U.k1);
     if (ny) {
-      const float L = U.dt * neglog32(u.x);
+      const float L = bridge_len32(u.x);
       if (qy <= L) { hy = true; fy = qy * __builtin_amdgcn_rcpf(L); }
     }
     if (nz) {
-      const float L = U.dt * neglog32(u.y);
+      const float L = bridge_len32(u.y);
       if (qz <= L) { hz = true; fz = qz * __builtin_amdgcn_rcpf(L); }
     }
   }
@@ -545,7 +545,7 @@ template <int SIG>
 __device__ __forceinline__ bool step32(const DevReq &Q, const U32<SIG> &U, W32 &W, uint32_t wa, uint32_t wb,
                                        bool live, uint32_t nstep, X32 &X) {
   float an, bn;
-  propose32(U.K, W.a, W.b, wa, wb, an, bn);
+  propose32(W.a, W.b, wa, wb, an, bn);
   const float e1y = U.hy - fabsf(an);
   const float e1z = U.hz - fabsf(bn);
   bool ex = false;
@@ -571,7 +571,7 @@ __device__ __forceinline__ bool step32(const DevReq &Q, const U32<SIG> &U, W32 &
 __device__ __forceinline__ PathRec finish32(const DevReq &Q, const X32 &X) {
   const double S = X.S;
   const bool along_y = (X.wall == 0) || (X.wall == 2);
-  double t = (double)X.t + (along_y ? Q.ymid : Q.zmid);
+  double t = (double)X.t * Q.kscale + (along_y ? Q.ymid : Q.zmid);
   const double lo = along_y ? Q.y_lo : Q.z_lo, hi = along_y ? Q.y_hi : Q.z_hi;
   t = t < lo ? lo : (t > hi ? hi : t);
   PathRec r;

@@ -56,8 +56,9 @@ __device__ __forceinline__ PhiloxPath philox_path(uint32_t path, uint32_t node, 
 // Philox4x32-10 of the counter (c0, path, node, c3) given P0 = M0 * c0.
 __device__ __forceinline__ uint4 philox_pp(uint64_t P0, uint32_t c3, const PhiloxPath &pp, uint32_t k0,
                                            uint32_t k1) {
-  // round 1 gives (x0, x1, hi(P0) ^ c3 ^ k1, lo(P0)); round 2 (key + W):
-  const uint32_t r1w2 = xor3((uint32_t)(P0 >> 32), c3, k1);
+  // round 1 gives (x0, x1, hi(P0) ^ c3 ^ k1, lo(P0)); round 2 (key + W).
+  // c3 ^ k1 is wave-uniform: one scalar XOR, then one vector XOR.
+  const uint32_t r1w2 = (uint32_t)(P0 >> 32) ^ (c3 ^ k1);
   const uint32_t r1w3 = (uint32_t)P0;
   const uint64_t p1 = (uint64_t)kM1 * (uint64_t)r1w2;
   uint32_t w0 = xor3((uint32_t)(p1 >> 32), pp.x1, k0 + kW0);

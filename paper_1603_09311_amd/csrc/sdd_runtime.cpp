@@ -305,9 +305,13 @@ static void fill_devreq(Prepared &P) {
   q.dt = r.dt;
   q.s = std::sqrt(r.dt);
   q.thr = 22.9 * r.dt;
-  // the FP32 walk measures positions from the centre of the domain
+  // the FP32 walk measures positions from the centre of the domain, in units
+  // of K = sqrt(dt) sqrt(2 ln 2) (the step length per sqrt(-log2 u))
   q.ymid = 0.5 * (q.y_lo + q.y_hi);
   q.zmid = 0.5 * (q.z_lo + q.z_hi);
+  q.kscale = q.s * std::sqrt(2.0 * std::log(2.0));
+  q.kinv = 1.0 / q.kscale;
+  const double ki = q.kinv;
   const uint32_t np = (uint32_t)m.regions.size();
   q.nprims = np;
   for (uint32_t k = 0; k < np; ++k) {
@@ -315,18 +319,18 @@ static void fill_devreq(Prepared &P) {
     q.kind[k] = m.regions[k].kind;
     const double *v = m.regions[k].v;
     for (int i = 0; i < 6; ++i) q.pd[k][i] = v[i];
-    // centred FP32 geometry: y-coordinates minus ymid, z-coordinates minus zmid
+    // centred FP32 geometry in units of K: (y - ymid) / K, (z - zmid) / K
     switch (m.regions[k].kind) {
-      case SDD_HALF_Z_LT: q.pf[k][0] = (float)(v[0] - q.zmid); break;
-      case SDD_HALF_Y_LT: q.pf[k][0] = (float)(v[0] - q.ymid); break;
+      case SDD_HALF_Z_LT: q.pf[k][0] = (float)((v[0] - q.zmid) * ki); break;
+      case SDD_HALF_Y_LT: q.pf[k][0] = (float)((v[0] - q.ymid) * ki); break;
       case SDD_BOX:
-        q.pf[k][0] = (float)(v[0] - q.ymid); q.pf[k][1] = (float)(v[1] - q.ymid);
-        q.pf[k][2] = (float)(v[2] - q.zmid); q.pf[k][3] = (float)(v[3] - q.zmid);
+        q.pf[k][0] = (float)((v[0] - q.ymid) * ki); q.pf[k][1] = (float)((v[1] - q.ymid) * ki);
+        q.pf[k][2] = (float)((v[2] - q.zmid) * ki); q.pf[k][3] = (float)((v[3] - q.zmid) * ki);
         break;
       default:
         for (int i = 0; i < 6; i += 2) {
-          q.pf[k][i] = (float)(v[i] - q.ymid);
-          q.pf[k][i + 1] = (float)(v[i + 1] - q.zmid);
+          q.pf[k][i] = (float)((v[i] - q.ymid) * ki);
+          q.pf[k][i + 1] = (float)((v[i + 1] - q.zmid) * ki);
         }
     }
   }
@@ -337,25 +341,26 @@ static void fill_devreq(Prepared &P) {
   if (np == 0) {
     q.sig = kSigNone;
   } else if (R[0].kind == SDD_HALF_Z_LT && np <= 2) {
-    q.sigp[0] = (float)(R[0].v[0] - q.zmid);
+    q.sigp[0] = (float)((R[0].v[0] - q.zmid) * ki);
     if (np == 1) {
       q.sig = kSigZ;
     } else if (R[1].kind == SDD_HALF_Y_LT) {
       q.sig = kSigZY;
-      q.sigp[1] = (float)(R[1].v[0] - q.ymid);
+      q.sigp[1] = (float)((R[1].v[0] - q.ymid) * ki);
     } else if (R[1].kind == SDD_BOX) {
       q.sig = kSigZBox;
-      q.sigp[1] = (float)(R[1].v[0] - q.ymid);
-      q.sigp[2] = (float)(R[1].v[1] - q.ymid);
-      q.sigp[3] = (float)(R[1].v[2] - q.zmid);
-      q.sigp[4] = (float)(R[1].v[3] - q.zmid);
+      q.sigp[1] = (float)((R[1].v[0] - q.ymid) * ki);
+      q.sigp[2] = (float)((R[1].v[1] - q.ymid) * ki);
+      q.sigp[3] = (float)((R[1].v[2] - q.zmid) * ki);
+      q.sigp[4] = (float)((R[1].v[3] - q.zmid) * ki);
     } else if (R[1].kind == SDD_TRIANGLE) {
       q.sig = kSigZTri;
-      // edge k from vertex k to vertex k+1 as A a + B b + C in centred coordinates
+      // edge k from vertex k to vertex k+1 as A a + B b + C in centred
+      // coordinates (units of K)
       double vy[3], vz[3];
       for (int i = 0; i < 3; ++i) {
-        vy[i] = R[1].v[2 * i] - q.ymid;
-        vz[i] = R[1].v[2 * i + 1] - q.zmid;
+        vy[i] = (R[1].v[2 * i] - q.ymid) * ki;
+        vz[i] = (R[1].v[2 * i + 1] - q.zmid) * ki;
       }
       for (int k = 0; k < 3; ++k) {
         const int l = (k + 1) % 3;
@@ -365,15 +370,12 @@ static void fill_devreq(Prepared &P) {
       }
     }
   }
-  q.fhy = (float)(0.5 * (q.y_hi - q.y_lo));
-  q.fhz = (float)(0.5 * (q.z_hi - q.z_lo));
-  q.fs = (float)q.s;
-  q.fdt = (float)q.dt;
-  // FP32 uniforms are at least 2^-24, so -ln U <= 24 ln 2 = 16.64: no bridge
-  // hit is possible once 2 d0 d1 > 16.7 dt
-  q.fthr = 16.7f * q.fdt;
+  q.fhy = (float)(0.5 * (q.y_hi - q.y_lo) * ki);
+  q.fhz = (float)(0.5 * (q.z_hi - q.z_lo) * ki);
+  // FP32 uniforms are at least 2^-24, so -log2(U) / 2 <= 12: no bridge hit is
+  // possible once 2 d0 d1 > 12.05 (16.7 dt in unscaled lengths)
+  q.fthr = 12.05f;
   q.fscr = 0.5f * q.fthr;
-  q.fK = (float)(q.s * std::sqrt(2.0 * std::log(2.0)));
   for (uint32_t k = 0; k <= np; ++k) q.fc[k] = (float)q.c[k];
   q.key0 = (uint32_t)(r.seed & 0xFFFFFFFFu);
   q.key1 = (uint32_t)(r.seed >> 32);
