@@ -381,14 +381,19 @@ def main():
         r64 = ctx.solve(sub)
         t_p64 = ctx.stats()["last_walk_ms"]
         sub32 = sub.replace(precision=W.FP32_MIXED)
-        ctx.solve(sub32)
+        r32 = ctx.solve(sub32)
         t_p32 = ctx.stats()["last_walk_ms"]
+        d32 = r32["mean"] - r64["mean"]
+        fp32_z = float(max(np.max(np.abs(d32.real) / r64["se_re"]), np.max(np.abs(d32.imag) / r64["se_im"])))
         out["comparison"] = {
             "subset": f"{sub.n_nodes} nodes x {args.paths} paths",
             "plain_fp64_walk_steps_per_s": s_plain / (t_plain * 1e-3),
             "persistent_fp64_walk_steps_per_s": s_plain / (t_p64 * 1e-3),
             "persistent_fp32_walk_steps_per_s": s_plain / (t_p32 * 1e-3),
             "fp64_persistent_equals_plain": bool(np.array_equal(r["mean"], r64["mean"])),
+            # the FP32-mixed walk against the FP64 walk on the same streams, per node and
+            # component, in units of the FP64 standard error
+            "fp32_vs_fp64_max_abs_z": fp32_z,
         }
         log(f"comparison: {out['comparison']}")
 
