@@ -74,7 +74,7 @@ def test_harmonic_and_cosh_second_order(solver):
 def test_layered_1d_reproduced(solver):
     """A sub-domain inside a uniform layer of the quarter-space ground, with
     the layered 1-D solution on its boundary: the solution everywhere inside
-    (the pin the survey names)."""
+    is the 1-D one (a field that depends on depth only)."""
     regions = [W.Region(W.HALF_Z_LT, (0.0,), 0.0)]
     tops, sig = W.column_layers(regions, 0.01, 0.0, -6.0)
     al = W._alpha_of(np.asarray(sig), 1.0, W.DELTA1, 0.0)
