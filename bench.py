@@ -302,8 +302,8 @@ def main():
     ap.add_argument("--served-rate", type=float, default=8.0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the walk shards by node and path "
-              "tile across GPUs by design, but this build measures one MI355X.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the walk would shard by node and "
+              "path tile across GPUs, but only the one-GPU path is implemented and measured.", file=sys.stderr)
         sys.exit(2)
 
     import torch
