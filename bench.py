@@ -134,31 +134,41 @@ def kappa_leg(ctx, n: int = 51, paths: int = 10000, dt: float = 1e-4, repeats: i
     """The discontinuous-kappa walk (Secs. 2.2, 3.1) on the analytic test
     model of Sec. 4.1 (kappa 1 | 10, lambda = 10 i) at every interior point
     of the n x n mesh with `paths` paths each (the paper: 51 x 51, 10000),
-    FP64: walk kernel time and rate, and the error against the exact
-    solution next to the Monte-Carlo error."""
+    in FP64 and FP32-mixed: walk kernel time and rate, the error against the
+    exact solution next to the Monte-Carlo error, and the FP32-mixed result
+    against the FP64 one on the same streams."""
+    from paper_1603_09311_amd import sdd as S
     from paper_1603_09311_amd import workloads as W
     kp = W.kappa_analytic_grid(n=n, paths=paths, dt=dt)
-    walls, kms = [], []
-    for _ in range(repeats):
-        t0 = time.perf_counter()
-        r = ctx.solve_kappa(kp)
-        walls.append(time.perf_counter() - t0)
-        kms.append(ctx.stats()["last_walk_ms"])
-    steps = float(r["steps"].sum())
     exact = W.kappa_model_field(kp.nodes[:, 0], kp.nodes[:, 1])
-    err = np.abs(r["mean"] - exact)
-    k_ms = float(np.median(kms))
     i06 = int(np.argmin(np.hypot(kp.nodes[:, 0] - 0.6, kp.nodes[:, 1] - 0.6)))
-    st = ctx.stats()
-    return {"workload": kp.name, "nodes": kp.n_nodes, "paths_per_node": paths, "dt": dt,
-            "kappa": list(kp.kappa), "lambda": "10i", "walk_steps": steps, "walk_kernel_ms": k_ms,
-            "walk_steps_per_s": steps / (k_ms * 1e-3), "nodes_per_s": kp.n_nodes / (k_ms * 1e-3),
-            "solve_wall_s_from_host_buffers": float(np.median(walls)),
-            "launch": {"blocks": st["last_blocks"], "threads": st["last_threads"]},
-            "max_abs_error": float(err.max()), "median_error_over_se": float(np.median(err / r["se"])),
-            "error_at_0.6_0.6": [float(abs((r["mean"][i06] - exact[i06]).real)),
-                                 float(abs((r["mean"][i06] - exact[i06]).imag))],
-            "table1_error_at_0.6_0.6_N1e4": [0.0086, 0.0067], "_kp": kp}
+    out = {"workload": kp.name, "nodes": kp.n_nodes, "paths_per_node": paths, "dt": dt,
+           "kappa": list(kp.kappa), "lambda": "10i", "table1_error_at_0.6_0.6_N1e4": [0.0086, 0.0067]}
+    res = {}
+    for name, prec in (("fp64", S.SDD_FP64), ("fp32", S.SDD_FP32_MIXED)):
+        walls, kms = [], []
+        for _ in range(repeats):
+            t0 = time.perf_counter()
+            r = ctx.solve_kappa(kp, precision=prec)
+            walls.append(time.perf_counter() - t0)
+            kms.append(ctx.stats()["last_walk_ms"])
+        st = ctx.stats()
+        steps = float(r["steps"].sum())
+        k_ms = float(np.median(kms))
+        err = np.abs(r["mean"] - exact)
+        res[name] = r
+        out[name] = {"walk_steps": steps, "walk_kernel_ms": k_ms, "walk_steps_per_s": steps / (k_ms * 1e-3),
+                     "nodes_per_s": kp.n_nodes / (k_ms * 1e-3),
+                     "solve_wall_s_from_host_buffers": float(np.median(walls)),
+                     "launch": {"blocks": st["last_blocks"], "threads": st["last_threads"]},
+                     "max_abs_error": float(err.max()), "median_error_over_se": float(np.median(err / r["se"])),
+                     "error_at_0.6_0.6": [float(abs((r["mean"][i06] - exact[i06]).real)),
+                                          float(abs((r["mean"][i06] - exact[i06]).imag))]}
+    d = res["fp32"]["mean"] - res["fp64"]["mean"]
+    out["fp32_vs_fp64_max_abs_z"] = float(max(np.nanmax(np.abs(d.real) / res["fp64"]["se_re"]),
+                                              np.nanmax(np.abs(d.imag) / res["fp64"]["se_im"])))
+    out["_kp"] = kp
+    return out
 
 
 def served_leg(ctx, n_requests: int, rate_hz: float, paths: int):

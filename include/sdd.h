@@ -349,13 +349,18 @@ typedef struct {
     double dt;                      /* 7 sqrt(max kappa dt) < half the shorter side */
     uint64_t seed;
     uint32_t stream;                /* < 2^30 */
-    uint32_t reserved;              /* 0 */
+    uint32_t precision;             /* SDD_FP64, or SDD_FP32_MIXED: positions, normals and tests in FP32
+                                       (hardware log2, sqrt, sin, cos), the same random numbers, full
+                                       steps counted per side, interface time shares and the weight in
+                                       FP64 */
 } sdd_kappa_request;
 
 /* Solve a discontinuous-kappa request on the context's stream.  Results per
  * node in `res` as for sdd_solve (path_records, when not NULL, receive every
  * path's record: w = the path's value).  Inputs are host memory and are
- * copied; the call returns when the results are on the host.
+ * copied; the call returns when the results are on the host.  SDD_FP64 is
+ * the parity form (the arithmetic of a plain FP64 reading of the scheme);
+ * SDD_FP32_MIXED walks the same paths up to FP32 rounding.
  * Errors: SDD_E_INVALID (NULL pointers, a value outside the ranges above, a
  * node not strictly inside Omega, a node with no paths or whose path range
  * passes 2^32, more than 2^40 paths), SDD_E_NOMEM (workspace), SDD_E_DEVICE. */

@@ -175,6 +175,18 @@ struct KReq {
   uint32_t n_tiles, M, key0, key1, ctr3, max_steps;
   uint32_t equal_kappa;   // kappa_0 == kappa_1: no interface rule
   uint32_t pad;
+  // FP32-mixed walk: positions relative to (ymid, zmid)
+  double ymid, zmid;
+  float fhy, fhz;      // half-widths
+  float fa_if;         // interface y_if - ymid
+  float fdt, frdt;     // dt, 1 / dt
+  float fK[2];         // sqrt(kappa_i dt) sqrt(2 ln 2): step length per sqrt(-log2 u)
+  float fs[2];         // sqrt(kappa_i dt): disc radius
+  float fthr[2];       // 16.7 kappa_i dt (FP32 uniforms are >= 2^-24)
+  float fkdt[2];       // kappa_i dt
+  float fkappa[2];
+  float fp[2];         // kappa_i / (kappa_0 + kappa_1)
+  float fpad;
 };
 
 }  // namespace sdd

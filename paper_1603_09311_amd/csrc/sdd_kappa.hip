@@ -57,20 +57,20 @@ struct KExit {
   int wall;          // 0 top, 1 right, 2 bottom, 3 left; -1 unfinished
 };
 
-// The record of a finished path: g at the exit point times
+// The record of a path that ended at step n: g at the exit point times
 // exp(-(lambda_0 T_0 + lambda_1 T_1)).
-__device__ __forceinline__ PathRec kfinish(const KReq &Q, const KWalker &W, const KExit &X) {
+__device__ __forceinline__ PathRec kfinish(const KReq &Q, double T0, double T1, uint32_t n, const KExit &X) {
   double gre, gim;
   g_table(Q.g, (int)Q.M, Q.y_lo, Q.y_hi, Q.z_lo, Q.z_hi, X.wall, X.t, gre, gim);
-  const double er = -(Q.lre[0] * W.T0 + Q.lre[1] * W.T1);
-  const double ei = -(Q.lim[0] * W.T0 + Q.lim[1] * W.T1);
+  const double er = -(Q.lre[0] * T0 + Q.lre[1] * T1);
+  const double ei = -(Q.lim[0] * T0 + Q.lim[1] * T1);
   const double m = exp(er);
   const double cr = m * cos(ei), ci = m * sin(ei);
   PathRec r;
   r.w_re = gre * cr - gim * ci;
   r.w_im = gre * ci + gim * cr;
   r.tau = X.tau;
-  r.steps = W.n + 1u;
+  r.steps = n + 1u;
   r.wall = X.wall;
   return r;
 }
@@ -208,10 +208,229 @@ __device__ __forceinline__ bool kstep(const KReq &Q, KWalker &W, double n0, doub
 }
 
 
+// The FP64 walk: two steps per normal draw (a walker is at an even step at
+// the start of a pair).  Returns 0 running, 1 exited (X), 2 step cap.
+struct K64 {
+  using Walker = KWalker;
+  static __device__ __forceinline__ void start(const KReq &, Walker &W, double2 xy, uint32_t p, uint32_t node,
+                                               uint64_t rec, uint32_t k0) {
+    W.y = xy.x;
+    W.z = xy.y;
+    W.T0 = 0.0;
+    W.T1 = 0.0;
+    W.n = 0u;
+    W.rec = rec;
+    W.pp = philox_path(p, node, k0);
+  }
+  static __device__ __forceinline__ int pair(const KReq &Q, Walker &W, KExit &X) {
+    const uint64_t P = (uint64_t)kM0 * (uint64_t)(W.n >> 1);
+    const uint4 w = philox_pp(P, Q.ctr3, W.pp, Q.key0, Q.key1);
+    double a0, a1, b0, b1;
+    normals64(w.x, w.y, a0, a1);
+    normals64(w.z, w.w, b0, b1);
+    if (kstep(Q, W, a0, a1, X)) return 1;
+    W.n += 1u;
+    if (W.n >= Q.max_steps) return 2;
+    if (kstep(Q, W, b0, b1, X)) return 1;
+    W.n += 1u;
+    return W.n >= Q.max_steps ? 2 : 0;
+  }
+  static __device__ __forceinline__ PathRec finish(const KReq &Q, const Walker &W, const KExit &X) {
+    return kfinish(Q, W.T0, W.T1, W.n, X);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// FP32-mixed walk: positions relative to the domain centre in FP32, the
+// hardware log2, sqrt, sin and cos (angles in revolutions), the same random
+// numbers as the FP64 walk (so the two are paired); full steps counted per
+// side in integers, the interface shares and the exit fraction of the
+// occupation times summed in FP64, the weight in FP64.
+// ---------------------------------------------------------------------------
+struct KWalker32 {
+  float a, b;        // y - ymid, z - zmid
+  uint32_t c0, c1;   // full steps on side 0 / side 1
+  double f0, f1;     // the rest of the occupation times (interface shares, exit fraction)
+  uint32_t n;
+  uint64_t rec;
+  PhiloxPath pp;
+};
+
+__device__ __forceinline__ float one_frac_k(uint32_t w) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_alignbit(0x7Fu, w, 9u));
+}
+// (2 (w >> 9) + 1) 2^-24, exact, in (0, 1)
+__device__ __forceinline__ float u01_k(uint32_t w) { return one_frac_k(w) - 0x1.fffffep-1f; }
+// -ln u
+__device__ __forceinline__ float neglog_k(uint32_t w) {
+  return -0.69314718055994531f * __builtin_amdgcn_logf(u01_k(w));
+}
+
+__device__ __forceinline__ bool kstep32(const KReq &Q, KWalker32 &W, uint32_t wa, uint32_t wb, KExit &X) {
+  const bool s1 = !(W.a < Q.fa_if);
+  const float K = s1 ? Q.fK[1] : Q.fK[0];
+  const float thr = s1 ? Q.fthr[1] : Q.fthr[0];
+  const float rk = K * __builtin_amdgcn_sqrtf(-__builtin_amdgcn_logf(u01_k(wa)));
+  const float ang = one_frac_k(wb);
+  const float an = __builtin_fmaf(__builtin_amdgcn_cosf(ang), rk, W.a);
+  const float bn = __builtin_fmaf(__builtin_amdgcn_sinf(ang), rk, W.b);
+
+  // outer boundary: nearer wall per axis (a tie goes to the lower wall)
+  const bool upy = W.a > 0.f, upz = W.b > 0.f;
+  const float d0y = Q.fhy - fabsf(W.a), d0z = Q.fhz - fabsf(W.b);
+  const float d1y = upy ? (Q.fhy - an) : (Q.fhy + an);
+  const float d1z = upz ? (Q.fhz - bn) : (Q.fhz + bn);
+  const bool cy = d1y <= 0.f, cz = d1z <= 0.f;
+  const float qy = (2.f * d0y) * d1y, qz = (2.f * d0z) * d1z;
+  const bool by = !cy && (qy <= thr), bz = !cz && (qz <= thr);
+
+  // interface candidates
+  const bool sn1 = !(an < Q.fa_if);
+  const bool jump = !Q.equal_kappa;
+  const float e0 = fabsf(W.a - Q.fa_if), e1 = fabsf(an - Q.fa_if);
+  const bool crossed = jump && (sn1 != s1);
+  const bool bridge_if = jump && !crossed && ((2.f * e0) * e1 <= thr);
+
+  uint4 u = make_uint4(0u, 0u, 0u, 0u);
+  if (by || bz || crossed || bridge_if) {
+    const uint64_t Pn = (uint64_t)kM0 * (uint64_t)W.n;
+    u = philox_pp(Pn, Q.ctr3 + 1u, W.pp, Q.key0, Q.key1);
+  }
+  const float kdt = s1 ? Q.fkdt[1] : Q.fkdt[0];
+  bool hy = cy, hz = cz;
+  float fy = 0.f, fz = 0.f;
+  if (by) {
+    const float L = kdt * neglog_k(u.x);
+    if (qy <= L) { hy = true; fy = qy * __builtin_amdgcn_rcpf(L); }
+  }
+  if (bz) {
+    const float L = kdt * neglog_k(u.y);
+    if (qz <= L) { hz = true; fz = qz * __builtin_amdgcn_rcpf(L); }
+  }
+  if (hy || hz) {
+    if (cy) fy = d0y * __builtin_amdgcn_rcpf(d0y - d1y);
+    if (cz) fz = d0z * __builtin_amdgcn_rcpf(d0z - d1z);
+    float f, t;
+    if (hy && (!hz || fy <= fz)) {
+      f = fminf(fy, 1.f);
+      X.wall = upy ? 1 : 3;
+      t = fminf(fmaxf(__builtin_fmaf(f, bn - W.b, W.b), -Q.fhz), Q.fhz);
+      X.t = (double)t + Q.zmid;
+    } else {
+      f = fminf(fz, 1.f);
+      X.wall = upz ? 2 : 0;
+      t = fminf(fmaxf(__builtin_fmaf(f, an - W.a, W.a), -Q.fhy), Q.fhy);
+      X.t = (double)t + Q.ymid;
+    }
+    const double occ = (double)f * Q.dt;
+    if (s1) W.f1 += occ; else W.f0 += occ;
+    X.tau = ((double)W.n + (double)f) * Q.dt;
+    return true;
+  }
+
+  if (!jump) {                                     // equal kappa: no regime change
+    if (sn1) W.c1 += 1u; else W.c0 += 1u;
+    W.a = an;
+    W.b = bn;
+    return false;
+  }
+  float tg = 0.f;
+  bool reached = crossed;
+  if (crossed) {
+    tg = Q.fdt * (e0 * __builtin_amdgcn_rcpf(fabsf(an - W.a)));
+  } else if (bridge_if) {
+    const float ki = s1 ? Q.fkappa[1] : Q.fkappa[0];
+    tg = ((2.f * e0) * e1) * __builtin_amdgcn_rcpf(ki * neglog_k(u.z));
+    reached = tg <= Q.fdt;
+  }
+  if (!reached) {
+    if (s1) W.c1 += 1u; else W.c0 += 1u;
+    W.a = an;
+    W.b = bn;
+    return false;
+  }
+
+  // resume inside a disc touching the interface from side i or side j
+  const float pi = s1 ? Q.fp[1] : Q.fp[0];
+  const float h = s1 ? Q.fs[1] : Q.fs[0];
+  const float zg = __builtin_fmaf(fminf(tg * Q.frdt, 1.f), bn - W.b, W.b);   // interface point
+  const float towards = s1 ? -1.f : 1.f;
+  const double half = 0.5 * (Q.dt - (double)tg);
+  float cyc;
+  double add_i, add_j;
+  if (u01_k(u.w) < pi) {
+    cyc = Q.fa_if - towards * h;
+    add_i = Q.dt - half * (double)pi;
+    add_j = half * (double)pi;
+  } else {
+    const double pj = 1.0 - (double)pi;
+    cyc = Q.fa_if + towards * h;
+    add_i = (double)tg + half * pj;
+    add_j = half * (2.0 - pj);
+  }
+  W.f0 += s1 ? add_j : add_i;
+  W.f1 += s1 ? add_i : add_j;
+  const uint64_t Pn = (uint64_t)kM0 * (uint64_t)W.n;
+  const uint4 d = philox_pp(Pn, Q.ctr3 + 2u, W.pp, Q.key0, Q.key1);
+  const float r = h * __builtin_amdgcn_sqrtf(u01_k(d.x));
+  const float th = one_frac_k(d.y);
+  const float a = __builtin_fmaf(__builtin_amdgcn_cosf(th), r, cyc);
+  const float bb = __builtin_fmaf(__builtin_amdgcn_sinf(th), r, zg);
+  if (!(fabsf(a) < Q.fhy && fabsf(bb) < Q.fhz)) {
+    // the nearest boundary point (ties in the order left, right, top, bottom)
+    const float dl = Q.fhy + a, dr = Q.fhy - a, dtp = Q.fhz + bb, db = Q.fhz - bb;
+    float m = dl;
+    int wall = 3;
+    if (dr < m) { m = dr; wall = 1; }
+    if (dtp < m) { m = dtp; wall = 0; }
+    if (db < m) { m = db; wall = 2; }
+    const float yy = fminf(fmaxf(a, -Q.fhy), Q.fhy), zz = fminf(fmaxf(bb, -Q.fhz), Q.fhz);
+    X.wall = wall;
+    X.t = (wall == 0 || wall == 2) ? (double)yy + Q.ymid : (double)zz + Q.zmid;
+    X.tau = ((double)W.n + 1.0) * Q.dt;
+    return true;
+  }
+  W.a = a;
+  W.b = bb;
+  return false;
+}
+
+struct K32 {
+  using Walker = KWalker32;
+  static __device__ __forceinline__ void start(const KReq &Q, Walker &W, double2 xy, uint32_t p, uint32_t node,
+                                               uint64_t rec, uint32_t k0) {
+    W.a = (float)(xy.x - Q.ymid);
+    W.b = (float)(xy.y - Q.zmid);
+    W.c0 = 0u;
+    W.c1 = 0u;
+    W.f0 = 0.0;
+    W.f1 = 0.0;
+    W.n = 0u;
+    W.rec = rec;
+    W.pp = philox_path(p, node, k0);
+  }
+  static __device__ __forceinline__ int pair(const KReq &Q, Walker &W, KExit &X) {
+    const uint64_t P = (uint64_t)kM0 * (uint64_t)(W.n >> 1);
+    const uint4 w = philox_pp(P, Q.ctr3, W.pp, Q.key0, Q.key1);
+    if (kstep32(Q, W, w.x, w.y, X)) return 1;
+    W.n += 1u;
+    if (W.n >= Q.max_steps) return 2;
+    if (kstep32(Q, W, w.z, w.w, X)) return 1;
+    W.n += 1u;
+    return W.n >= Q.max_steps ? 2 : 0;
+  }
+  static __device__ __forceinline__ PathRec finish(const KReq &Q, const Walker &W, const KExit &X) {
+    const double T0 = Q.dt * (double)W.c0 + W.f0;
+    const double T1 = Q.dt * (double)W.c1 + W.f1;
+    return kfinish(Q, T0, T1, W.n, X);
+  }
+};
+
+template <class T>
 __global__ void __launch_bounds__(kKappaThreads) walk_kappa(const KReq *__restrict__ qp) {
   const KReq &Q = *qp;
   const uint32_t lane = __lane_id();
-  KWalker W;
+  typename T::Walker W;
   bool active = false;
   bool exhausted = false;
   // wave-uniform tile cursor
@@ -242,13 +461,7 @@ __global__ void __launch_bounds__(kKappaThreads) walk_kappa(const KReq *__restri
         if (!active && rank >= given && rank < given + take) {
           const uint32_t p = t_next + (rank - given);
           const double2 xy = *reinterpret_cast<const double2 *>(Q.nodes + 2 * (size_t)t_node);
-          W.y = xy.x;
-          W.z = xy.y;
-          W.T0 = 0.0;
-          W.T1 = 0.0;
-          W.n = 0u;
-          W.rec = t_rec0 + (p - t_p0);
-          W.pp = philox_path(p, t_node, Q.key0);
+          T::start(Q, W, xy, p, t_node, t_rec0 + (p - t_p0), Q.key0);
           active = true;
         }
         t_next += take;
@@ -258,31 +471,14 @@ __global__ void __launch_bounds__(kKappaThreads) walk_kappa(const KReq *__restri
     if (__builtin_amdgcn_ballot_w64(!active) == ~0ull) break;   // no work left for this wave
 
     if (active) {
-      // two steps per normal draw; a walker is at an even step here
-      const uint64_t P = (uint64_t)kM0 * (uint64_t)(W.n >> 1);
-      const uint4 w = philox_pp(P, Q.ctr3, W.pp, Q.key0, Q.key1);
-      double a0, a1, b0, b1;
-      normals64(w.x, w.y, a0, a1);
-      normals64(w.z, w.w, b0, b1);
       KExit X;
       X.wall = -1;
-      bool end = kstep(Q, W, a0, a1, X);
-      if (!end) {
-        W.n += 1u;
-        end = W.n >= Q.max_steps;
-        if (!end) {
-          end = kstep(Q, W, b0, b1, X);
-          if (!end) {
-            W.n += 1u;
-            end = W.n >= Q.max_steps;
-          }
-        }
-      }
-      if (end) {
+      const int st = T::pair(Q, W, X);
+      if (st != 0) {
         PathRec r;
-        if (X.wall >= 0) {
-          r = kfinish(Q, W, X);
-        } else {   // step cap: W.n == max_steps steps drawn
+        if (st == 1) {
+          r = T::finish(Q, W, X);
+        } else {   // step cap: max_steps steps drawn
           r.w_re = 0.0;
           r.w_im = 0.0;
           r.tau = -1.0;
@@ -298,15 +494,18 @@ __global__ void __launch_bounds__(kKappaThreads) walk_kappa(const KReq *__restri
 
 }  // namespace
 
-hipError_t launch_walk_kappa(const KReq *req_dev, uint32_t blocks, hipStream_t st) {
+hipError_t launch_walk_kappa(int precision, const KReq *req_dev, uint32_t blocks, hipStream_t st) {
   if (blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(walk_kappa, dim3(blocks), dim3(kKappaThreads), 0, st, req_dev);
+  if (precision == 1) hipLaunchKernelGGL(walk_kappa<K32>, dim3(blocks), dim3(kKappaThreads), 0, st, req_dev);
+  else hipLaunchKernelGGL(walk_kappa<K64>, dim3(blocks), dim3(kKappaThreads), 0, st, req_dev);
   return hipGetLastError();
 }
 
-int kappa_blocks_per_cu() {
+int kappa_blocks_per_cu(int precision) {
   int nb = 0;
-  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_kappa, (int)kKappaThreads, 0);
+  const hipError_t e = precision == 1
+      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_kappa<K32>, (int)kKappaThreads, 0)
+      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_kappa<K64>, (int)kKappaThreads, 0);
   return e == hipSuccess ? nb : 0;
 }
 

@@ -37,8 +37,8 @@ hipError_t launch_reduce_fanout(const FanJob *jobs_dev, uint32_t n_jobs, int M, 
                                 double z_hi, hipStream_t st);
 hipError_t launch_reset(uint32_t *tile_counters, unsigned long long *done, uint32_t n, hipStream_t st);
 int persist_blocks_per_cu(int precision, int sig, uint32_t threads);
-hipError_t launch_walk_kappa(const KReq *req_dev, uint32_t blocks, hipStream_t st);
-int kappa_blocks_per_cu();
+hipError_t launch_walk_kappa(int precision, const KReq *req_dev, uint32_t blocks, hipStream_t st);
+int kappa_blocks_per_cu(int precision);
 uint32_t kappa_threads();
 }  // namespace sdd
 
@@ -1609,7 +1609,8 @@ static sdd_status validate_kappa(const sdd_kappa_request *r) {
   if (!(7.0 * std::sqrt(std::max(r->kappa[0], r->kappa[1]) * r->dt) < half))
     return fail(SDD_E_INVALID, "dt too large: 7 sqrt(kappa dt) must be below half the shorter side");
   if (r->stream >= (1u << 30)) return fail(SDD_E_INVALID, "stream must be < 2^30");
-  if (r->reserved != 0) return fail(SDD_E_INVALID, "reserved must be 0");
+  if (r->precision != SDD_FP64 && r->precision != SDD_FP32_MIXED)
+    return fail(SDD_E_INVALID, "precision must be SDD_FP64 or SDD_FP32_MIXED");
   if (r->g_samples < 2 || !r->g_tables) return fail(SDD_E_INVALID, "g_tables need >= 2 samples per wall");
   for (size_t k = 0; k < (size_t)8 * r->g_samples; ++k)
     if (!fin(r->g_tables[k])) return fail(SDD_E_INVALID, "g_tables must be finite");
@@ -1701,6 +1702,23 @@ sdd_status sdd_solve_kappa(sdd_ctx_t ctx, const sdd_kappa_request *r, sdd_result
   K.ctr3 = 4u * r->stream;
   K.max_steps = r->max_steps ? r->max_steps : kDefaultMaxSteps;
   K.equal_kappa = r->kappa[0] == r->kappa[1] ? 1u : 0u;
+  K.ymid = 0.5 * (r->y_lo + r->y_hi);
+  K.zmid = 0.5 * (r->z_lo + r->z_hi);
+  K.fhy = (float)(0.5 * (r->y_hi - r->y_lo));
+  K.fhz = (float)(0.5 * (r->z_hi - r->z_lo));
+  K.fa_if = (float)(r->y_if - K.ymid);
+  K.fdt = (float)r->dt;
+  K.frdt = (float)(1.0 / r->dt);
+  for (int i = 0; i < 2; ++i) {
+    K.fK[i] = (float)(K.s[i] * std::sqrt(2.0 * std::log(2.0)));
+    K.fs[i] = (float)K.s[i];
+    // FP32 uniforms are at least 2^-24, so -ln U <= 16.64: no bridge hit is
+    // possible once 2 d0 d1 > 16.7 kappa_i dt
+    K.fthr[i] = (float)(16.7 * K.kdt[i]);
+    K.fkdt[i] = (float)K.kdt[i];
+    K.fkappa[i] = (float)r->kappa[i];
+    K.fp[i] = (float)K.p[i];
+  }
 
   ExecGuard ex(ctx);
   HIP_TRY(hipSetDevice(ctx->device));
@@ -1735,7 +1753,7 @@ sdd_status sdd_solve_kappa(sdd_ctx_t ctx, const sdd_kappa_request *r, sdd_result
   }
   const uint32_t threads = kappa_threads();
   const uint32_t waves_per_block = threads / 64u;
-  const int bpc = std::max(kappa_blocks_per_cu(), 1);
+  const int bpc = std::max(kappa_blocks_per_cu((int)r->precision), 1);
   uint32_t blocks = (uint32_t)std::max(ctx->cus, 1) * (uint32_t)bpc;
   blocks = std::max<uint32_t>(1u, std::min<uint32_t>(blocks, (K.n_tiles + waves_per_block - 1) / waves_per_block));
   const uint32_t zero = 0u;
@@ -1748,7 +1766,7 @@ sdd_status sdd_solve_kappa(sdd_ctx_t ctx, const sdd_kappa_request *r, sdd_result
   if (e == hipSuccess) e = hipMemcpyAsync(d_ctr, &zero, sizeof(zero), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(d_jobs, jobs.data(), jobs.size() * sizeof(NodeJob), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipEventRecord(ctx->ev[0], s);
-  if (e == hipSuccess) e = launch_walk_kappa(reinterpret_cast<const KReq *>(d_req), blocks, s);
+  if (e == hipSuccess) e = launch_walk_kappa((int)r->precision, reinterpret_cast<const KReq *>(d_req), blocks, s);
   if (e == hipSuccess) e = hipEventRecord(ctx->ev[1], s);
   if (e == hipSuccess) e = launch_reduce(reinterpret_cast<const NodeJob *>(d_jobs), n, s);
   if (e == hipSuccess) e = hipEventRecord(ctx->ev[2], s);

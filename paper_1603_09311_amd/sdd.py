@@ -55,7 +55,7 @@ class sdd_kappa_request(C.Structure):
                 ("n_nodes", C.c_uint32), ("nodes_yz", C.POINTER(C.c_double)),
                 ("path_begin", C.POINTER(C.c_uint32)), ("path_count", C.POINTER(C.c_uint32)),
                 ("paths_uniform", C.c_uint32), ("max_steps", C.c_uint32), ("dt", C.c_double),
-                ("seed", C.c_uint64), ("stream", C.c_uint32), ("reserved", C.c_uint32)]
+                ("seed", C.c_uint64), ("stream", C.c_uint32), ("precision", C.c_uint32)]
 
 
 class sdd_path_record(C.Structure):
@@ -196,7 +196,7 @@ class _Req:
 class _KReq:
     """An sdd_kappa_request (discontinuous kappa) and the numpy buffers it points into."""
 
-    def __init__(self, p):
+    def __init__(self, p, precision: int = 0):
         self.g = np.ascontiguousarray(np.stack([p.g.real, p.g.imag], axis=-1).reshape(-1), dtype=np.float64)
         self.nodes = np.ascontiguousarray(p.nodes, dtype=np.float64).reshape(-1)
         self.pb = np.ascontiguousarray(p.path_begin, dtype=np.uint32)
@@ -207,7 +207,7 @@ class _KReq:
                                    d2(*[x.real for x in lam]), d2(*[x.imag for x in lam]),
                                    _ptr(self.g, C.c_double), p.g.shape[1], p.n_nodes, _ptr(self.nodes, C.c_double),
                                    _ptr(self.pb, C.c_uint32), _ptr(self.pc, C.c_uint32), 0,
-                                   min(int(p.max_steps), 0xFFFFFFFF), p.dt, p.seed, p.stream, 0)
+                                   min(int(p.max_steps), 0xFFFFFFFF), p.dt, p.seed, p.stream, precision)
         self.n = p.n_nodes
         self.total = int(self.pc.astype(np.uint64).sum())
 
@@ -387,10 +387,11 @@ class Context:
         _check(lib().sdd_solve_multi_freq(self.h, C.byref(q.s), len(tabs), _ptr(fr, C.c_double), ptrs, ress))
         return [r.as_dict() for r in rs]
 
-    def solve_kappa(self, p, records: bool = False):
+    def solve_kappa(self, p, records: bool = False, precision: int = 0):
         """The discontinuous-kappa walk of a workloads.KappaProblem (one
-        vertical interface; Secs. 2.2 and 3.1), FP64."""
-        q = _KReq(p)
+        vertical interface; Secs. 2.2 and 3.1): SDD_FP64 (default) or
+        SDD_FP32_MIXED."""
+        q = _KReq(p, precision)
         r = _Res(q.n, q.total if records else 0)
         _check(lib().sdd_solve_kappa(self.h, C.byref(q.s), C.byref(r.s)))
         return r.as_dict()

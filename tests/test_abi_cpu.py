@@ -63,7 +63,7 @@ def test_struct_layouts_match_header(tmp_path):
                    'printf("%zu %zu %zu %zu\\n", offsetof(sdd_request, dt), offsetof(sdd_request, target_rel_se),'
                    ' offsetof(sdd_result, path_records), offsetof(sdd_model_desc, regions));\n'
                    'printf("%zu %zu %zu %zu\\n", sizeof(sdd_kappa_request), offsetof(sdd_kappa_request, g_tables),'
-                   ' offsetof(sdd_kappa_request, dt), offsetof(sdd_kappa_request, reserved));\nreturn 0;}\n')
+                   ' offsetof(sdd_kappa_request, dt), offsetof(sdd_kappa_request, precision));\nreturn 0;}\n')
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     a, b, c = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")[:3]
@@ -74,7 +74,7 @@ def test_struct_layouts_match_header(tmp_path):
             sdd.sdd_model_desc.regions.offset]
     assert [int(x) for x in b.split()] == offs
     K = sdd.sdd_kappa_request
-    assert [int(x) for x in c.split()] == [C.sizeof(K), K.g_tables.offset, K.dt.offset, K.reserved.offset]
+    assert [int(x) for x in c.split()] == [C.sizeof(K), K.g_tables.offset, K.dt.offset, K.precision.offset]
 
 
 def test_product_path_never_reaches_the_oracle():

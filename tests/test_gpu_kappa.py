@@ -170,3 +170,71 @@ def test_kappa_analytic_grid_sampled_at_full_size(ctx, orc):
     # interface bias at dt = 1e-4 measured on the oracle at a few hundredths at most
     assert np.all(err <= 5.0 * g["se"] + 0.03), (err - 5 * g["se"]).max()
     assert np.median(err / g["se"]) < 1.5
+
+
+# ---------------------------------------------------------------------------
+# FP32-mixed kappa walk: same random numbers, FP32 rounding.
+# ---------------------------------------------------------------------------
+FP32 = sdd.SDD_FP32_MIXED
+
+
+def assert_within_3se(g, o):
+    e_o = o["mean_re"] + 1j * o["mean_im"]
+    d = g["mean"] - e_o
+    z = np.concatenate([np.abs(d.real) / o["se_re"], np.abs(d.imag) / o["se_im"]])
+    z = z[np.isfinite(z)]
+    assert z.max() <= 3.0, z.max()
+    from scipy import stats
+    assert np.sum(z ** 2) <= stats.chi2.ppf(0.999, z.size)
+
+
+def test_kappa_fp32_within_3se_and_paired_with_fp64(ctx, orc):
+    for kappa in ((1.0, 10.0), (10.0, 1.0), (3.0, 3.0)):
+        p = two_media(paths=4000, kappa=kappa)
+        log(f"kappa fp32: kappa={kappa} nodes={p.n_nodes} paths={p.total_paths}")
+        g32 = ctx.solve_kappa(p, precision=FP32)
+        g64 = ctx.solve_kappa(p)
+        o, _ = orc.ksolve(p)
+        assert_within_3se(g32, o)
+        assert_fp64_parity(g64, o)
+        # the same paths up to rounding: far inside the Monte-Carlo error
+        se = np.hypot(g64["se_re"], g64["se_im"])
+        assert np.all(np.abs(g32["mean"] - g64["mean"]) <= 0.5 * se)
+        assert np.all(g32["unfinished"] == 0)
+
+
+def test_kappa_fp32_launch_shape_and_caps(ctx):
+    p = two_media(paths=777)
+    ref = ctx.solve_kappa(p, records=True, precision=FP32)
+    try:
+        for tile in (64, 4096):
+            ctx.set_tuning(tile_paths=tile)
+            g = ctx.solve_kappa(p, records=True, precision=FP32)
+            assert g["records"].tobytes() == ref["records"].tobytes(), tile
+    finally:
+        ctx.set_tuning()
+    for cap in (1, 2, 3, 40):
+        g = ctx.solve_kappa(two_media(paths=200).replace(max_steps=cap), records=True, precision=FP32)
+        rec = g["records"]
+        assert np.all(rec["steps"] <= cap)
+        assert np.all((rec["wall"] >= 0) | (rec["steps"] == cap))
+    with pytest.raises(sdd.SddError):
+        ctx.solve_kappa(p, precision=2)
+
+
+def test_kappa_fp32_analytic_grid_full_size(ctx):
+    """Sec. 4.1 on the full 51 x 51 mesh (10000 paths per node): FP32-mixed
+    against the FP64 walk on the same streams, and against the exact
+    solution as for FP64."""
+    p = W.kappa_analytic_grid()
+    g32 = ctx.solve_kappa(p, precision=FP32)
+    ms32 = ctx.stats()["last_walk_ms"]
+    g64 = ctx.solve_kappa(p)
+    log(f"kappa grid fp32 walk {ms32:.1f} ms, fp64 {ctx.stats()['last_walk_ms']:.1f} ms")
+    z = np.concatenate([np.abs((g32["mean"] - g64["mean"]).real) / g64["se_re"],
+                        np.abs((g32["mean"] - g64["mean"]).imag) / g64["se_im"]])
+    assert np.nanmax(z) <= 3.0, np.nanmax(z)
+    exact = W.kappa_model_field(p.nodes[:, 0], p.nodes[:, 1])
+    err = np.abs(g32["mean"] - exact)
+    assert np.all(g32["unfinished"] == 0)
+    assert np.all(err <= 5.0 * g32["se"] + 0.03)
