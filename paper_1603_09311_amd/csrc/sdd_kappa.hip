@@ -1,6 +1,7 @@
-// HIP kernel for gfx950: the walk of (1/2) div(kappa grad u) - lambda u = 0
+// HIP kernels for gfx950: the walk of (1/2) div(kappa grad u) - lambda u = 0
 // (Eq. 9) when kappa and lambda are constant on each side of one vertical
-// interface y = y_if, in FP64 (Secs. 2.2 and 3.1).
+// interface y = y_if (Secs. 2.2 and 3.1): walk_kappa64 in FP64 (the parity
+// form) and walk_kappa32, FP32-mixed, on the same random numbers.
 //
 // Away from the interface the process is sqrt(kappa_i) times Brownian motion
 // (Eq. 10): a step is the Euler-Maruyama proposal of Eq. (13) with kappa_i.
@@ -208,38 +209,6 @@ __device__ __forceinline__ bool kstep(const KReq &Q, KWalker &W, double n0, doub
 }
 
 
-// The FP64 walk: two steps per normal draw (a walker is at an even step at
-// the start of a pair).  Returns 0 running, 1 exited (X), 2 step cap.
-struct K64 {
-  using Walker = KWalker;
-  static __device__ __forceinline__ void start(const KReq &, Walker &W, double2 xy, uint32_t p, uint32_t node,
-                                               uint64_t rec, uint32_t k0) {
-    W.y = xy.x;
-    W.z = xy.y;
-    W.T0 = 0.0;
-    W.T1 = 0.0;
-    W.n = 0u;
-    W.rec = rec;
-    W.pp = philox_path(p, node, k0);
-  }
-  static __device__ __forceinline__ int pair(const KReq &Q, Walker &W, KExit &X) {
-    const uint64_t P = (uint64_t)kM0 * (uint64_t)(W.n >> 1);
-    const uint4 w = philox_pp(P, Q.ctr3, W.pp, Q.key0, Q.key1);
-    double a0, a1, b0, b1;
-    normals64(w.x, w.y, a0, a1);
-    normals64(w.z, w.w, b0, b1);
-    if (kstep(Q, W, a0, a1, X)) return 1;
-    W.n += 1u;
-    if (W.n >= Q.max_steps) return 2;
-    if (kstep(Q, W, b0, b1, X)) return 1;
-    W.n += 1u;
-    return W.n >= Q.max_steps ? 2 : 0;
-  }
-  static __device__ __forceinline__ PathRec finish(const KReq &Q, const Walker &W, const KExit &X) {
-    return kfinish(Q, W.T0, W.T1, W.n, X);
-  }
-};
-
 // ---------------------------------------------------------------------------
 // FP32-mixed walk: positions relative to the domain centre in FP32, the
 // hardware log2, sqrt, sin and cos (angles in revolutions), the same random
@@ -395,6 +364,8 @@ __device__ __forceinline__ bool kstep32(const KReq &Q, KWalker32 &W, uint32_t wa
   return false;
 }
 
+// Two steps per normal draw (a walker is at an even step at the start of a
+// pair).  pair() returns 0 running, 1 exited (X), 2 step cap.
 struct K32 {
   using Walker = KWalker32;
   static __device__ __forceinline__ void start(const KReq &Q, Walker &W, double2 xy, uint32_t p, uint32_t node,
@@ -426,8 +397,10 @@ struct K32 {
   }
 };
 
-template <class T>
-__global__ void __launch_bounds__(kKappaThreads) walk_kappa(const KReq *__restrict__ qp) {
+// The two walks keep separate kernels (the same loop), so that each gets the
+// register allocation of its own step.
+__global__ void __launch_bounds__(kKappaThreads) walk_kappa32(const KReq *__restrict__ qp) {
+  using T = K32;
   const KReq &Q = *qp;
   const uint32_t lane = __lane_id();
   typename T::Walker W;
@@ -492,20 +465,108 @@ __global__ void __launch_bounds__(kKappaThreads) walk_kappa(const KReq *__restri
   }
 }
 
+__global__ void __launch_bounds__(kKappaThreads) walk_kappa64(const KReq *__restrict__ qp) {
+  const KReq &Q = *qp;
+  const uint32_t lane = __lane_id();
+  KWalker W;
+  bool active = false;
+  bool exhausted = false;
+  // wave-uniform tile cursor
+  uint32_t t_node = 0, t_p0 = 0, t_next = 0, t_end = 0;
+  uint64_t t_rec0 = 0;
+
+  for (;;) {
+    const uint64_t freemask = __builtin_amdgcn_ballot_w64(!active);
+    if (freemask != 0ull && !exhausted) {
+      const uint32_t nfree = (uint32_t)__popcll(freemask);
+      const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(freemask >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)freemask, 0u));
+      uint32_t given = 0;
+      while (given < nfree) {
+        if (t_next == t_end) {
+          uint32_t t = 0;
+          if (lane == 0) t = atomicAdd(Q.tile_counter, 1u);
+          t = uni(t);
+          if (t >= Q.n_tiles) { exhausted = true; break; }
+          const DevTile Tl = Q.tiles[t];
+          t_node = uni(Tl.node);
+          t_p0 = uni(Tl.p0);
+          t_next = t_p0;
+          t_end = t_p0 + uni(Tl.count);
+          t_rec0 = ((uint64_t)uni((uint32_t)(Tl.rec0 >> 32)) << 32) | uni((uint32_t)Tl.rec0);
+        }
+        const uint32_t take = min(t_end - t_next, nfree - given);
+        if (!active && rank >= given && rank < given + take) {
+          const uint32_t p = t_next + (rank - given);
+          const double2 xy = *reinterpret_cast<const double2 *>(Q.nodes + 2 * (size_t)t_node);
+          W.y = xy.x;
+          W.z = xy.y;
+          W.T0 = 0.0;
+          W.T1 = 0.0;
+          W.n = 0u;
+          W.rec = t_rec0 + (p - t_p0);
+          W.pp = philox_path(p, t_node, Q.key0);
+          active = true;
+        }
+        t_next += take;
+        given += take;
+      }
+    }
+    if (__builtin_amdgcn_ballot_w64(!active) == ~0ull) break;   // no work left for this wave
+
+    if (active) {
+      // two steps per normal draw; a walker is at an even step here
+      const uint64_t P = (uint64_t)kM0 * (uint64_t)(W.n >> 1);
+      const uint4 w = philox_pp(P, Q.ctr3, W.pp, Q.key0, Q.key1);
+      double a0, a1, b0, b1;
+      normals64(w.x, w.y, a0, a1);
+      normals64(w.z, w.w, b0, b1);
+      KExit X;
+      X.wall = -1;
+      bool end = kstep(Q, W, a0, a1, X);
+      if (!end) {
+        W.n += 1u;
+        end = W.n >= Q.max_steps;
+        if (!end) {
+          end = kstep(Q, W, b0, b1, X);
+          if (!end) {
+            W.n += 1u;
+            end = W.n >= Q.max_steps;
+          }
+        }
+      }
+      if (end) {
+        PathRec r;
+        if (X.wall >= 0) {
+          r = kfinish(Q, W.T0, W.T1, W.n, X);
+        } else {   // step cap: W.n == max_steps steps drawn
+          r.w_re = 0.0;
+          r.w_im = 0.0;
+          r.tau = -1.0;
+          r.steps = W.n;
+          r.wall = -1;
+        }
+        Q.recs[W.rec] = r;
+        active = false;
+      }
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_walk_kappa(int precision, const KReq *req_dev, uint32_t blocks, hipStream_t st) {
   if (blocks == 0) return hipSuccess;
-  if (precision == 1) hipLaunchKernelGGL(walk_kappa<K32>, dim3(blocks), dim3(kKappaThreads), 0, st, req_dev);
-  else hipLaunchKernelGGL(walk_kappa<K64>, dim3(blocks), dim3(kKappaThreads), 0, st, req_dev);
+  if (precision == 1) hipLaunchKernelGGL(walk_kappa32, dim3(blocks), dim3(kKappaThreads), 0, st, req_dev);
+  else hipLaunchKernelGGL(walk_kappa64, dim3(blocks), dim3(kKappaThreads), 0, st, req_dev);
   return hipGetLastError();
 }
 
 int kappa_blocks_per_cu(int precision) {
   int nb = 0;
   const hipError_t e = precision == 1
-      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_kappa<K32>, (int)kKappaThreads, 0)
-      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_kappa<K64>, (int)kKappaThreads, 0);
+      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_kappa32, (int)kKappaThreads, 0)
+      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_kappa64, (int)kKappaThreads, 0);
   return e == hipSuccess ? nb : 0;
 }
 
