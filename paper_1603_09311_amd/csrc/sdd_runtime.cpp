@@ -1122,7 +1122,9 @@ static void complete_flights(sdd_ctx *ctx, std::vector<std::unique_ptr<Flight>> 
 }
 
 static void worker_main(sdd_ctx *ctx) {
-  hipSetDevice(ctx->device);
+  // if this fails, the worker's first HIP call fails too and its tickets
+  // report SDD_E_DEVICE
+  (void)hipSetDevice(ctx->device);
   std::vector<std::unique_ptr<Flight>> flights;
   uint64_t reserved = 0;   // workspace promised to flights
   for (;;) {
@@ -1286,7 +1288,7 @@ sdd_status sdd_destroy(sdd_ctx_t ctx) {
   {
     ExecGuard ex(ctx);   // no blocking call still running
     for (auto &e : ctx->ev)
-      if (e) hipEventDestroy(e);
+      if (e) (void)hipEventDestroy(e);   // teardown: nothing to do on failure
   }
   delete ctx;
   return SDD_OK;
@@ -1948,13 +1950,14 @@ struct sdd_batch {
 static void batch_free(sdd_batch *b) {
   if (!b) return;
   sdd_ctx *ctx = b->ctx;
-  if (b->exec) hipGraphExecDestroy(b->exec);
-  if (b->graph) hipGraphDestroy(b->graph);
-  if (b->cap) hipStreamDestroy(b->cap);
+  // teardown: nothing to do on failure
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
   for (auto &e : b->ev)
-    if (e) hipEventDestroy(e);
-  if (b->h_out) hipHostFree(b->h_out);
-  if (b->h_done) hipHostFree(b->h_done);
+    if (e) (void)hipEventDestroy(e);
+  if (b->h_out) (void)hipHostFree(b->h_out);
+  if (b->h_done) (void)hipHostFree(b->h_done);
   for (auto &g : b->groups) {
     ctx->release(g.d_reqs);
     ctx->release(g.d_ctr);
