@@ -114,12 +114,21 @@ typedef struct {
     uint64_t seed;
     uint32_t stream;            /* < 2^31 */
     uint32_t max_steps;         /* proposals per path before it counts as unfinished; 0 = 2e9 */
-    uint32_t flags;             /* 0 */
+    uint32_t flags;             /* 0, or SDD_FLAG_NO_SIGMA_GRID */
     uint32_t reserved;          /* 0 */
     double target_rel_se;       /* 0: fixed paths.  > 0: a 4096-path pilot per node, then
                                    extended on the same streams to N = ceil((s/(target*|g|inf))^2)
                                    (capped at 2^20), s^2 = var_re + var_im of the pilot */
 } sdd_request;
+
+/* Request flags.  SDD_FLAG_NO_SIGMA_GRID: an FP32-mixed request whose model
+ * has no specialised walker (more than two primitives, or other than air plus
+ * one half-space, box or triangle) looks regions up by the loop over its
+ * primitives instead of the sigma grid: a grid of 256 cells along the longer
+ * side, each holding its region or the one boundary inequality that crosses
+ * it (cells crossed by more than one use the loop).  Both give the same
+ * region for every point, hence the same results; the grid is faster. */
+enum { SDD_FLAG_NO_SIGMA_GRID = 1 };
 
 /* Per-path record (node-major, path order), for inspection and tests. */
 typedef struct {

@@ -90,6 +90,22 @@ struct FanJob {
   uint64_t pad;
 };
 
+// One cell of the sigma grid of the FP32 walk's generic signature (32 B):
+// the region of a point of the cell is rate_in if the point passes the cell's
+// test, else rate_out.  The test is the edge function
+//   e = dy (b - v1) - dz (a - v0)
+// in FP32, the same expression the primitive loop evaluates, compared with 0
+// by `mode` (0: e < 0, 1: e >= 0, 2: e <= 0).  A pure cell has a zero line
+// and mode 1 (e is +-0, so the test passes) and rate_in = rate_out.  A cell
+// with flags & kCellLoop set is crossed by more than one boundary: its points
+// take the primitive loop.
+constexpr uint32_t kCellLoop = 1u;
+struct SigmaCell {
+  uint32_t flags, mode;
+  float rate_in, rate_out;
+  float v0, v1, dy, dz;
+};
+
 // Per-request device descriptor.
 struct DevReq {
   // FP64 walk (absolute coordinates, the same arithmetic as a plain FP64 reference)
@@ -137,6 +153,11 @@ struct DevReq {
   double pd[kMaxPrims][6];    // FP64 geometry of the model's primitives
   float pf[kMaxPrims][8];     // FP32 geometry relative to the centre, padded to 8
   const DevModel *model;      // resident model the primitives were taken from
+  // sigma grid of the FP32 generic signature (null: the primitive loop); cell
+  // (i, j) = (trunc(a gsy + goy), trunc(b gsz + goz)) clamped, at grid[j gy + i]
+  const SigmaCell *grid;
+  uint32_t gy, gz;
+  float gsy, goy, gsz, goz;
   const double *nodes;  // n x (y, z)
   const double *g;      // 4 x (M + 1) x (re, im)
   const DevTile *tiles;

@@ -159,7 +159,16 @@ __device__ __forceinline__ int region_index_generic(int np, const int32_t *kind,
 template <int SIG> struct Reg32 {
   static constexpr bool kCounted = SIG != kSigGeneric;
   float p[10];
+  // generic signature: the sigma grid
+  const SigmaCell *grid;
+  uint32_t gy, gz;
+  float gsy, goy, gsz, goz;
   __device__ __forceinline__ void load(const DevReq &Q) {
+    if constexpr (SIG == kSigGeneric) {
+      grid = Q.grid;
+      gy = Q.gy; gz = Q.gz;
+      gsy = Q.gsy; goy = Q.goy; gsz = Q.gsz; goz = Q.goz;
+    }
     if constexpr (SIG != kSigNone && SIG != kSigGeneric) p[0] = unif(Q.sigp[0]);
     if constexpr (SIG == kSigZY || SIG == kSigZBox || SIG == kSigZTri) {
 #pragma unroll
@@ -227,9 +236,29 @@ template <int SIG> struct Reg32 {
       return (unid(Q.c[0]) * (double)(n - g) + unid(Q.c[1]) * (double)m) + cb * (double)(g - m);
     }
   }
-  // generic signature: FP32 rate of the region containing (a, b)
+  // generic signature: FP32 rate of the region containing (a, b).  With the
+  // sigma grid: one cell read and one edge function (the primitive loop only
+  // in cells crossed by more than one boundary); the same result as the loop
+  // for every point (the host classifies cells with margins for the FP32
+  // rounding of the cell index and of the edge functions).
   __device__ __forceinline__ float rate32(const DevReq &Q, float a, float b) const {
-    return region_c_generic<float, 8>((int)Q.nprims, Q.kind, &Q.pf[0][0], Q.fc, a, b);
+    if (grid == nullptr) return region_c_generic<float, 8>((int)Q.nprims, Q.kind, &Q.pf[0][0], Q.fc, a, b);
+    int i = (int)__builtin_fmaf(a, gsy, goy);
+    int j = (int)__builtin_fmaf(b, gsz, goz);
+    i = min(max(i, 0), (int)gy - 1);
+    j = min(max(j, 0), (int)gz - 1);
+    // both halves of the cell in flight together, through the global address
+    // space (one memory latency per step)
+    typedef const __attribute__((address_space(1))) uint32_t *gptr;
+    const gptr w = (gptr)(grid + ((uint32_t)j * gy + (uint32_t)i));
+    const uint32_t flags = w[0], mode = w[1], rin = w[2], rout = w[3];
+    const float v0 = __builtin_bit_cast(float, w[4]), v1 = __builtin_bit_cast(float, w[5]);
+    const float dy = __builtin_bit_cast(float, w[6]), dz = __builtin_bit_cast(float, w[7]);
+    const float e = dy * (b - v1) - dz * (a - v0);
+    const bool in = mode == 0u ? (e < 0.f) : (mode == 1u ? (e >= 0.f) : (e <= 0.f));
+    float c = __builtin_bit_cast(float, in ? rin : rout);
+    if (flags & kCellLoop) c = region_c_generic<float, 8>((int)Q.nprims, Q.kind, &Q.pf[0][0], Q.fc, a, b);
+    return c;
   }
 };
 

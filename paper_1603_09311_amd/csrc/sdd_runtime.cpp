@@ -162,8 +162,10 @@ struct Prepared {
   std::vector<DevTile> tiles;
   uint64_t n_paths = 0;            // paths in this pass
   std::vector<uint64_t> rec_off;   // per node record offset of this pass
+  std::vector<SigmaCell> grid;     // sigma grid (FP32 generic signature), empty if none
   // device allocations
   char *d_g = nullptr, *d_nodes = nullptr, *d_tiles = nullptr, *d_recs = nullptr;
+  char *d_grid = nullptr;
   char *d_recs_pilot = nullptr;    // pilot records kept for the final reduction
   std::vector<uint64_t> pilot_off; // per node pilot record offset
   std::vector<uint32_t> pilot_cnt;
@@ -269,7 +271,7 @@ static sdd_status validate(sdd_ctx *ctx, const sdd_request *r, const HostModel *
   if (r->freq_hz < 0.0 || !std::isfinite(r->freq_hz)) return fail(SDD_E_INVALID, "freq_hz must be >= 0");
   if (r->freq_hz == 0.0 && (!(r->alpha_direct >= 0.0) || !std::isfinite(r->alpha_direct)))
     return fail(SDD_E_INVALID, "alpha_direct must be >= 0 when freq_hz == 0");
-  if (r->flags != 0) return fail(SDD_E_INVALID, "flags must be 0");
+  if (r->flags & ~(uint32_t)SDD_FLAG_NO_SIGMA_GRID) return fail(SDD_E_INVALID, "unknown flags");
   if (!(r->target_rel_se >= 0.0) || !std::isfinite(r->target_rel_se))
     return fail(SDD_E_INVALID, "target_rel_se must be >= 0");
   for (uint32_t k = 0; k < 4 * 2 * r->g_samples; ++k)
@@ -294,6 +296,166 @@ static sdd_status validate(sdd_ctx *ctx, const sdd_request *r, const HostModel *
   }
   *out_model = &m;
   return SDD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Sigma grid of the FP32 walk's generic signature (SigmaCell).  Each cell is
+// classified against every inequality of every primitive over the cell grown
+// by a margin (1e-3 of its width; the FP32 cell index errs by at most about
+// 1.5e-5 of a width), and each inequality's edge function only where its sign
+// holds with a margin (4 2^-24 times the magnitude of its terms) above the
+// rounding of its FP32 evaluation.  So for every FP32 point the kernel maps to
+// a cell, the cell's answer is the primitive loop's.
+// ---------------------------------------------------------------------------
+namespace {
+struct GLine {
+  float v0, v1, dy, dz;
+  uint32_t mode;   // 0: in iff e < 0, 1: in iff e >= 0 (triangles: decided per cell)
+};
+enum GSign { kGNeg, kGPos, kGCross };
+enum GStat { kGOut, kGIn, kGOne, kGMany };
+
+// The primitive's inequalities as edge functions e = dy (b - v1) - dz (a - v0),
+// in the primitive loop's expressions (FP32 parameters relative to the centre).
+int prim_lines(int kind, const float *v, GLine *L) {
+  switch (kind) {
+    case SDD_HALF_Z_LT: L[0] = {0.f, v[0], 1.f, 0.f, 0u}; return 1;   // b < z0: e = b - z0
+    case SDD_HALF_Y_LT: L[0] = {v[0], 0.f, 0.f, -1.f, 0u}; return 1;  // a < y0: e = a - y0
+    case SDD_BOX:
+      L[0] = {v[0], 0.f, 0.f, -1.f, 1u};   // a >= y0
+      L[1] = {v[1], 0.f, 0.f, -1.f, 0u};   // a < y1
+      L[2] = {0.f, v[2], 1.f, 0.f, 1u};    // b >= z0
+      L[3] = {0.f, v[3], 1.f, 0.f, 0u};    // b < z1
+      return 4;
+    default:   // triangle edge m: (v[2m+2] - v[2m]) (b - v[2m+1]) - (v[2m+3] - v[2m+1]) (a - v[2m])
+      for (int m = 0; m < 3; ++m) {
+        const int i0 = 2 * m, i1 = (2 * m + 2) % 6;
+        L[m] = {v[i0], v[i0 + 1], (float)((double)v[i1] - (double)v[i0]),
+                (float)((double)v[i1 + 1] - (double)v[i0 + 1]), 0u};
+      }
+      return 3;
+  }
+}
+
+GSign classify(const GLine &L, double a0, double a1, double b0, double b1) {
+  double emin = HUGE_VAL, emax = -HUGE_VAL, mag = 0.0;
+  const double as[2] = {a0, a1}, bs[2] = {b0, b1};
+  for (double a : as)
+    for (double b : bs) {
+      const double e = (double)L.dy * (b - (double)L.v1) - (double)L.dz * (a - (double)L.v0);
+      emin = std::min(emin, e);
+      emax = std::max(emax, e);
+      mag = std::max(mag, std::fabs((double)L.dy) * std::fabs(b - (double)L.v1) +
+                              std::fabs((double)L.dz) * std::fabs(a - (double)L.v0));
+    }
+  const double m = 4.0 * 0x1p-24 * mag;
+  if (emin > m) return kGPos;
+  if (emax < -m) return kGNeg;
+  return kGCross;
+}
+
+// status of one primitive over the cell; for kGOne, the crossing line and
+// the mode of its test
+GStat prim_status(int kind, const GLine *L, int nl, double a0, double a1, double b0, double b1, GLine &one) {
+  GSign c[4];
+  for (int i = 0; i < nl; ++i) c[i] = classify(L[i], a0, a1, b0, b1);
+  if (kind == SDD_TRIANGLE) {
+    int pos = 0, neg = 0, cross = 0, ci = -1;
+    for (int i = 0; i < 3; ++i) {
+      if (c[i] == kGPos) ++pos;
+      else if (c[i] == kGNeg) ++neg;
+      else { ++cross; ci = i; }
+    }
+    if (pos && neg) return kGOut;    // no point has all three edge signs equal
+    if (cross == 0) return kGIn;
+    if (cross > 1) return kGMany;
+    one = L[ci];
+    one.mode = pos ? 1u : 2u;        // inside iff e >= 0 (others > 0) or e <= 0 (others < 0)
+    return kGOne;
+  }
+  int cross = 0, ci = -1;
+  for (int i = 0; i < nl; ++i) {
+    const bool holds = L[i].mode == 0u ? c[i] == kGNeg : c[i] == kGPos;
+    const bool fails = L[i].mode == 0u ? c[i] == kGPos : c[i] == kGNeg;
+    if (fails) return kGOut;
+    if (!holds) { ++cross; ci = i; }
+  }
+  if (cross == 0) return kGIn;
+  if (cross > 1) return kGMany;
+  one = L[ci];
+  return kGOne;
+}
+}  // namespace
+
+static constexpr uint32_t kGridCells = 65536;
+
+static void build_sigma_grid(DevReq &q, std::vector<SigmaCell> &grid) {
+  const int np = (int)q.nprims;
+  GLine lines[kMaxPrims][4];
+  int nl[kMaxPrims];
+  for (int k = 0; k < np; ++k) nl[k] = prim_lines(q.kind[k], q.pf[k], lines[k]);
+  // cells about square, at most kGridCells
+  const double hy = q.fhy, hz = q.fhz;
+  uint32_t gy, gz;
+  if (hy >= hz) {
+    gy = 256;
+    gz = (uint32_t)std::max(1.0, std::min(256.0, std::floor(256.0 * hz / hy)));
+  } else {
+    gz = 256;
+    gy = (uint32_t)std::max(1.0, std::min(256.0, std::floor(256.0 * hy / hz)));
+  }
+  q.gy = gy;
+  q.gz = gz;
+  q.gsy = (float)((double)gy / (2.0 * hy));
+  q.goy = (float)(hy * (double)q.gsy);
+  q.gsz = (float)((double)gz / (2.0 * hz));
+  q.goz = (float)(hz * (double)q.gsz);
+  grid.assign((size_t)gy * gz, SigmaCell{});
+  for (uint32_t j = 0; j < gz; ++j) {
+    // the points the kernel maps to row j: j <= b gsz + goz < j + 1
+    const double b0 = ((double)j - (double)q.goz) / (double)q.gsz;
+    const double b1 = ((double)j + 1.0 - (double)q.goz) / (double)q.gsz;
+    const double db = 1e-3 * (b1 - b0);
+    for (uint32_t i = 0; i < gy; ++i) {
+      const double a0 = ((double)i - (double)q.goy) / (double)q.gsy;
+      const double a1 = ((double)i + 1.0 - (double)q.goy) / (double)q.gsy;
+      const double da = 1e-3 * (a1 - a0);
+      SigmaCell &C = grid[(size_t)j * gy + i];
+      int pend = -1;
+      GLine pl{};
+      bool loop = false;
+      int region = np;   // background unless a primitive decides
+      for (int k = 0; k < np && !loop; ++k) {
+        GLine one{};
+        const GStat st = prim_status(q.kind[k], lines[k], nl[k], a0 - da, a1 + da, b0 - db, b1 + db, one);
+        if (st == kGOut) continue;
+        if (st == kGMany) { loop = true; break; }
+        if (st == kGOne) {
+          if (pend >= 0) { loop = true; break; }
+          pend = k;
+          pl = one;
+          continue;
+        }
+        region = k;   // kGIn: the first primitive that holds on the whole cell
+        break;
+      }
+      if (loop) {
+        C.flags = kCellLoop;
+        continue;
+      }
+      C.flags = 0u;
+      if (pend >= 0) {
+        C.mode = pl.mode;
+        C.v0 = pl.v0; C.v1 = pl.v1; C.dy = pl.dy; C.dz = pl.dz;
+        C.rate_in = q.fc[pend];
+        C.rate_out = q.fc[region];
+      } else {
+        C.mode = 1u;   // e = +-0 >= 0: rate_in
+        C.v0 = C.v1 = C.dy = C.dz = 0.f;
+        C.rate_in = C.rate_out = q.fc[region];
+      }
+    }
+  }
 }
 
 static void fill_devreq(Prepared &P) {
@@ -386,6 +548,10 @@ static void fill_devreq(Prepared &P) {
   q.precision = (uint32_t)r.precision;
   q.M = r.g_samples - 1;
   q.model = reinterpret_cast<const DevModel *>(m.dev);
+  P.grid.clear();
+  q.grid = nullptr;
+  if (q.sig == kSigGeneric && r.precision == SDD_FP32_MIXED && !(r.flags & SDD_FLAG_NO_SIGMA_GRID) && np > 0)
+    build_sigma_grid(q, P.grid);
 }
 
 // Copy the request's inputs; set up the first pass's path ranges.
@@ -497,6 +663,7 @@ static uint32_t tile_size(sdd_ctx *ctx, const Prepared &P) {
 
 static size_t pass_bytes(const Prepared &P) {
   return Arena::round(P.g.size() * 8) + Arena::round(P.nodes.size() * 8 + 16) +
+         Arena::round(P.grid.size() * sizeof(SigmaCell)) +
          Arena::round(P.tiles.size() * sizeof(DevTile) + 16) + Arena::round(P.n_paths * sizeof(PathRec) + 16);
 }
 
@@ -505,7 +672,8 @@ static void release_pass(sdd_ctx *ctx, Prepared &P) {
   ctx->release(P.d_nodes);
   ctx->release(P.d_tiles);
   ctx->release(P.d_recs);
-  P.d_g = P.d_nodes = P.d_tiles = P.d_recs = nullptr;
+  ctx->release(P.d_grid);
+  P.d_g = P.d_nodes = P.d_tiles = P.d_recs = P.d_grid = nullptr;
 }
 
 static void release_all(sdd_ctx *ctx, Prepared &P) {
@@ -521,7 +689,8 @@ static sdd_status upload_pass(sdd_ctx *ctx, Prepared &P) {
   P.d_nodes = ctx->alloc(P.nodes.size() * 8 + 16);
   P.d_tiles = ctx->alloc(P.tiles.size() * sizeof(DevTile) + 16);
   P.d_recs = ctx->alloc(P.n_paths * sizeof(PathRec) + 16);
-  if (!P.d_g || !P.d_nodes || !P.d_tiles || !P.d_recs) {
+  if (!P.grid.empty()) P.d_grid = ctx->alloc(P.grid.size() * sizeof(SigmaCell));
+  if (!P.d_g || !P.d_nodes || !P.d_tiles || !P.d_recs || (!P.grid.empty() && !P.d_grid)) {
     release_pass(ctx, P);
     size_t largest;
     {
@@ -542,6 +711,12 @@ static sdd_status upload_pass(sdd_ctx *ctx, Prepared &P) {
   P.dreq.tiles = reinterpret_cast<const DevTile *>(P.d_tiles);
   P.dreq.recs = reinterpret_cast<PathRec *>(P.d_recs);
   P.dreq.n_tiles = (uint32_t)P.tiles.size();
+  P.dreq.grid = nullptr;
+  if (!P.grid.empty()) {
+    HIP_TRY(hipMemcpyAsync(P.d_grid, P.grid.data(), P.grid.size() * sizeof(SigmaCell), hipMemcpyHostToDevice,
+                           ctx->stream));
+    P.dreq.grid = reinterpret_cast<const SigmaCell *>(P.d_grid);
+  }
   return SDD_OK;
 }
 

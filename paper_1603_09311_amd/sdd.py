@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libsdd.so")
 SDD_OK, SDD_E_INVALID, SDD_E_NOMEM, SDD_E_DEVICE = 0, -1, -2, -3
 SDD_E_BUSY, SDD_E_NOTFOUND, SDD_E_TIMEOUT, SDD_E_CANCELLED = -4, -5, -6, -7
 SDD_FP64, SDD_FP32_MIXED = 0, 1
+SDD_FLAG_NO_SIGMA_GRID = 1
 SDD_MAX_REGIONS = 16
 
 
@@ -179,7 +180,7 @@ def model_key(p):
 class _Req:
     """An sdd_request and the numpy buffers it points into."""
 
-    def __init__(self, p, model: int, precision: Optional[int] = None, target_rel_se: float = 0.0):
+    def __init__(self, p, model: int, precision: Optional[int] = None, target_rel_se: float = 0.0, flags: int = 0):
         self.g = np.ascontiguousarray(np.stack([p.g.real, p.g.imag], axis=-1).reshape(-1), dtype=np.float64)
         self.nodes = np.ascontiguousarray(p.nodes, dtype=np.float64).reshape(-1)
         self.pb = np.ascontiguousarray(p.path_begin, dtype=np.uint32)
@@ -188,7 +189,7 @@ class _Req:
         self.s = sdd_request(model, prec, p.freq_hz, p.alpha_direct, _ptr(self.g, C.c_double),
                              p.g.shape[1], p.n_nodes, _ptr(self.nodes, C.c_double), _ptr(self.pb, C.c_uint32),
                              _ptr(self.pc, C.c_uint32), 0, p.dt, p.seed, p.stream,
-                             min(int(p.max_steps), 0xFFFFFFFF), 0, 0, target_rel_se)
+                             min(int(p.max_steps), 0xFFFFFFFF), flags, 0, target_rel_se)
         self.n = p.n_nodes
         self.total = int(self.pc.astype(np.uint64).sum())
 
@@ -360,8 +361,9 @@ class Context:
         _check(lib().sdd_request_footprint(self.h, C.byref(q.s), C.byref(b)))
         return b.value
 
-    def solve(self, p, precision: Optional[int] = None, records: bool = False, target_rel_se: float = 0.0):
-        q = _Req(p, self.model(p), precision, target_rel_se)
+    def solve(self, p, precision: Optional[int] = None, records: bool = False, target_rel_se: float = 0.0,
+              flags: int = 0):
+        q = _Req(p, self.model(p), precision, target_rel_se, flags)
         r = _Res(q.n, q.total if records else 0)
         _check(lib().sdd_solve(self.h, C.byref(q.s), C.byref(r.s)))
         return r.as_dict()

@@ -239,6 +239,52 @@ def test_triangle_uneven_graph_batch_fp32_within_3se(ctx, orc):
         assert_within_se(g, o)
 
 
+def multi_body_model(seed, paths=128):
+    """A seeded model with 4-11 bodies (boxes, triangles, a half-space) under
+    air on the quarter-space domain, nodes on edges, at corners and at random
+    points (the walker's generic signature)."""
+    rng = np.random.default_rng(seed)
+    regions = [W.Region(W.HALF_Z_LT, (0.0,), 0.0)]
+    nodes = []
+    for _ in range(int(rng.integers(4, 12))):
+        kind = rng.choice([W.BOX, W.BOX, W.TRIANGLE, W.HALF_Y_LT], p=[0.45, 0.1, 0.35, 0.1])
+        sig = float(10.0 ** rng.uniform(-2, 0.5))
+        if kind == W.BOX:
+            y0, z0 = rng.uniform(-6, 5), rng.uniform(0.1, 6)
+            y1, z1 = y0 + rng.uniform(0.3, 3), z0 + rng.uniform(0.3, 2)
+            regions.append(W.Region(W.BOX, (y0, y1, z0, z1), sig))
+            nodes += [(y0, z0), (y1, (z0 + z1) / 2), ((y0 + y1) / 2, z1)]
+        elif kind == W.TRIANGLE:
+            v = [(rng.uniform(-6, 6), rng.uniform(0.1, 7)) for _ in range(3)]
+            regions.append(W.Region(W.TRIANGLE, tuple(x for pt in v for x in pt), sig))
+            nodes += [v[0], ((v[1][0] + v[2][0]) / 2, (v[1][1] + v[2][1]) / 2)]
+        else:
+            regions.append(W.Region(W.HALF_Y_LT, (rng.uniform(-7, 7),), sig))
+    nodes += [tuple(x) for x in rng.uniform((-7.5, -5.5), (7.5, 7.5), (8, 2))]
+    nodes = np.array([(y, z) for y, z in nodes if -8 < y < 8 and -6 < z < 8])
+    p = W.unit_square(paths=paths, precision=W.FP32_MIXED, dt=4e-4, M=1024, nodes=nodes, seed=seed)
+    g = W.column_tables(regions, 0.01, W.QS_WALLS, 1.0, W.DELTA1, 0.0, 1024)
+    return p.replace(y_lo=W.QS_WALLS[0], y_hi=W.QS_WALLS[1], z_lo=W.QS_WALLS[2], z_hi=W.QS_WALLS[3],
+                     regions=regions, sigma_background=0.01, length_unit_m=W.DELTA1, freq_hz=1.0,
+                     alpha_direct=0.0, g=g)
+
+
+def test_sigma_grid_equals_primitive_loop_bitwise(ctx, orc):
+    """FP32-mixed walks on multi-body models: the sigma grid gives every
+    path the record the primitive loop gives, bit for bit; and within 3 SE
+    of the FP64 oracle."""
+    for seed in range(6):
+        p = multi_body_model(seed)
+        log(f"sigma grid: seed {seed}, {len(p.regions)} primitives, {p.n_nodes} nodes")
+        a = ctx.solve(p, records=True)
+        b = ctx.solve(p, records=True, flags=sdd.SDD_FLAG_NO_SIGMA_GRID)
+        assert a["records"].tobytes() == b["records"].tobytes(), seed
+        assert np.array_equal(a["mean"], b["mean"])
+        if seed < 2:
+            o, _ = oracle_solve(orc, p.with_paths(2048))
+            assert_within_se(ctx.solve(p.with_paths(2048)), o)
+
+
 def test_batch_equals_alone_bitwise(ctx):
     """Uneven node counts, path counts, frequencies, models and precisions in
     one persistent launch: each result is bitwise the one it gets alone."""
