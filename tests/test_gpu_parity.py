@@ -588,6 +588,27 @@ def test_mt_response_half_space_physics(ctx):
     assert np.all(np.abs(rho - 100.0) < 12.0) and np.all(np.abs(phi - 45.0) < 2.5)
 
 
+def test_mt_response_commemi_within_table2(ctx):
+    """TE apparent resistivity of COMMEMI 2D-1 at 10 Hz at the five sites of
+    Sec. 4.3 from the FP32 walk (four independent seeds of 2^20 paths per
+    point, h = 50 m) lies inside the COMMEMI spread of Table 2 widened by the
+    Monte-Carlo error of the four-seed mean (99% two-sided Student t with
+    three degrees of freedom times the seed spread over 2)."""
+    tab = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "commemi_te_table2.txt"))
+    assert np.allclose(tab[:, 0], 1000.0 * np.asarray(W.COMMEMI_SITES_KM))
+    rhos = []
+    for seed in range(4):
+        ps = W.commemi_te_points(paths=1 << 20, seed=seed, dt=4e-4, h=0.05)
+        got = ctx.solve_batch(ps)
+        rho, _ = sdd.mt_te_response(*[g["mean"] for g in got], 0.05, 1000.0, 10.0)
+        rhos.append(rho)
+    rhos = np.array(rhos)
+    mean, sd = rhos.mean(0), rhos.std(0, ddof=1)
+    allow = tab[:, 2] + stats.t.ppf(0.995, 3) * sd / 2.0
+    log(f"COMMEMI rho_a {mean.round(2)} sd {sd.round(2)}; Table 2 {tab[:, 1]} +- {tab[:, 2]}")
+    assert np.all(np.abs(mean - tab[:, 1]) <= allow), (mean - tab[:, 1]) / allow
+
+
 def test_domain_decomposition_layered_model(ctx):
     """Stochastic domain decomposition end to end: FP32 walks at the 138
     interface nodes of air over a uniform half-space cut into three
