@@ -10,11 +10,14 @@ Legs besides the timed workload (each bounded, each can be switched off):
             walker on a node subset (the comparison form);
   --served  a short Poisson stream of mixed requests through the served
             mode, for p50/p99 latency, beside the same stream through
-            blocking solves in arrival order;
+            blocking solves in arrival order and, for its first requests
+            (a bounded wall time), through the plain FP64 form;
   --mt      pointwise TE apparent resistivity and phase at the COMMEMI 2D-1
             sites (Table 2 of the paper as context);
   --sdd     domain decomposition of the quarter-space: walks on the
             interfaces, RBF-FD in the sub-domains, surface responses;
+  --kappa   the discontinuous-kappa walk on the analytic model of Sec. 4.1
+            (FP64 and FP32-mixed) against its exact solution;
   cpu       the FP64 CPU oracle on a bounded sample of the same workload
             (rank 0 only), as a baseline.
 """
@@ -171,20 +174,28 @@ def kappa_leg(ctx, n: int = 51, paths: int = 10000, dt: float = 1e-4, repeats: i
     return out
 
 
-def served_leg(ctx, n_requests: int, rate_hz: float, paths: int):
+def served_leg(ctx, n_requests: int, rate_hz: float, paths: int, plain_budget_s: float = 12.0):
     """A Poisson trace of mixed requests (unit square, quarter-space and block
     node subsets) through the served mode (continuous batching in time
-    slices), and the same trace through blocking solves in arrival order (one
-    persistent launch per request, FIFO) as the baseline.  Latency = result
-    available - arrival time."""
+    slices), and two baselines on the same arrivals: blocking solves in
+    arrival order (one persistent launch per request, FIFO), and the plain
+    FP64 form (one launch per node, one thread per path) in arrival order.
+    The plain form is some hundred times slower, so it runs the trace's
+    first requests until plain_budget_s of wall time is spent, and the served
+    and FIFO latencies of the same requests are reported beside it.
+    Latency = result available - arrival time."""
     from paper_1603_09311_amd import workloads as W
     trace = W.served_trace(n_requests, rate_hz, seed=1, paths_override=paths)
+    nodes = sum(p.n_nodes for _, p in trace)
     work = 0
 
-    def stats_of(lat, wall):
+    def stats_of(lat, wall=None):
         lat = np.array(lat)
-        return {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-                "mean_ms": float(lat.mean() * 1e3), "wall_s": wall}
+        out = {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+               "mean_ms": float(lat.mean() * 1e3)}
+        if wall is not None:
+            out["wall_s"] = wall
+        return out
 
     # served: submit each request at its arrival time and poll every ticket
     # in flight meanwhile (latency = completion seen by the poll - arrival)
@@ -204,20 +215,38 @@ def served_leg(ctx, n_requests: int, rate_hz: float, paths: int):
                 work += int(r["steps"].sum())
                 del left[i]
         time.sleep(0.0002)
-    served = stats_of([done_at[i] for i in range(len(trace))], time.perf_counter() - t0)
-    # baseline: blocking solves, first come first served
-    t0 = time.perf_counter()
-    lat = []
-    for t_arr, p in trace:
-        now = time.perf_counter() - t0
-        if t_arr > now:
-            time.sleep(t_arr - now)
-        ctx.solve(p)
-        lat.append(time.perf_counter() - t0 - t_arr)
-    fifo = stats_of(lat, time.perf_counter() - t0)
-    return {"requests": n_requests, "rate_hz": rate_hz, "paths_per_node": paths, "walk_steps": work,
+    served_wall = time.perf_counter() - t0
+    served_lat = [done_at[i] for i in range(len(trace))]
+    served = stats_of(served_lat, served_wall)
+    served["nodes_per_s"] = nodes / served_wall
+
+    def fifo(solve, budget=None):
+        t0 = time.perf_counter()
+        lat, steps = [], 0
+        for t_arr, p in trace:
+            now = time.perf_counter() - t0
+            if budget is not None and now > budget:
+                break
+            if t_arr > now:
+                time.sleep(t_arr - now)
+            r = solve(p)
+            lat.append(time.perf_counter() - t0 - t_arr)
+            steps += int(r["steps"].sum())
+        return lat, steps, time.perf_counter() - t0
+
+    fifo_lat, _, fifo_wall = fifo(ctx.solve)
+    blocking = stats_of(fifo_lat, fifo_wall)
+    blocking["nodes_per_s"] = nodes / fifo_wall
+    plain_lat, plain_steps, plain_wall = fifo(ctx.solve_plain, plain_budget_s)
+    k = len(plain_lat)
+    plain = stats_of(plain_lat, plain_wall)
+    plain.update({"requests": k, "nodes_per_s": sum(p.n_nodes for _, p in trace[:k]) / plain_wall,
+                  "walk_steps_per_s": plain_steps / plain_wall,
+                  "served_same_requests": stats_of(served_lat[:k]),
+                  "fifo_blocking_same_requests": stats_of(fifo_lat[:k])})
+    return {"requests": n_requests, "rate_hz": rate_hz, "paths_per_node": paths, "nodes": nodes, "walk_steps": work,
             "p50_ms": served["p50_ms"], "p99_ms": served["p99_ms"], "served": served,
-            "fifo_blocking_baseline": fifo}
+            "fifo_blocking_baseline": blocking, "plain_fp64_fifo_baseline": plain}
 
 
 # Table 2 of Sec. 4.3 (TE apparent resistivity, ohm m, COMMEMI 2D-1 at 10 Hz):
