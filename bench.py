@@ -54,10 +54,13 @@ VALU_PEAK = CUS * SIMDS * LANES * CLOCK
 #   uniforms: radius (align + exact subtract), angle (align)         =  3
 #   Box-Muller + proposal (log2, sqrt, cos, sin, 2 fma; positions in
 #   units of the step scale, so no multiply)                          =  6
-#   exit screen, both axes (2 sub |.|, 2 mul, min, compare)          =  6
+#   exit screen: distances to the walls (2 sub |.|), and per pair of
+#   steps the least of its six distances (3 integer minima) and one
+#   compare                                                   2 + 4/2 =  4
 #   region of the proposal: 2 tests, 2 count increments              =  4
-#   step counter and cap (one add and one compare per two steps)     =  1
-OPS_PER_STEP = 18.5 + 3 + 6 + 6 + 4 + 1   # = 38.5
+#   step cap (one compare per two steps), step counter (one add per
+#   four steps)                                                       =  0.75
+OPS_PER_STEP = 18.5 + 3 + 6 + 4 + 4 + 0.75   # = 36.25
 
 
 def kernel_source_hash() -> str:

@@ -155,8 +155,10 @@ typedef struct {
     uint32_t block_threads;   /* multiple of 64, <= 256 */
     uint32_t blocks_per_cu;
     uint32_t tile_paths;      /* paths per tile (work unit claimed by a wave) */
-    uint32_t slice_iters;     /* served mode: iterations (2 steps) per wave per slice */
-    uint32_t refill_every;    /* refill idle lanes every k iterations (power of 2, <= 64) */
+    uint32_t slice_iters;     /* served mode: pairs of steps per wave per slice (the FP32
+                                 walker takes two pairs per iteration: rounded up to even) */
+    uint32_t refill_every;    /* refill idle lanes every k pairs of steps (power of 2, <= 64;
+                                 the FP32 walker at most every second pair) */
 } sdd_tuning;
 
 /* Context on device `device` (HIP ordinal) with a caller-owned device

@@ -123,6 +123,7 @@ struct DevReq {
   float fhy, fhz;      // half-widths / K
   float fthr;          // 12.05 > 24 / 2, compared with 2 d0 d1 (FP32 uniforms are >= 2^-24)
   float fscr;          // fthr / 2, compared with d0 d1' in the per-step screen
+  float fscr_root;     // least float r with fl(r r) > fscr: distances all > r pass both screens of a pair
   float fc[kMaxRegions + 3];
   // model signature (which specialised region lookup the walkers use) and its
   // FP32 parameters in centred coordinates (units of K):
@@ -137,9 +138,12 @@ struct DevReq {
   uint32_t fanout;
   // step caps of the FP32 walk, which starts every pair of steps at an even
   // step index n: the pair is the last one when n >= cap2 (max_steps - 2, or
-  // 0), and then its first step is the last allowed iff max_steps is odd
+  // 0), and then its first step is the last allowed iff max_steps is odd;
+  // the walker takes two pairs per iteration, and the second compares the
+  // iteration's first n with cap2b (cap2 - 2, or 0)
   uint32_t cap2;
   uint32_t cap_odd;
+  uint32_t cap2b;
   float sigp[12];
   // streams and limits
   uint32_t key0, key1;  // Philox key (seed low, high)

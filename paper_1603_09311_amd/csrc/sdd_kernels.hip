@@ -6,8 +6,9 @@
 //   walk_persist_f64  persistent walker, FP64: identical arithmetic to a
 //                     plain FP64 reference on the same streams.
 //   walk_persist_f32  persistent walker, FP32-mixed: coordinates relative to
-//                     the domain centre, a conservative 6-operation exit
-//                     screen per step, compensated FP32 phase; weight and
+//                     the domain centre, a conservative exit screen per
+//                     pair of steps (the least distance of three points
+//                     to the walls), compensated FP32 phase; weight and
 //                     reduction in FP64.
 //   reduce_nodes      deterministic FP64 reduction of each node's path records
 //                     to the MC estimate, variance, covariance and SE.
@@ -462,14 +463,15 @@ struct X32 {
 };
 
 template <int SIG> struct U32 {
-  float hy, hz, thr, scr;
-  uint32_t k0, k1, ctr3, max_steps, cap2;
+  float hy, hz, thr, scr, scr_root;
+  uint32_t k0, k1, ctr3, max_steps, cap2, cap2b;
   bool cap_odd;
   Reg32<SIG> reg;
   __device__ __forceinline__ void load(const DevReq &Q) {
-    hy = Q.fhy; hz = Q.fhz; thr = Q.fthr; scr = Q.fscr;
+    hy = Q.fhy; hz = Q.fhz; thr = Q.fthr; scr = Q.fscr; scr_root = Q.fscr_root;
     k0 = Q.key0; k1 = Q.key1; ctr3 = Q.ctr3; max_steps = Q.max_steps;
     cap2 = Q.cap2;
+    cap2b = Q.cap2b;
     cap_odd = Q.cap_odd != 0u;
     reg.load(Q);
   }
@@ -568,20 +570,13 @@ __device__ __forceinline__ bool exit32(const DevReq &Q, const U32<SIG> &U, const
   return true;
 }
 
-// One step; returns true if the walker left the domain (recorded in X when
-// `live`).  The state is advanced either way.
+// A full step to (an, bn): the walker moves there and the step's phase goes
+// to the region of that point (right-point rule): a step count per region,
+// or (generic signature) a compensated FP32 sum (Fast2Sum: S_hi grows from 0
+// by increments c >= 0).
 template <int SIG>
-__device__ __forceinline__ bool step32(const DevReq &Q, const U32<SIG> &U, W32 &W, uint32_t wa, uint32_t wb,
-                                       bool live, uint32_t nstep, X32 &X) {
-  float an, bn;
-  propose32(W.a, W.b, wa, wb, an, bn);
-  const float e1y = U.hy - fabsf(an);
-  const float e1z = U.hz - fabsf(bn);
-  bool ex = false;
-  if (live && fminf(W.d0y * e1y, W.d0z * e1z) <= U.scr) ex = exit32<SIG>(Q, U, W, an, bn, nstep, X);
-  // the full step's phase goes to the region of the proposal (right-point
-  // rule): a step count per region, or (generic signature) a compensated
-  // FP32 sum (Fast2Sum: S_hi grows from 0 by increments c >= 0)
+__device__ __forceinline__ void advance32(const DevReq &Q, const U32<SIG> &U, W32 &W, float an, float bn, float e1y,
+                                          float e1z) {
   if constexpr (Reg32<SIG>::kCounted) {
     U.reg.count(an, bn, W.n0, W.n1);
   } else {
@@ -594,7 +589,6 @@ __device__ __forceinline__ bool step32(const DevReq &Q, const U32<SIG> &U, W32 &
   W.b = bn;
   W.d0y = e1y;
   W.d0z = e1z;
-  return ex;
 }
 
 __device__ __forceinline__ PathRec finish32(const DevReq &Q, const X32 &X) {
@@ -611,25 +605,65 @@ __device__ __forceinline__ PathRec finish32(const DevReq &Q, const X32 &X) {
   return r;
 }
 
-// Two steps.  Returns 0 running, 1 exited, 2 step cap.
-template <int SIG>
-__device__ __forceinline__ int iterate32(const DevReq &Q, const U32<SIG> &U, W32 &W, X32 &X) {
+__device__ __forceinline__ int32_t fbits(float x) { return __builtin_bit_cast(int32_t, x); }
+
+// Two steps (one Philox call).  Both proposals are made first; a step needs
+// its exact exit logic only if its screen min(d0y d1y', d0z d1z') <= scr
+// flags it, which needs some distance of the pair's three points at or below
+// r = scr_root (every product of two distances above r exceeds scr in FP32),
+// so one test of the least of the six distances clears both steps in all but
+// a few percent of pairs.  The walker always advances; `stop` (the lane's
+// walk ended in an earlier pair: exit, recorded in X, or step cap) skips the
+// exit logic, and the state after a stop is discarded.
+template <int SIG, int K>
+__device__ __forceinline__ void pair32(const DevReq &Q, const U32<SIG> &U, W32 &W, X32 &X, uint32_t n0, bool &ex,
+                                       bool &stop) {
   const uint4 w = philox_pp(W.P, U.ctr3, W.pp, U.k0, U.k1);
-  const uint32_t n = W.n;
-  const bool exA = step32<SIG>(Q, U, W, w.x, w.y, true, n, X);
+  const uint32_t n = n0 + 2u * K;   // index of the pair's first step (K: the pair within the iteration)
+  float a1, b1, a2, b2;
+  propose32(W.a, W.b, w.x, w.y, a1, b1);
+  propose32(a1, b1, w.z, w.w, a2, b2);
+  const float e1y = U.hy - fabsf(a1), e1z = U.hz - fabsf(b1);
+  const float e2y = U.hy - fabsf(a2), e2z = U.hz - fabsf(b2);
+  // least distance compared through the bit patterns: for r > 0, x <= r iff
+  // the signed integer reading of x is <= that of r (negative x, -0 included,
+  // read as negative integers), and integer minima need no NaN handling
+  const int32_t m =
+      min(min(min(min(min(fbits(W.d0y), fbits(W.d0z)), fbits(e1y)), fbits(e1z)), fbits(e2y)), fbits(e2z));
   // step caps (n is even here): the pair is the last one when n >= cap2, and
   // its first step is then the last allowed iff max_steps is odd
-  const bool near = n >= U.cap2;
+  const bool near = K == 0 ? (n0 >= U.cap2) : (n0 >= U.cap2b);
   const bool capA = near && U.cap_odd;
-  const bool exB = step32<SIG>(Q, U, W, w.z, w.w, !exA && !capA, n + 1u, X);
-  W.n = n + 2u;
+  const W32 W0 = W;   // the walker before the pair, for the first step's exit logic
+  advance32<SIG>(Q, U, W, a1, b1, e1y, e1z);
+  if (!stop && m <= fbits(U.scr_root)) {
+    if (fminf(W0.d0y * e1y, W0.d0z * e1z) <= U.scr) ex = exit32<SIG>(Q, U, W0, a1, b1, n, X);
+    if (!ex && !capA && fminf(e1y * e2y, e1z * e2z) <= U.scr) ex = exit32<SIG>(Q, U, W, a2, b2, n + 1u, X);
+  }
+  advance32<SIG>(Q, U, W, a2, b2, e2y, e2z);
   W.P += (uint64_t)kM0;
-  if (exA || exB) return 1;
-  return near ? 2 : 0;
+  stop = stop || ex || near;
 }
 
-// Precision traits for the persistent loop.
+// Four steps, two pairs.  Returns 0 running, 1 exited, 2 step cap.  With two
+// pairs per call the walker state alternates between two register sets (a
+// pair's old state is live until its exit logic, after its new state
+// exists), so no copies close the loop; a lane whose walk ends in the first
+// pair idles for two steps, against paths of thousands of steps.
+template <int SIG>
+__device__ __forceinline__ int iterate32(const DevReq &Q, const U32<SIG> &U, W32 &W, X32 &X) {
+  bool ex = false, stop = false;
+  const uint32_t n0 = W.n;
+  pair32<SIG, 0>(Q, U, W, X, n0, ex, stop);
+  pair32<SIG, 1>(Q, U, W, X, n0, ex, stop);
+  W.n = n0 + 4u;
+  return ex ? 1 : (stop ? 2 : 0);
+}
+
+// Precision traits for the persistent loop (kPairs: pairs of steps per
+// iterate call, the unit of the slice budget).
 template <int SIG> struct F64 {
+  static constexpr uint32_t kPairs = 1;
   using Walker = W64;
   using Uni = U64<SIG>;
   using Exit = ExitInfo<double>;
@@ -654,6 +688,7 @@ template <int SIG> struct F64 {
   }
 };
 template <int SIG> struct F32 {
+  static constexpr uint32_t kPairs = 2;
   using Walker = W32;
   using Uni = U32<SIG>;
   using Exit = X32;
@@ -769,7 +804,8 @@ __device__ __forceinline__ bool run_request(const DevReq &Q, uint32_t budget, ui
 
   for (;;) {
     uint64_t freemask = __builtin_amdgcn_ballot_w64(!active);
-    // refill every (refill_mask + 1) iterations, and whenever every lane is idle
+    // refill every (refill_mask + 1) pairs of steps (`iters` counts pairs), and
+    // whenever every lane is idle
     const bool refill = ((iters & refill_mask) == 0u) || (freemask == ~0ull);
     if (!refill) freemask = 0ull;
     // (with every lane busy, or between refills, nothing below changes `active`)
@@ -844,7 +880,7 @@ __device__ __forceinline__ bool run_request(const DevReq &Q, uint32_t budget, ui
         finished += 1u;
       }
     }
-    iters += 1u;
+    iters += T::kPairs;
     if (budget != 0u && iters >= budget) {
       // suspend: in-flight walkers to pool_out, the tile remainder to extra_out
       const uint64_t am = __builtin_amdgcn_ballot_w64(active);

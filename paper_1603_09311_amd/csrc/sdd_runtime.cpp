@@ -538,12 +538,15 @@ static void fill_devreq(Prepared &P) {
   // possible once 2 d0 d1 > 12.05 (16.7 dt in unscaled lengths)
   q.fthr = 12.05f;
   q.fscr = 0.5f * q.fthr;
+  q.fscr_root = sqrtf(q.fscr);
+  while (!(q.fscr_root * q.fscr_root > q.fscr)) q.fscr_root = nextafterf(q.fscr_root, INFINITY);
   for (uint32_t k = 0; k <= np; ++k) q.fc[k] = (float)q.c[k];
   q.key0 = (uint32_t)(r.seed & 0xFFFFFFFFu);
   q.key1 = (uint32_t)(r.seed >> 32);
   q.ctr3 = 2u * r.stream;
   q.max_steps = r.max_steps ? r.max_steps : kDefaultMaxSteps;
   q.cap2 = q.max_steps >= 2u ? q.max_steps - 2u : 0u;
+  q.cap2b = q.cap2 >= 2u ? q.cap2 - 2u : 0u;
   q.cap_odd = q.max_steps & 1u;
   q.precision = (uint32_t)r.precision;
   q.M = r.g_samples - 1;
