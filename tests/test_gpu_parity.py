@@ -417,6 +417,25 @@ def test_served_results_equal_blocking(ctx):
     assert e.value.status == sdd.SDD_E_NOTFOUND
 
 
+def test_served_fp32_at_1e3_rel_se_within_3se_of_oracle(ctx, orc):
+    """The served target: FP32-mixed requests of two families submitted
+    together, each asking for a relative standard error of 1e-3 of |g|inf
+    (pilot of 4096 paths, then the extension the pilot variance asks for),
+    each node within 3 SE of the FP64 oracle on the same paths, and every SE
+    at the target (25% slack for the pilot's variance estimate)."""
+    ps = [W.unit_square(paths=1, precision=W.FP32_MIXED, dt=4e-4, n_nodes=4),
+          W.layered_check(n_nodes=4, paths=1, dt=1e-3, precision=W.FP32_MIXED)]
+    tickets = [ctx.submit(p, target_rel_se=1e-3) for p in ps]
+    got = [ctx.wait(t, timeout_s=120) for t in tickets]
+    for p, g in zip(ps, got):
+        n = g["paths_done"].astype(np.uint32)
+        log(f"{p.name}: paths {n.tolist()}, max SE / |g|inf {(g['se'] / p.g_norm).max():.3e}")
+        assert np.all(n > 4096)
+        assert np.all(g["se"] <= 1e-3 * p.g_norm * 1.25)
+        o, _ = oracle_solve(orc, p.replace(path_begin=np.zeros(p.n_nodes, np.uint32), path_count=n))
+        assert_within_se(g, o)
+
+
 def test_served_time_slices_are_exact(ctx):
     """Tiny slices: walkers are suspended and resumed thousands of times;
     every result is still bitwise the blocking one (alone vs in the mix)."""
