@@ -438,10 +438,11 @@ __device__ __forceinline__ int iterate64(const DevReq &Q, const U64<SIG> &U, W64
 // (distance to the wall nearer to the proposal) satisfies d1' <= d1, so the
 // screen min(d0y d1y', d0z d1z') <= 8.35 dt never misses one.
 //
-// One iteration is two steps (one Philox call).  Both steps update the walker
-// unconditionally; an exit in the first step is recorded in the exit info,
-// which the second step leaves alone, and the walker state after an exit is
-// discarded.  This keeps every state update in place (no per-lane merges).
+// A pair of steps uses one Philox call, and one iteration of the persistent
+// loop walks two pairs.  Every step updates the walker unconditionally; an
+// exit is recorded in the exit info, which later steps of the iteration leave
+// alone, and the walker state after an exit (or a step cap) is discarded.
+// This keeps every state update in place (no per-lane merges).
 // ===========================================================================
 struct W32 {
   float a, b;       // y - ymid, z - zmid
