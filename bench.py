@@ -28,6 +28,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -64,10 +65,17 @@ OPS_PER_STEP = 18.5 + 3 + 6 + 4 + 4 + 0.75   # = 36.25
 
 
 def kernel_source_hash() -> str:
+    """Hash of the walker's source as compiled: comments removed and white
+    space collapsed, so that an edit of a comment keeps the recorded counters
+    valid and any change of code invalidates them."""
     h = hashlib.sha256()
     for f in ("sdd_kernels.hip", "sdd_device.h", "sdd_rng.h"):
-        with open(os.path.join(ROOT, "paper_1603_09311_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1603_09311_amd", "csrc", f)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
+        h.update(b"\0")
     return h.hexdigest()[:16]
 
 
