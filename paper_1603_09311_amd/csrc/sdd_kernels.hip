@@ -895,7 +895,7 @@ __device__ __forceinline__ bool run_request(const DevReq &Q, uint32_t budget, ui
         // the capacity is reported to it (the walker is not written)
         if (active && base + r < Q.pool_cap) T::save(W, Q.pool_out[base + r]);
       }
-      if (t_next < t_end) {
+      if (t_next != t_end) {   // (modular: a tile may end at path 2^32)
         uint32_t e = 0;
         if (lane == 0) e = atomicAdd(ctl + kExtraOut, 1u);
         e = uni(e);

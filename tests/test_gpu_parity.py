@@ -334,6 +334,17 @@ def test_edge_cases(ctx, orc):
     o, orec = oracle_solve(orc, pr, records=True)
     assert_records_match(g["records"], orec)
     assert_fp64_parity(g, o)
+    # the top of the 32-bit path range: path indices up to 2^32 - 1
+    top = np.array([0xFFFFFFFF - 299, 0xFFFFFFFF - 64, 0xFFFFFFFF, 0xFFFFFF00, 0, 1, 2, 0xFFFFFFFF - 1], np.uint32)
+    cnt = np.array([300, 65, 1, 256, 3, 3, 3, 2], np.uint32)
+    pt = W.unit_square(paths=1, precision=W.FP64, dt=4e-4).replace(path_begin=top, path_count=cnt)
+    g = ctx.solve(pt, records=True)
+    o, orec = oracle_solve(orc, pt, records=True)
+    assert_records_match(g["records"], orec)
+    assert_fp64_parity(g, o)
+    g32 = ctx.solve(pt, precision=sdd.SDD_FP32_MIXED, records=True)
+    assert np.array_equal(g32["paths_done"], cnt.astype(np.uint64))
+    assert np.mean(g32["records"]["steps"] == g["records"]["steps"]) > 0.98   # paired walks
     # a tiny step cap: unfinished paths counted and left out of the estimate
     pc = W.unit_square(paths=300, precision=W.FP64, dt=4e-4).replace(max_steps=25)
     g = ctx.solve(pc, records=True)
@@ -456,6 +467,23 @@ def test_served_time_slices_are_exact(ctx):
         assert np.array_equal(r["mean"], alone["mean"]) and np.array_equal(r["se"], alone["se"])
     alone = ctx.solve(ps[4], target_rel_se=2e-2)
     assert np.array_equal(got[4]["mean"], alone["mean"]) and np.array_equal(got[4]["paths_done"], alone["paths_done"])
+
+
+def test_served_slices_at_the_top_of_the_path_range(ctx):
+    """Tiles that end at path 2^32, suspended and resumed in tiny slices:
+    every path is walked once, bitwise as in a blocking solve."""
+    top = np.array([0xFFFFFFFF - 299, 0xFFFFFFFF - 64, 0xFFFFFFFF, 0xFFFFFF00], np.uint32)
+    cnt = np.array([300, 65, 1, 256], np.uint32)
+    p = W.unit_square(paths=1, precision=W.FP32_MIXED, dt=4e-4, n_nodes=4).replace(path_begin=top,
+                                                                                  path_count=cnt)
+    try:
+        ctx.set_tuning(slice_iters=8, tile_paths=37)
+        r = ctx.wait(ctx.submit(p, records=True), timeout_s=100)
+    finally:
+        ctx.set_tuning()
+    alone = ctx.solve(p, records=True)
+    assert np.array_equal(r["paths_done"], cnt.astype(np.uint64))
+    assert r["records"].tobytes() == alone["records"].tobytes()
 
 
 def test_served_requests_join_while_others_run(ctx):
