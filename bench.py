@@ -14,6 +14,8 @@ Legs besides the timed workload (each bounded, each can be switched off):
             (a bounded wall time), through the plain FP64 form;
   --mt      pointwise TE apparent resistivity and phase at the COMMEMI 2D-1
             sites (Table 2 of the paper as context);
+  --multifreq  the block model at four frequencies: four requests in one
+            launch against one walk weighted for all four;
   --sdd     domain decomposition of the quarter-space: walks on the
             interfaces, RBF-FD in the sub-domains, surface responses;
   --kappa   the discontinuous-kappa walk on the analytic model of Sec. 4.1
@@ -260,6 +262,42 @@ def served_leg(ctx, n_requests: int, rate_hz: float, paths: int, plain_budget_s:
             "fifo_blocking_baseline": blocking, "plain_fp64_fifo_baseline": plain}
 
 
+def multifreq_leg(ctx, paths: int = 32768):
+    """The block-in-half-space model at 0.1, 1, 10 and 100 Hz (FP32-mixed,
+    1024 nodes on the block edges and the surface, `paths` per node): the
+    four frequencies as four requests in one persistent launch, and as one
+    walk weighted for all four (the TE walk is frequency-free and its phase
+    linear in the frequency), with the largest difference between the two
+    forms in units of the batch's standard errors."""
+    from paper_1603_09311_amd import workloads as W
+    freqs = [0.1, 1.0, 10.0, 100.0]
+    ps = [W.block_in_half_space(f, paths=paths, precision=W.FP32_MIXED) for f in freqs]
+    t0 = time.perf_counter()
+    rb = ctx.solve_batch(ps)
+    wall_b = time.perf_counter() - t0
+    k_b = ctx.stats()["last_walk_ms"]
+    steps_b = sum(float(r["steps"].sum()) for r in rb)
+    t0 = time.perf_counter()
+    rf = ctx.solve_multi_freq(ps[1], freqs, [q.g for q in ps])
+    wall_f = time.perf_counter() - t0
+    k_f = ctx.stats()["last_walk_ms"]
+    steps_f = float(rf[0]["steps"].sum())
+    est = len(freqs) * ps[0].n_nodes
+    z = 0.0
+    for a, b in zip(rb, rf):
+        d = b["mean"] - a["mean"]
+        z = max(z, float(np.nanmax(np.abs(d.real) / a["se_re"])), float(np.nanmax(np.abs(d.imag) / a["se_im"])))
+    return {"workload": "block_in_half_space", "freqs_hz": freqs, "nodes": ps[0].n_nodes, "paths_per_node": paths,
+            "batch_four_requests": {"walk_steps": steps_b, "walk_kernel_ms": k_b,
+                                    "walk_steps_per_s": steps_b / (k_b * 1e-3), "wall_s": wall_b,
+                                    "node_frequency_estimates_per_s": est / wall_b},
+            "one_walk_fanout": {"walk_steps": steps_f, "walk_kernel_ms": k_f,
+                                "walk_steps_per_s": steps_f / (k_f * 1e-3), "wall_s": wall_f,
+                                "node_frequency_estimates_per_s": est / wall_f},
+            "fanout_vs_batch_max_abs_z": z,
+            "max_rel_se": float(max(np.max(r["se"]) for r in rb) / ps[0].g_norm)}
+
+
 # Table 2 of Sec. 4.3 (TE apparent resistivity, ohm m, COMMEMI 2D-1 at 10 Hz):
 # the COMMEMI mean and spread the paper quotes, and the paper's own pointwise
 # stochastic values; context for the mt leg, not a target.
@@ -348,6 +386,7 @@ def main():
     ap.add_argument("--no-mt", action="store_true", help="skip the pointwise MT response leg")
     ap.add_argument("--no-sdd", action="store_true", help="skip the domain decomposition leg")
     ap.add_argument("--no-kappa", action="store_true", help="skip the discontinuous-kappa leg")
+    ap.add_argument("--no-multifreq", action="store_true", help="skip the multi-frequency leg")
     ap.add_argument("--served-requests", type=int, default=24)
     ap.add_argument("--served-rate", type=float, default=8.0)
     args = ap.parse_args()
@@ -452,6 +491,10 @@ def main():
         log(f"served: {out['served']}")
         out["p50_ms"] = out["served"]["p50_ms"]
         out["p99_ms"] = out["served"]["p99_ms"]
+
+    if not args.no_multifreq:
+        out["multi_frequency"] = multifreq_leg(ctx)
+        log(f"multi-frequency: {out['multi_frequency']}")
 
     if not args.no_sdd:
         out["domain_decomposition"] = sdd_leg(ctx)
