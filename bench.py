@@ -16,6 +16,9 @@ Legs besides the timed workload (each bounded, each can be switched off):
             sites (Table 2 of the paper as context);
   --multifreq  the block model at four frequencies: four requests in one
             launch against one walk weighted for all four;
+  --triangles  the triangle family as one uneven batch: a launch per
+            request against one graph-replayed persistent launch, default
+            and autotuned;
   --sdd     domain decomposition of the quarter-space: walks on the
             interfaces, RBF-FD in the sub-domains, surface responses;
   --kappa   the discontinuous-kappa walk on the analytic model of Sec. 4.1
@@ -298,6 +301,55 @@ def multifreq_leg(ctx, paths: int = 32768):
             "max_rel_se": float(max(np.max(r["se"]) for r in rb) / ps[0].g_norm)}
 
 
+def triangle_leg(ctx, n_requests: int = 64, paths_scale: float = 1.0 / 64.0):
+    """The triangle family as one uneven batch: `n_requests` seeded models
+    (a triangle of random shape and conductivity under air, one of eight
+    frequencies, 32..1024 nodes, path counts log-uniform, scaled by
+    paths_scale to bound the leg), FP32-mixed.  Solved one by one (a launch
+    per request), then prepared once and replayed as a HIP graph (one
+    persistent launch for the whole batch) under the default tuning and
+    under the autotuner's choice; results of the three runs compared."""
+    from paper_1603_09311_amd import workloads as W
+    import torch
+    ps = [W.triangle_request(m, paths_scale=paths_scale, M=1024) for m in range(n_requests)]
+
+    def replay():
+        b = ctx.batch(ps)
+        try:
+            b.run()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = b.run()
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+        finally:
+            b.close()
+        return r, wall, ctx.stats()["last_walk_ms"]
+
+    t0 = time.perf_counter()
+    one = [ctx.solve(p) for p in ps]
+    serial_s = time.perf_counter() - t0
+    steps = sum(float(r["steps"].sum()) for r in one)
+    r_def, wall_def, k_def = replay()
+    big = max(ps, key=lambda p: p.n_nodes)
+    try:
+        chosen, trials = ctx.autotune(big)
+        r_tun, wall_tun, k_tun = replay()
+    finally:
+        ctx.set_tuning()
+    same = all(np.array_equal(a["mean"], b["mean"]) and np.array_equal(a["mean"], c["mean"])
+               for a, b, c in zip(one, r_def, r_tun))
+    return {"requests": n_requests, "nodes": sum(p.n_nodes for p in ps), "paths": sum(p.total_paths for p in ps),
+            "frequencies_hz": sorted({p.freq_hz for p in ps}), "walk_steps": steps,
+            "one_launch_per_request": {"wall_s": serial_s, "walk_steps_per_s": steps / serial_s},
+            "graph_batch_default_tuning": {"wall_s": wall_def, "walk_kernel_ms": k_def,
+                                           "walk_steps_per_s": steps / wall_def},
+            "graph_batch_autotuned": {"wall_s": wall_tun, "walk_kernel_ms": k_tun,
+                                      "walk_steps_per_s": steps / wall_tun, "tuning": chosen,
+                                      "trials": len(trials), "tuned_on": big.name},
+            "results_identical": bool(same)}
+
+
 # Table 2 of Sec. 4.3 (TE apparent resistivity, ohm m, COMMEMI 2D-1 at 10 Hz):
 # the COMMEMI mean and spread the paper quotes, and the paper's own pointwise
 # stochastic values; context for the mt leg, not a target.
@@ -387,6 +439,7 @@ def main():
     ap.add_argument("--no-sdd", action="store_true", help="skip the domain decomposition leg")
     ap.add_argument("--no-kappa", action="store_true", help="skip the discontinuous-kappa leg")
     ap.add_argument("--no-multifreq", action="store_true", help="skip the multi-frequency leg")
+    ap.add_argument("--no-triangles", action="store_true", help="skip the uneven triangle batch leg")
     ap.add_argument("--served-requests", type=int, default=24)
     ap.add_argument("--served-rate", type=float, default=8.0)
     args = ap.parse_args()
@@ -495,6 +548,10 @@ def main():
     if not args.no_multifreq:
         out["multi_frequency"] = multifreq_leg(ctx)
         log(f"multi-frequency: {out['multi_frequency']}")
+
+    if not args.no_triangles:
+        out["triangle_batch"] = triangle_leg(ctx)
+        log(f"triangle batch: {out['triangle_batch']}")
 
     if not args.no_sdd:
         out["domain_decomposition"] = sdd_leg(ctx)
