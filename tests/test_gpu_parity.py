@@ -486,6 +486,46 @@ def test_served_slices_at_the_top_of_the_path_range(ctx):
     assert r["records"].tobytes() == alone["records"].tobytes()
 
 
+def test_concurrent_callers_share_one_context(ctx):
+    """Six host threads drive one context at once, mixing blocking solves,
+    served requests and a prepared batch; every result is bitwise the one a
+    single caller gets (one launch sequence at a time on the context's
+    stream, the served worker yielding to waiting callers)."""
+    import threading
+    ps = [W.unit_square(paths=300, precision=W.FP32_MIXED, seed=s) for s in range(3)] + \
+         [small_mixed_model().with_paths(100), W.unit_square(paths=200, precision=W.FP64, seed=9)]
+    ref = [ctx.solve(p, records=True)["records"].tobytes() for p in ps]
+    ok, errs = {}, []
+
+    def worker(i):
+        try:
+            p, want = ps[i % len(ps)], ref[i % len(ps)]
+            for r in range(3):
+                kind = (i + r) % 3
+                if kind == 0:
+                    g = ctx.solve(p, records=True)
+                elif kind == 1:
+                    g = ctx.wait(ctx.submit(p, records=True), timeout_s=100)
+                else:
+                    b = ctx.batch([p], records=True)
+                    try:
+                        g = b.run()[0]
+                    finally:
+                        b.close()
+                ok[(i, r)] = g["records"].tobytes() == want
+        except Exception as e:   # reported below
+            errs.append(repr(e))
+
+    threads = [threading.Thread(target=worker, args=(i,), daemon=True) for i in range(6)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=150)
+    assert not any(t.is_alive() for t in threads), "a caller did not finish"
+    assert not errs, errs
+    assert len(ok) == 18 and all(ok.values()), ok
+
+
 def test_served_requests_join_while_others_run(ctx):
     """Continuous batching: a small request submitted while a long one is on
     the GPU finishes first, and its result equals the blocking one."""
