@@ -538,6 +538,11 @@ int orc_solve(const orc_problem *P, int n_threads, orc_node *out_nodes,
  * a disc point outside the rectangle ends the walk at the nearest boundary
  * point with f = 1; equal kappa: the proposal is kept and the step's time
  * goes to the side of the proposal.
+ * Parity unpinned: how a step that reaches the interface splits its time
+ * between the two sides (the (1/2)(dt - t_gamma) p terms) is pinned only
+ * through the sum (exact time conservation) and the bounds of each share;
+ * its effect is of the order of the scheme's own bias, so no closed form
+ * separates it.
  * Random numbers: counter (n/2, p, j, 4s) -> the normals of steps n, n+1
  * (words 0,1 / 2,3); (n, p, j, 4s+1) -> outer bridge uniforms (words 0, 1),
  * the interface bridge uniform (word 2), the side uniform (word 3);
