@@ -114,7 +114,7 @@ typedef struct {
     uint64_t seed;
     uint32_t stream;            /* < 2^31 */
     uint32_t max_steps;         /* proposals per path before it counts as unfinished; 0 = 2e9 */
-    uint32_t flags;             /* 0, or SDD_FLAG_NO_SIGMA_GRID */
+    uint32_t flags;             /* 0, or SDD_FLAG_NO_SIGMA_GRID | SDD_FLAG_EXIT_NAIVE */
     uint32_t reserved;          /* 0 */
     double target_rel_se;       /* 0: fixed paths.  > 0: a 4096-path pilot per node, then
                                    extended on the same streams to N = ceil((s/(target*|g|inf))^2)
@@ -128,7 +128,14 @@ typedef struct {
  * side, each holding its region or the one boundary inequality that crosses
  * it (cells crossed by more than one use the loop).  Both give the same
  * region for every point, hence the same results; the grid is faster. */
-enum { SDD_FLAG_NO_SIGMA_GRID = 1 };
+enum { SDD_FLAG_NO_SIGMA_GRID = 1, SDD_FLAG_EXIT_NAIVE = 2 };
+
+/* SDD_FLAG_EXIT_NAIVE: an ablation of the exit rule of Sec. 3.1.  A path
+ * leaves the domain only when a proposal lands outside it (the crossing case
+ * of Eq. 14); the Brownian-bridge test for a path that left and came back
+ * within a step is skipped.  Exit times are then biased late by O(sqrt(dt))
+ * and so is the field; the default (flag clear) applies both cases.  Both
+ * precisions, all request kinds. */
 
 /* Per-path record (node-major, path order), for inspection and tests. */
 typedef struct {

@@ -52,6 +52,7 @@ class Problem_C(C.Structure):
         ("seed", C.c_uint64),
         ("stream", C.c_uint32),
         ("max_steps", C.c_uint32),
+        ("naive_exit", C.c_int32),
     ]
 
 
@@ -151,7 +152,7 @@ class _Marshalled:
             p.alpha_direct, p.g.shape[1], self.g.ctypes.data_as(dp), p.n_nodes,
             self.nodes.ctypes.data_as(dp), self.pb.ctypes.data_as(C.POINTER(C.c_uint32)),
             self.pc.ctypes.data_as(C.POINTER(C.c_uint32)), p.dt, p.seed, p.stream,
-            min(int(p.max_steps), 0xFFFFFFFF))
+            min(int(p.max_steps), 0xFFFFFFFF), 1 if getattr(p, "naive_exit", False) else 0)
 
 
 def default_threads() -> int:

@@ -83,6 +83,7 @@ typedef struct {
     uint64_t seed;                /* Philox key */
     uint32_t stream;              /* Philox counter word 3 = 2 stream + domain */
     uint32_t max_steps;           /* proposals per path before giving up */
+    int32_t naive_exit;           /* 1: exit on a crossing only (no bridge test) */
 } orc_problem;
 
 typedef struct {
@@ -308,7 +309,7 @@ int orc_walk_path(const orc_problem *P, int j, uint32_t p, orc_path *out)
             if (d1 <= 0.0) {
                 hit[a] = 1;
                 f[a] = d0 / (d0 - d1);
-            } else {
+            } else if (!P->naive_exit) {
                 double q = (2.0 * d0) * d1;
                 double L = -log(bridge_uniform(P, j, p, n, a));
                 if (q <= P->dt * L) {

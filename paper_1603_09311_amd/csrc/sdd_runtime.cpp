@@ -271,7 +271,8 @@ static sdd_status validate(sdd_ctx *ctx, const sdd_request *r, const HostModel *
   if (r->freq_hz < 0.0 || !std::isfinite(r->freq_hz)) return fail(SDD_E_INVALID, "freq_hz must be >= 0");
   if (r->freq_hz == 0.0 && (!(r->alpha_direct >= 0.0) || !std::isfinite(r->alpha_direct)))
     return fail(SDD_E_INVALID, "alpha_direct must be >= 0 when freq_hz == 0");
-  if (r->flags & ~(uint32_t)SDD_FLAG_NO_SIGMA_GRID) return fail(SDD_E_INVALID, "unknown flags");
+  if (r->flags & ~(uint32_t)(SDD_FLAG_NO_SIGMA_GRID | SDD_FLAG_EXIT_NAIVE))
+    return fail(SDD_E_INVALID, "unknown flags");
   if (!(r->target_rel_se >= 0.0) || !std::isfinite(r->target_rel_se))
     return fail(SDD_E_INVALID, "target_rel_se must be >= 0");
   for (uint32_t k = 0; k < 4 * 2 * r->g_samples; ++k)
@@ -538,6 +539,12 @@ static void fill_devreq(Prepared &P) {
   // possible once 2 d0 d1 > 12.05 (16.7 dt in unscaled lengths)
   q.fthr = 12.05f;
   q.fscr = 0.5f * q.fthr;
+  // naive exits: no bridge test (2 d0 d1 > 0 always exceeds a negative
+  // threshold), crossings only; the screens still flag every crossing
+  if (r.flags & SDD_FLAG_EXIT_NAIVE) {
+    q.thr = -1.0;
+    q.fthr = -1.0f;
+  }
   q.fscr_root = sqrtf(q.fscr);
   while (!(q.fscr_root * q.fscr_root > q.fscr)) q.fscr_root = nextafterf(q.fscr_root, INFINITY);
   for (uint32_t k = 0; k <= np; ++k) q.fc[k] = (float)q.c[k];

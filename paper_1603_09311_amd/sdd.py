@@ -20,6 +20,7 @@ SDD_OK, SDD_E_INVALID, SDD_E_NOMEM, SDD_E_DEVICE = 0, -1, -2, -3
 SDD_E_BUSY, SDD_E_NOTFOUND, SDD_E_TIMEOUT, SDD_E_CANCELLED = -4, -5, -6, -7
 SDD_FP64, SDD_FP32_MIXED = 0, 1
 SDD_FLAG_NO_SIGMA_GRID = 1
+SDD_FLAG_EXIT_NAIVE = 2
 SDD_MAX_REGIONS = 16
 
 
@@ -189,7 +190,9 @@ class _Req:
         self.s = sdd_request(model, prec, p.freq_hz, p.alpha_direct, _ptr(self.g, C.c_double),
                              p.g.shape[1], p.n_nodes, _ptr(self.nodes, C.c_double), _ptr(self.pb, C.c_uint32),
                              _ptr(self.pc, C.c_uint32), 0, p.dt, p.seed, p.stream,
-                             min(int(p.max_steps), 0xFFFFFFFF), flags, 0, target_rel_se)
+                             min(int(p.max_steps), 0xFFFFFFFF),
+                             flags | (SDD_FLAG_EXIT_NAIVE if getattr(p, "naive_exit", False) else 0), 0,
+                             target_rel_se)
         self.n = p.n_nodes
         self.total = int(self.pc.astype(np.uint64).sum())
 

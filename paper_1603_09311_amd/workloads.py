@@ -66,6 +66,7 @@ class Problem:
     max_steps: int = 2_000_000_000
     precision: int = FP64
     name: str = ""
+    naive_exit: bool = False           # exit only on a crossing (no Brownian-bridge test)
 
     @property
     def n_nodes(self) -> int:

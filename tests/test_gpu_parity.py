@@ -356,6 +356,24 @@ def test_edge_cases(ctx, orc):
         assert np.all(g32["paths_done"] + g32["unfinished"] == 300)
 
 
+def test_naive_exit_ablation(ctx, orc):
+    """SDD_FLAG_EXIT_NAIVE (exits on crossings only): FP64 records path by
+    path as the oracle's naive walk, FP32 within 3 SE of it; both exit later
+    than the bridge walk on the same streams."""
+    p = small_mixed_model().with_paths(150).replace(naive_exit=True)
+    g = ctx.solve(p, precision=sdd.SDD_FP64, records=True)
+    o, orec = oracle_solve(orc, p, records=True)
+    assert_records_match(g["records"], orec)
+    assert_fp64_parity(g, o)
+    q = W.unit_square(paths=4096, precision=W.FP32_MIXED, dt=4e-4)
+    g32 = ctx.solve(q.replace(naive_exit=True))
+    o32, _ = oracle_solve(orc, q.replace(naive_exit=True))
+    assert_within_se(g32, o32)
+    bridge = ctx.solve(q)
+    assert np.all(g32["mean_exit_time"] > bridge["mean_exit_time"])
+    assert np.all(g32["steps"] >= bridge["steps"])
+
+
 def test_invalid_requests_rejected(ctx):
     p = W.unit_square(paths=8)
     bad = [p.replace(dt=0.0), p.replace(dt=0.02), p.replace(nodes=np.array([[0.0, 0.5]] * 8)),
