@@ -187,8 +187,10 @@ __device__ __forceinline__ bool kstep(const KReq &Q, KWalker &W, double n0, doub
   const double two_pi = 6.283185307179586476925286766559;
   const double r = s * sqrt(u01_64(d.x));
   const double th = two_pi * u01_64(d.y);
-  const double y = cyc + r * cos(th);
-  const double z = zg + r * sin(th);
+  double sth, cth;
+  sincos(th, &sth, &cth);
+  const double y = cyc + r * cth;
+  const double z = zg + r * sth;
   if (!(y > Q.y_lo && y < Q.y_hi && z > Q.z_lo && z < Q.z_hi)) {
     // the nearest boundary point (ties in the order left, right, top, bottom)
     const double dl = y - Q.y_lo, dr = Q.y_hi - y, dtp = z - Q.z_lo, db = Q.z_hi - z;

@@ -92,8 +92,10 @@ __device__ __forceinline__ void normals64(uint32_t a, uint32_t b, double &n0, do
   const double two_pi = 6.283185307179586476925286766559;
   const double r = sqrt(-2.0 * log(u01_64(a)));
   const double th = two_pi * u01_64(b);
-  n0 = r * cos(th);
-  n1 = r * sin(th);
+  double sn, cs;
+  sincos(th, &sn, &cs);   // one argument reduction for both
+  n0 = r * cs;
+  n1 = r * sn;
 }
 
 // g at the tangential coordinate t of wall `wall` (0 top, 1 right, 2 bottom,
