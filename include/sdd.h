@@ -54,8 +54,10 @@ typedef enum {
 /* Arithmetic of the walk.  SDD_FP64: every step in FP64 (the plain form,
  * identical decisions to an FP64 reference on the same streams).
  * SDD_FP32_MIXED: positions, normals, exit test and region lookup in FP32,
- * the phase integral in compensated FP32 (hi + lo), the per-path weight and
- * the per-node reduction in FP64. */
+ * the phase integral as exact per-region step counts formed in FP64 (models
+ * of air plus at most one half-space, box or triangle) or in compensated
+ * FP32 (hi + lo; other models), the per-path weight and the per-node
+ * reduction in FP64.  Both precisions draw the same random numbers. */
 typedef enum { SDD_FP64 = 0, SDD_FP32_MIXED = 1 } sdd_precision;
 
 /* Conductivity primitives (Sec. 2.2: piecewise-constant sub-domains).
