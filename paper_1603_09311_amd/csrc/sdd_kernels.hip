@@ -306,6 +306,7 @@ __device__ __forceinline__ PathRec unfinished_rec(uint32_t steps) {
 // ===========================================================================
 struct W64 {
   double y, z, S, cc;   // position, phase, phase rate of the current region
+  double dy, dz;        // distance of the position to its nearer wall, per axis
   uint32_t n, path, node;
   uint64_t rec;
   uint64_t P;           // M0 * (n / 2): counter product of the next normal pair
@@ -313,11 +314,12 @@ struct W64 {
 };
 
 template <int SIG> struct U64 {
-  double ylo, yhi, zlo, zhi, s, dt, thr;
+  double ylo, yhi, zlo, zhi, s, dt, thr, thr0;
   uint32_t k0, k1, ctr3, max_steps;
   Reg64<SIG> reg;
   __device__ __forceinline__ void load(const DevReq &Q) {
     ylo = Q.y_lo; yhi = Q.y_hi; zlo = Q.z_lo; zhi = Q.z_hi; s = Q.s; dt = Q.dt; thr = Q.thr;
+    thr0 = thr > 0.0 ? thr : 0.0;
     k0 = Q.key0; k1 = Q.key1; ctr3 = Q.ctr3; max_steps = Q.max_steps;
     reg.load(Q);
   }
@@ -337,14 +339,14 @@ __device__ __forceinline__ void start64(const DevReq &Q, const U64<SIG> &U, W64 
   W.P = 0;
   W.pp = philox_path(path, node, U.k0);
   W.cc = U.reg.eval(Q, W.y, W.z);
+  W.dy = fmin(W.y - U.ylo, U.yhi - W.y);
+  W.dz = fmin(W.z - U.zlo, U.zhi - W.z);
 }
 
-// One FP64 step.  Returns true when the step reaches the outer boundary.
+// The exact exit logic of one step from (W.y, W.z) to (yn, zn): true when
+// the step reaches the outer boundary (recorded in X).
 template <int SIG>
-__device__ __forceinline__ bool step64(const DevReq &Q, const U64<SIG> &U, W64 &W, double n0, double n1,
-                                       ExitInfo<double> &X) {
-  const double yn = W.y + U.s * n0;
-  const double zn = W.z + U.s * n1;
+__device__ __forceinline__ bool exit64(const U64<SIG> &U, const W64 &W, double yn, double zn, ExitInfo<double> &X) {
   // nearer wall per axis; a tie goes to the lower wall
   const double dly = W.y - U.ylo, dhy = U.yhi - W.y;
   const bool upy = !(dly <= dhy);
@@ -395,11 +397,30 @@ __device__ __forceinline__ bool step64(const DevReq &Q, const U64<SIG> &U, W64 &
     }
     return true;
   }
+  return false;
+}
+
+// One FP64 step.  Returns true when the step reaches the outer boundary.
+template <int SIG>
+__device__ __forceinline__ bool step64(const DevReq &Q, const U64<SIG> &U, W64 &W, double n0, double n1,
+                                       ExitInfo<double> &X) {
+  const double yn = W.y + U.s * n0;
+  const double zn = W.z + U.s * n1;
+  // Screen: the distance d1 of the proposal to the wall nearer the current
+  // point is at least e1, its distance to its own nearer wall, so when
+  // 2 d0 e1 > max(thr, 0) on both axes the proposal crossed no wall and no
+  // bridge uniform is needed (rounding is monotone): the step is an ordinary
+  // one, as the exact logic below would find.
+  const double e1y = fmin(yn - U.ylo, U.yhi - yn), e1z = fmin(zn - U.zlo, U.zhi - zn);
+  if (!((2.0 * W.dy) * e1y > U.thr0 && (2.0 * W.dz) * e1z > U.thr0) && exit64<SIG>(U, W, yn, zn, X))
+    return true;
   const double c = U.reg.eval(Q, yn, zn);
   W.S = W.S + c;
   W.cc = c;
   W.y = yn;
   W.z = zn;
+  W.dy = e1y;
+  W.dz = e1z;
   return false;
 }
 
@@ -686,6 +707,8 @@ template <int SIG> struct F64 {
     W.P = (uint64_t)kM0 * (uint64_t)(W.n >> 1);
     W.pp = philox_path(W.path, W.node, U.k0);
     W.cc = U.reg.eval(Q, W.y, W.z);
+    W.dy = fmin(W.y - U.ylo, U.yhi - W.y);
+    W.dz = fmin(W.z - U.zlo, U.zhi - W.z);
   }
 };
 template <int SIG> struct F32 {
