@@ -58,6 +58,24 @@ def halfspace_e0(alpha, z_top):
     return 1.0 / (1.0 - k * z_top)
 
 
+def skin_depth_m(rho_ohm_m, freq_hz):
+    """Plane-wave skin depth in metres by the textbook magnetotelluric rule
+    delta = 503.29 sqrt(rho / f) (rho in ohm m, f in Hz).  The constant is
+    the published one, not derived here from mu0, so a pin built on it does
+    not repeat the oracle's own conversion of a frequency into a phase
+    rate."""
+    return 503.29 * np.sqrt(rho_ohm_m / freq_hz)
+
+
+def air_over_halfspace(k, z, z_top):
+    """Air (alpha = 0, linear field) over a uniform half-space with wave
+    number k (field exp(-k z) below z = 0), normalised to 1 at z_top < 0:
+    E = E0 (1 - k z) for z < 0 and E0 exp(-k z) below, E0 = 1 / (1 - k z_top)."""
+    z = np.asarray(z, dtype=np.float64)
+    e0 = 1.0 / (1.0 - k * z_top)
+    return np.where(z < 0.0, e0 * (1.0 - k * z), e0 * np.exp(-k * z))
+
+
 def zscores(mean, exact, se_re, se_im, bias=0.0):
     """Component z-scores with a stated bias allowance subtracted first."""
     d = np.asarray(mean) - np.asarray(exact)

@@ -33,6 +33,11 @@ MUTANTS = [
      "out[0] = (1.0 - lam) * gw[2 * i + 2] + lam * gw[2 * i + 4];", ["test_table_interpolation_linear_exact"]),
     ("air_phase", "if (P->freq_hz > 0.0) {", "if (sigma == 0.0) return P->alpha_direct;\n    if (P->freq_hz > 0.0) {",
      ["test_layered_halfspace_is_1d"]),
+    ("mu0_without_pi", "double mu0 = 4.0e-7 * pi;", "double mu0 = 4.0e-7;", ["test_frequency_branch_skin_depth"]),
+    ("frequency_for_omega", "double omega = 2.0 * pi * P->freq_hz;", "double omega = P->freq_hz;",
+     ["test_frequency_branch_skin_depth"]),
+    ("length_unit_not_squared", "return omega * mu0 * sigma * (L * L);", "return omega * mu0 * sigma * L;",
+     ["test_frequency_branch_skin_depth"]),
     ("region_order", "for (int r = 0; r < P->n_regions; ++r)\n        if (in_primitive",
      "for (int r = P->n_regions - 1; r >= 0; --r)\n        if (in_primitive", ["test_region_predicate"]),
     # the discontinuous-kappa walk

@@ -335,6 +335,31 @@ def test_layered_halfspace_is_1d(orc):
     _check(res, exact, bias=2e-3)
 
 
+def test_frequency_branch_skin_depth(orc):
+    """A model entered by frequency, conductivity and a length unit in metres
+    (the TE equation of Sec. 2.1 as measured): air over a 100 ohm m
+    half-space, lengths in units of L = 5 km, at 1 Hz and at 4 Hz.  Below the
+    surface the 1-D TE field decays as exp(-(1 + i) z / delta) with the skin
+    depth of the textbook rule delta = 503.29 sqrt(rho / f) m, and with that
+    1-D field on every wall the 2-D solution is the 1-D field at every node.
+    This pins alpha = omega mu0 sigma L^2 end to end: the angular frequency
+    2 pi f (not f), mu0 = 4 pi 1e-7 H/m (Sec. 2.1 prints 4e-7) and the
+    squared length unit."""
+    walls = (-2.0, 2.0, -1.0, 3.0)
+    L = 5000.0
+    zs = np.linspace(-0.75, 2.75, 8)
+    nodes = np.stack([np.full(8, 0.3), zs], axis=1)
+    for f in (1.0, 4.0):
+        k = (1.0 + 1.0j) * L / CF.skin_depth_m(100.0, f)
+        fn = lambda y, z: CF.air_over_halfspace(k, z, walls[2]) + 0.0 * np.asarray(y)  # noqa: E731
+        p = W.Problem(*walls, regions=[W.Region(W.HALF_Z_LT, (0.0,), 0.0)], sigma_background=0.01,
+                      length_unit_m=L, freq_hz=f, alpha_direct=0.0, g=W.tables_from_function(fn, walls, 4096),
+                      nodes=nodes, path_begin=np.zeros(8, np.uint32), path_count=np.full(8, 4096, np.uint32),
+                      dt=4e-4, seed=11)
+        res, _ = orc.solve(p)
+        _check(res, fn(nodes[:, 0], nodes[:, 1]), bias=2e-3)
+
+
 def test_mirror_symmetry(orc):
     """Mirror-symmetric model and data: E(y, z) = E(1 - y, z)."""
     p = W.unit_square(alpha=20.0, paths=8192, dt=4e-4, seed=9,
