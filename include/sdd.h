@@ -120,7 +120,9 @@ typedef struct {
     uint32_t reserved;          /* 0 */
     double target_rel_se;       /* 0: fixed paths.  > 0: a 4096-path pilot per node, then
                                    extended on the same streams to N = ceil((s/(target*|g|inf))^2)
-                                   (capped at 2^20), s^2 = var_re + var_im of the pilot */
+                                   (capped at 2^20), s^2 = var_re + var_im of the pilot.  The
+                                   target is relative to |g|inf, the largest modulus in g_tables,
+                                   not to each node's own estimate: SE <= target |g|inf */
 } sdd_request;
 
 /* Request flags.  SDD_FLAG_NO_SIGMA_GRID: an FP32-mixed request whose model
@@ -147,6 +149,26 @@ typedef struct {
     int32_t wall;        /* 0 top, 1 right, 2 bottom, 3 left; -1 unfinished */
 } sdd_path_record;
 
+/* Diagnostics of one solve, written when sdd_result.diag is not NULL.
+ *   rho_dt        the largest phase one full step adds, max over regions of
+ *                 alpha_r dt / 2 (kappa walk: max_i |lambda_i| dt).  The
+ *                 paper chooses dt proportional to dx^2 (Sec. 4.1) so that
+ *                 the phase is resolved; rho_dt > 0.1 sets
+ *                 SDD_DIAG_DT_UNRESOLVED: the result carries a time-step bias
+ *                 that the Monte-Carlo error does not show.
+ *   g_norm        |g|inf, the largest modulus in the request's tables (the
+ *                 scale of target_rel_se).
+ *   se_over_gnorm the largest se (third column of sdd_result.se) over the
+ *                 nodes divided by g_norm. */
+typedef struct {
+    double rho_dt;
+    uint32_t flags;          /* SDD_DIAG_* */
+    uint32_t reserved;
+    double g_norm;
+    double se_over_gnorm;
+} sdd_diag;
+#define SDD_DIAG_DT_UNRESOLVED 1u
+
 /* Results per node (arrays of n_nodes rows; every pointer but `mean` is nullable). */
 typedef struct {
     double *mean;            /* n x 2: re, im */
@@ -157,6 +179,7 @@ typedef struct {
     uint64_t *unfinished;    /* n: paths that reached max_steps */
     double *mean_exit_time;  /* n */
     sdd_path_record *path_records; /* sum of path counts; fixed-path requests only */
+    sdd_diag *diag;          /* one per request */
 } sdd_result;
 
 /* Launch shape of the persistent walker (0 = automatic). */
@@ -246,6 +269,13 @@ typedef struct {
     uint64_t last_walk_paths;     /* paths walked by that launch */
     uint32_t last_blocks, last_threads;  /* launch shape of the last persistent walk */
     uint64_t launches;            /* walk launches since sdd_create */
+    /* served mode, since sdd_create */
+    uint32_t served_in_flight_max;  /* most requests walked together in one slice */
+    uint32_t served_waits;          /* requests that waited in the queue for workspace */
+    uint32_t served_requeues;       /* target-SE requests whose extension did not fit next to the
+                                       others: they gave their workspace back and were walked again
+                                       in one pass, all paths, once admitted (same results) */
+    uint32_t reserved;
 } sdd_stats;
 
 sdd_status sdd_get_stats(sdd_ctx_t ctx, sdd_stats *out);
@@ -386,7 +416,8 @@ typedef struct {
  * passes 2^32, more than 2^40 paths), SDD_E_NOMEM (workspace), SDD_E_DEVICE. */
 sdd_status sdd_solve_kappa(sdd_ctx_t ctx, const sdd_kappa_request *req, sdd_result *res);
 
-/* Bytes of workspace a request needs (tables, nodes, tiles, records). */
+/* Bytes of workspace a request needs (tables, nodes, tiles, records; for a
+ * target-SE request the pilot and the largest extension). */
 sdd_status sdd_request_footprint(sdd_ctx_t ctx, const sdd_request *req, uint64_t *bytes);
 
 const char *sdd_status_string(sdd_status s);

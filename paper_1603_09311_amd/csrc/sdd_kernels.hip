@@ -868,8 +868,14 @@ __device__ __forceinline__ bool run_request(const DevReq &Q, uint32_t budget, ui
               else extra_done = true;
             }
             if (src == nullptr) {
-              uint32_t t = 0;
-              if (lane == 0) t = atomicAdd(Q.tile_counter, 1u);
+              // a request whose tiles are all claimed is left alone: the
+              // counter moves past n_tiles only in a race between waves
+              // that both saw a tile left (at most one step per wave)
+              uint32_t t = n_tiles;
+              if (lane == 0) {
+                t = __hip_atomic_load(Q.tile_counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (t < n_tiles) t = atomicAdd(Q.tile_counter, 1u);
+              }
               t = uni(t);
               if (t >= n_tiles) { exhausted = true; break; }
               src = Q.tiles + t;

@@ -178,6 +178,7 @@ struct Ticket {
   sdd_result res{};
   sdd_status status = SDD_OK;
   bool done = false, cancelled = false;
+  bool waited = false;             // admission once had to wait for workspace
   std::string error;
 };
 
@@ -204,15 +205,30 @@ struct sdd_ctx {
     std::lock_guard<std::mutex> lk(mu);
     return arena.alloc(b);
   }
+  // Every release moves the memory epoch and wakes the served worker, which
+  // may be waiting for workspace to admit a request.
   void release(char *p) {
-    std::lock_guard<std::mutex> lk(mu);
-    arena.release(p);
+    if (!p) return;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      arena.release(p);
+      ++epoch;
+    }
+    cv.notify_all();
   }
+  uint64_t epoch = 0;              // bumped by every release, submit, cancel and stop
+  uint64_t held_long = 0;          // workspace held by resident models and prepared batches
+  uint64_t reserved = 0;           // workspace promised to served flights
+  uint32_t served_in_flight_max = 0, served_waits = 0, served_requeues = 0;
   std::unordered_map<uint32_t, std::unique_ptr<HostModel>> models;
   uint32_t next_model = 1;
   // served mode
   std::unordered_map<uint64_t, std::shared_ptr<Ticket>> tickets;
   std::deque<std::shared_ptr<Ticket>> queue;
+  // target-SE flights whose extension did not fit next to the others: they
+  // gave their workspace back and walk all their paths in one pass once
+  // admitted again (ahead of the queue)
+  std::deque<std::shared_ptr<Ticket>> requeue;
   uint64_t next_ticket = 1;
   std::condition_variable cv, done_cv;
   std::thread worker;
@@ -934,11 +950,17 @@ static sdd_status reduce_passes(sdd_ctx *ctx, std::vector<Prepared *> &passes, s
   return st;
 }
 
+// |g|inf of a request's tables (interleaved re, im).
+static double g_norm(const std::vector<double> &g) {
+  double m = 0.0;
+  for (size_t k = 0; k + 1 < g.size(); k += 2) m = std::max(m, std::hypot(g[k], g[k + 1]));
+  return m;
+}
+
 // After a pilot pass: decide each node's path count and set up the extension.
 static void plan_extension(Prepared &P, const NodeOut *pilot_rows) {
   const uint32_t n = (uint32_t)P.pbeg_all.size();
-  double gnorm = 0.0;
-  for (size_t k = 0; k + 1 < P.g.size(); k += 2) gnorm = std::max(gnorm, std::hypot(P.g[k], P.g[k + 1]));
+  const double gnorm = g_norm(P.g);
   const double target = P.req.target_rel_se * (gnorm > 0 ? gnorm : 1.0);
   P.pilot_off = P.rec_off;
   P.pilot_cnt = P.pcnt;
@@ -968,8 +990,26 @@ static void scatter_rows(uint32_t n, const NodeOut *rows, sdd_result *res) {
   }
 }
 
+// The diagnostics block of a result: rho_dt, its flag, |g|inf and the
+// largest se / |g|inf over the nodes.
+static void fill_diag(sdd_diag *d, double rho_dt, double gn, uint32_t n, const NodeOut *rows) {
+  if (!d) return;
+  std::memset(d, 0, sizeof(*d));
+  d->rho_dt = rho_dt;
+  d->flags = rho_dt > 0.1 ? SDD_DIAG_DT_UNRESOLVED : 0u;
+  d->g_norm = gn;
+  double se = 0.0;
+  for (uint32_t j = 0; j < n; ++j)
+    if (std::isfinite(rows[j].se)) se = std::max(se, rows[j].se);
+  d->se_over_gnorm = gn > 0.0 ? se / gn : 0.0;
+}
+
 static void scatter(const Prepared &P, const NodeOut *rows, sdd_result *res) {
-  scatter_rows((uint32_t)P.pbeg_all.size(), rows, res);
+  const uint32_t n = (uint32_t)P.pbeg_all.size();
+  scatter_rows(n, rows, res);
+  double rho = 0.0;
+  for (uint32_t k = 0; k <= P.dreq.nprims; ++k) rho = std::max(rho, P.dreq.c[k]);
+  fill_diag(res->diag, rho, g_norm(P.g), n, rows);
 }
 
 static sdd_status copy_records(sdd_ctx *ctx, const Prepared &P, sdd_result *res) {
@@ -1035,14 +1075,19 @@ static sdd_status execute(sdd_ctx *ctx, std::vector<Prepared *> &Ps, std::vector
   return SDD_OK;
 }
 
-// Workspace a request needs while it runs (upper bound for target-SE
-// requests, whose extension size is known only after the pilot).
-static uint64_t footprint(sdd_ctx *ctx, Prepared &P) {
+// Workspace a request's current pass needs while it runs: tables, nodes,
+// sigma grid, tiles, records, the reduction and the launch descriptors.  A
+// target-SE request's first pass is its pilot; with `upper`, its extension
+// at the largest size (2^20 paths per node) is added: the bound for a
+// blocking solve, which keeps the pilot's records while it walks the
+// extension.
+static uint64_t footprint(sdd_ctx *ctx, Prepared &P, bool upper) {
   build_tiles(P, tile_size(ctx, P), launch_waves_estimate(ctx));
   const uint64_t n = P.pbeg.size();
   uint64_t b = pass_bytes(P) + Arena::round(n * (sizeof(NodeOut) + sizeof(NodeJob))) + 4 * 1024 +
                Arena::round(sizeof(DevReq) * 2);
-  if (P.req.target_rel_se > 0.0) b += Arena::round(n * (uint64_t)kMaxTargetPaths * sizeof(PathRec));
+  if (upper && P.req.target_rel_se > 0.0 && P.pass == 0)
+    b += Arena::round(n * (uint64_t)kMaxTargetPaths * sizeof(PathRec));
   return b;
 }
 
@@ -1071,8 +1116,20 @@ struct Flight {
   uint32_t pool_n = 0, extra_n = 0;
   uint32_t tile_counter = 0;
   uint64_t done = 0;
-  uint64_t reserved = 0;   // workspace bytes counted at admission
+  uint64_t reserved = 0;   // workspace bytes promised to this flight
+  bool requeue = false;    // give the workspace back and wait for admission again
 };
+
+// Suspension pools of a served flight at the launch shape of its own walker
+// build: two buffers of suspended walkers (each up to two per lane: the
+// slice's own and those a narrower launch left) and two of tile remainders
+// (two per wave).
+static uint64_t pool_bytes(sdd_ctx *ctx, const Prepared &P) {
+  uint32_t blocks, threads;
+  launch_shape(ctx, (int)P.dreq.precision, P.dreq.sig, blocks, threads);
+  const uint64_t lanes = (uint64_t)blocks * threads, waves = lanes / 64;
+  return 2 * Arena::round(2 * lanes * sizeof(SuspRec)) + 2 * Arena::round(2 * waves * sizeof(DevTile));
+}
 
 // Control words of one flight for one slice (device and host copies).
 struct FlightCtl {
@@ -1096,10 +1153,12 @@ static void release_flight(sdd_ctx *ctx, Flight &F) {
 // entries of the input pools that the slice leaves unclaimed (carried over by
 // the host; a launch may have fewer lanes than the previous slice had).
 // Suspended walkers already waiting in the input pool are kept.
+// The first pools hold two per lane and per wave (what the flight's
+// reservation counts), so slices at one launch shape never reallocate them.
 static sdd_status ensure_pools(sdd_ctx *ctx, Flight &F, uint32_t lanes, uint32_t waves) {
   const uint32_t need_p = lanes + F.pool_n, need_e = waves + F.extra_n;
   if (F.pool_cap >= need_p && F.extra_cap >= need_e && F.d_pool[0]) return SDD_OK;
-  const uint32_t cap_p = std::max(need_p, F.pool_cap), cap_e = std::max(need_e, F.extra_cap);
+  const uint32_t cap_p = std::max({need_p, F.pool_cap, 2 * lanes}), cap_e = std::max({need_e, F.extra_cap, 2 * waves});
   char *np[2] = {ctx->alloc((size_t)cap_p * sizeof(SuspRec)), ctx->alloc((size_t)cap_p * sizeof(SuspRec))};
   char *ne[2] = {ctx->alloc((size_t)cap_e * sizeof(DevTile)), ctx->alloc((size_t)cap_e * sizeof(DevTile))};
   if (!np[0] || !np[1] || !ne[0] || !ne[1]) {
@@ -1233,10 +1292,90 @@ static sdd_status run_slice(sdd_ctx *ctx, std::vector<Flight *> &fl, int precisi
     F.par = out;
     F.pool_n = c.slice[kPoolOut] + carry_p;
     F.extra_n = c.slice[kExtraOut] + carry_e;
-    F.tile_counter = c.tile_counter;
+    // claims past the last tile (waves racing for it) carry no work: the next
+    // slice starts from n_tiles at most, so the counter never wraps
+    F.tile_counter = std::min(c.tile_counter, F.P->dreq.n_tiles);
     F.done = c.done;
   }
   return SDD_OK;
+}
+
+// Hands a flight's workspace back: its passes, its pools and its reservation.
+static void drop_flight(sdd_ctx *ctx, Flight &F) {
+  release_flight(ctx, F);
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->reserved -= std::min(ctx->reserved, F.reserved);
+  F.reserved = 0;
+}
+
+// After a target-SE pilot: reduce it, plan each node's path count and set up
+// the extension.  The extension gets the workspace it needs if that fits
+// next to the other flights' reservations; otherwise the flight gives all of
+// its workspace back (pilot records included) and is re-queued to walk every
+// path of every node in one pass once admitted again -- the same paths, read
+// by the reduction in the same order, so the result is the same bit for bit.
+static sdd_status start_extension(sdd_ctx *ctx, Flight &F) {
+  Prepared &P = *F.P;
+  std::vector<Prepared *> one{&P};
+  std::vector<NodeOut> rows;
+  sdd_status st = reduce_passes(ctx, one, rows);
+  if (st != SDD_OK) return st;
+  plan_extension(P, rows.data());
+  P.d_recs_pilot = P.d_recs;
+  P.d_recs = nullptr;
+  release_pass(ctx, P);
+  const uint64_t pilot_recs = Arena::round(P.n_paths * sizeof(PathRec) + 16);
+  const uint64_t need = footprint(ctx, P, false) + pilot_recs + pool_bytes(ctx, P);
+  bool fits;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const uint64_t cap = ctx->arena.size() > ctx->held_long ? ctx->arena.size() - ctx->held_long : 0;
+    fits = ctx->reserved - F.reserved + need <= cap;
+    if (fits && need > F.reserved) {
+      ctx->reserved += need - F.reserved;
+      F.reserved = need;
+    }
+  }
+  if (ctx->debug)
+    std::fprintf(stderr, "[sdd] extension needs %llu (reserved %llu): %s\n", (unsigned long long)need,
+                 (unsigned long long)F.reserved, fits ? "fits" : "re-queued");
+  st = fits ? upload_pass(ctx, P) : SDD_E_NOMEM;
+  if (st == SDD_OK) {
+    F.uploaded = true;
+    F.tile_counter = 0;
+    F.done = 0;
+    F.pool_n = F.extra_n = 0;
+    return SDD_OK;
+  }
+  if (st != SDD_E_NOMEM) return st;
+  ctx->release(P.d_recs_pilot);
+  P.d_recs_pilot = nullptr;
+  P.pbeg = P.pbeg_all;
+  P.pcnt = P.pcnt_all;
+  P.pass = 2;
+  F.requeue = true;
+  return SDD_OK;
+}
+
+// Moves the flights marked for re-queueing back to the front of the
+// admission order (in their order), their workspace given back.
+static void requeue_flights(sdd_ctx *ctx, std::vector<std::unique_ptr<Flight>> &flights) {
+  std::vector<std::shared_ptr<Ticket>> back;
+  for (auto &F : flights) {
+    if (!F->requeue) continue;
+    drop_flight(ctx, *F);
+    back.push_back(F->T);
+    F->P = nullptr;
+  }
+  if (back.empty()) return;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (auto &T : back) ctx->served_requeues += T->P && T->P->pass == 2 ? 1u : 0u;
+  }
+  flights.erase(std::remove_if(flights.begin(), flights.end(), [](const std::unique_ptr<Flight> &F) { return F->P == nullptr; }),
+                flights.end());
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  for (auto it = back.rbegin(); it != back.rend(); ++it) ctx->requeue.push_front(*it);
 }
 
 // Finish the flights whose pass has every path done: a pilot is turned into
@@ -1244,32 +1383,16 @@ static sdd_status run_slice(sdd_ctx *ctx, std::vector<Flight *> &fl, int precisi
 static void complete_flights(sdd_ctx *ctx, std::vector<std::unique_ptr<Flight>> &flights) {
   std::vector<Flight *> fin;
   for (auto &F : flights) {
-    if (F->done < F->P->n_paths || F->pool_n || F->extra_n) continue;
-    if (F->P->req.target_rel_se > 0.0 && F->P->pass == 0) {
-      std::vector<Prepared *> one{F->P};
-      std::vector<NodeOut> rows;
-      sdd_status st = reduce_passes(ctx, one, rows);
-      if (st == SDD_OK) {
-        plan_extension(*F->P, rows.data());
-        F->P->d_recs_pilot = F->P->d_recs;
-        F->P->d_recs = nullptr;
-        release_pass(ctx, *F->P);
-        st = upload_pass(ctx, *F->P);
-      }
-      if (st == SDD_OK) {
-        F->uploaded = true;
-        F->tile_counter = 0;
-        F->done = 0;
-        F->pool_n = F->extra_n = 0;
-        continue;
-      }
+    if (F->requeue || F->done < F->P->n_paths || F->pool_n || F->extra_n) continue;
+    if (F->P->req.target_rel_se > 0.0 && F->P->pass == 0 && F->T->status == SDD_OK) {
+      const sdd_status st = start_extension(ctx, *F);
+      if (st == SDD_OK) continue;
       F->T->error = g_last_error;
       F->T->status = st;
-      fin.push_back(F.get());
-      continue;
     }
     fin.push_back(F.get());
   }
+  requeue_flights(ctx, flights);
   if (fin.empty()) return;
   std::vector<Prepared *> Ps;
   for (auto *F : fin)
@@ -1292,7 +1415,7 @@ static void complete_flights(sdd_ctx *ctx, std::vector<std::unique_ptr<Flight>> 
     }
     row += P->pbeg.size();
   }
-  for (auto *F : fin) release_flight(ctx, *F);
+  for (auto *F : fin) drop_flight(ctx, *F);
   {
     std::lock_guard<std::mutex> lk(ctx->mu);
     for (auto *F : fin) {
@@ -1306,73 +1429,117 @@ static void complete_flights(sdd_ctx *ctx, std::vector<std::unique_ptr<Flight>> 
   ctx->done_cv.notify_all();
 }
 
+// Admission (caller holds ctx->mu): re-queued flights first, then the queue,
+// each in order, while the promised footprints fit in the workspace less
+// what models and prepared batches hold.  A request that could not fit even
+// in that much is failed with SDD_E_NOMEM; one that only has to wait for
+// memory keeps its place and everything behind it waits too.
+static void admit(sdd_ctx *ctx, std::vector<std::unique_ptr<Flight>> &flights) {
+  const uint64_t cap = ctx->arena.size() > ctx->held_long ? ctx->arena.size() - ctx->held_long : 0;
+  for (auto *q : {&ctx->requeue, &ctx->queue}) {
+    while (!q->empty()) {
+      auto T = q->front();
+      const uint64_t need = footprint(ctx, *T->P, false) + pool_bytes(ctx, *T->P);
+      if (need > cap) {
+        q->pop_front();
+        char msg[192];
+        std::snprintf(msg, sizeof(msg),
+                      "request needs %llu bytes of workspace; %llu are left beside the resident models and "
+                      "prepared batches",
+                      (unsigned long long)need, (unsigned long long)cap);
+        finish_ticket(ctx, *T, SDD_E_NOMEM, msg);
+        T->P.reset();
+        ctx->done_cv.notify_all();
+        continue;
+      }
+      if (ctx->reserved + need > cap) {   // wait for memory to free up
+        if (!T->waited) {
+          T->waited = true;
+          ++ctx->served_waits;
+        }
+        if (ctx->debug)
+          std::fprintf(stderr, "[sdd] admission waits: needs %llu, %llu of %llu promised\n",
+                       (unsigned long long)need, (unsigned long long)ctx->reserved, (unsigned long long)cap);
+        return;
+      }
+      auto F = std::make_unique<Flight>();
+      F->T = T;
+      F->P = T->P.get();
+      F->reserved = need;
+      ctx->reserved += need;
+      if (ctx->debug)
+        std::fprintf(stderr, "[sdd] admitted (%s): reserves %llu, %llu of %llu promised\n",
+                     q == &ctx->requeue ? "again, one pass" : "new", (unsigned long long)need,
+                     (unsigned long long)ctx->reserved, (unsigned long long)cap);
+      flights.push_back(std::move(F));
+      q->pop_front();
+      ctx->served_in_flight_max = std::max(ctx->served_in_flight_max, (uint32_t)flights.size());
+    }
+  }
+}
+
 static void worker_main(sdd_ctx *ctx) {
   // if this fails, the worker's first HIP call fails too and its tickets
   // report SDD_E_DEVICE
   (void)hipSetDevice(ctx->device);
   std::vector<std::unique_ptr<Flight>> flights;
-  uint64_t reserved = 0;   // workspace promised to flights
+  // memory epoch at which admission last stalled with nothing in flight: the
+  // worker then sleeps until memory is released or the queue changes
+  uint64_t stalled_at = ~0ull;
   for (;;) {
     std::vector<std::unique_ptr<Flight>> dropped;
+    bool stop;
     {
       std::unique_lock<std::mutex> lk(ctx->mu);
-      ctx->cv.wait(lk, [&] { return ctx->stop || !ctx->queue.empty() || !flights.empty(); });
-      if (ctx->stop) {
-        for (auto &T : ctx->queue) {
-          T->cancelled = true;
-          finish_ticket(ctx, *T, SDD_E_CANCELLED, "context destroyed");
-          T->P.reset();
+      ctx->cv.wait(lk, [&] {
+        return ctx->stop || !flights.empty() ||
+               ((!ctx->queue.empty() || !ctx->requeue.empty()) && ctx->epoch != stalled_at);
+      });
+      stop = ctx->stop;
+      if (stop) {
+        for (auto *q : {&ctx->queue, &ctx->requeue}) {
+          for (auto &T : *q) {
+            T->cancelled = true;
+            finish_ticket(ctx, *T, SDD_E_CANCELLED, "context destroyed");
+            T->P.reset();
+          }
+          q->clear();
         }
-        ctx->queue.clear();
         for (auto &F : flights) F->T->cancelled = true;
       }
       // cancelled flights leave at the slice boundary
       for (auto &F : flights)
         if (F->T->cancelled) dropped.push_back(std::move(F));
       flights.erase(std::remove(flights.begin(), flights.end(), nullptr), flights.end());
-      // admission by workspace: FIFO while the footprints fit
-      while (!ctx->stop && !ctx->queue.empty()) {
-        auto T = ctx->queue.front();
-        const uint64_t pools = 2ull * 1024 * 1024 * 64 + 2ull * 64 * 1024 * 32;   // at most 2^20 lanes
-        const uint64_t need = footprint(ctx, *T->P) + pools;
-        if (need > ctx->arena.size()) {
-          ctx->queue.pop_front();
-          finish_ticket(ctx, *T, SDD_E_NOMEM, "request can never fit in the workspace");
-          T->P.reset();
-          continue;
-        }
-        // the promised footprints of everything in flight stay within the
-        // workspace (what blocking callers and models hold counts too)
-        const uint64_t others = ctx->arena.used() > reserved ? ctx->arena.used() - reserved : 0;
-        if (reserved + need + others > ctx->arena.size()) break;   // wait for memory to free up
-        auto F = std::make_unique<Flight>();
-        F->T = T;
-        F->P = T->P.get();
-        F->reserved = need;
-        reserved += need;
-        flights.push_back(std::move(F));
-        ctx->queue.pop_front();
-      }
+      if (!stop) admit(ctx, flights);
+      if (flights.empty()) stalled_at = ctx->epoch;
     }
     for (auto &F : dropped) {
       auto ex = worker_exec(ctx);
-      release_flight(ctx, *F);
-      reserved -= F->reserved;
+      drop_flight(ctx, *F);
       std::lock_guard<std::mutex> lk(ctx->mu);
       finish_ticket(ctx, *F->T, SDD_E_CANCELLED, "cancelled");
       F->T->P.reset();
     }
     if (!dropped.empty()) ctx->done_cv.notify_all();
-    if (ctx->stop && flights.empty()) return;
+    if (stop && flights.empty()) return;
     if (flights.empty()) continue;
     {
       auto ex = worker_exec(ctx);
-      // upload newly admitted requests
+      // upload newly admitted requests.  While the worker holds exec, blocking
+      // callers hold no workspace, so a request whose reservation fitted but
+      // whose buffers do not (a fragmented workspace) waits for the running
+      // flights to give theirs back, and fails if none is running.
+      bool running = false;
+      for (auto &F : flights) running = running || F->uploaded;
       for (auto &F : flights) {
         if (F->uploaded) continue;
         sdd_status st = upload_pass(ctx, *F->P);
         if (st == SDD_OK) {
           F->uploaded = true;
+          running = true;
+        } else if (st == SDD_E_NOMEM && running) {
+          F->requeue = true;
         } else {
           F->T->status = st;
           F->T->error = g_last_error;
@@ -1380,13 +1547,13 @@ static void worker_main(sdd_ctx *ctx) {
           F->uploaded = true;
         }
       }
+      requeue_flights(ctx, flights);
       // one slice per precision present
-      sdd_status st = SDD_OK;
       for (int prec : {SDD_FP32_MIXED, SDD_FP64}) {
         std::vector<Flight *> group;
         for (auto &F : flights)
           if ((int)F->P->dreq.precision == prec && F->T->status == SDD_OK) group.push_back(F.get());
-        st = run_slice(ctx, group, prec);
+        const sdd_status st = run_slice(ctx, group, prec);
         if (st != SDD_OK) {
           for (auto *F : group) {
             F->T->status = st;
@@ -1404,12 +1571,7 @@ static void worker_main(sdd_ctx *ctx) {
                        F->extra_n);
         std::fprintf(stderr, "\n");
       }
-      const size_t before = flights.size();
-      uint64_t freed = 0;
-      for (auto &F : flights) freed += F->reserved;
       complete_flights(ctx, flights);
-      for (auto &F : flights) freed -= F->reserved;
-      if (flights.size() != before) reserved -= freed;
     }
   }
 }
@@ -1467,6 +1629,7 @@ sdd_status sdd_destroy(sdd_ctx_t ctx) {
   {
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->stop = true;
+    ++ctx->epoch;
   }
   ctx->cv.notify_all();
   if (ctx->worker.joinable()) ctx->worker.join();
@@ -1530,6 +1693,7 @@ sdd_status sdd_model_create(sdd_ctx_t ctx, const sdd_model_desc *d, sdd_model_t 
   std::lock_guard<std::mutex> lk(ctx->mu);
   const uint32_t id = ctx->next_model++;
   ctx->models[id] = std::move(m);
+  ctx->held_long += Arena::round(sizeof(DevModel));
   *out = id;
   return SDD_OK;
 }
@@ -1543,6 +1707,9 @@ sdd_status sdd_model_destroy(sdd_ctx_t ctx, sdd_model_t model) {
   if (busy > 0) return fail(SDD_E_BUSY, "model %u is used by %d requests in flight", model, busy);
   ctx->arena.release(it->second->dev);
   ctx->models.erase(it);
+  ctx->held_long -= std::min<uint64_t>(ctx->held_long, Arena::round(sizeof(DevModel)));
+  ++ctx->epoch;
+  ctx->cv.notify_all();
   return SDD_OK;
 }
 
@@ -1674,7 +1841,15 @@ sdd_status sdd_solve_multi_freq(sdd_ctx_t ctx, const sdd_request *req, uint32_t 
   ctx->release(d_jobs);
   ctx->release(d_out);
   if (st == SDD_OK)
-    for (uint32_t k = 0; k < n_freq; ++k) scatter(*P, rows.data() + (uint64_t)k * n, &res[k]);
+    for (uint32_t k = 0; k < n_freq; ++k) {
+      const NodeOut *rk = rows.data() + (uint64_t)k * n;
+      scatter_rows(n, rk, &res[k]);
+      // the phase per step scales with the frequency; each frequency has its tables
+      double rho = 0.0;
+      for (uint32_t r = 0; r <= P->dreq.nprims; ++r) rho = std::max(rho, P->dreq.c[r]);
+      fill_diag(res[k].diag, rho * (freqs[k] / ref), g_norm(std::vector<double>(g_tables[k], g_tables[k] + tab)),
+                n, rk);
+    }
   release_all(ctx, *P);
   return st;
 }
@@ -1718,6 +1893,7 @@ sdd_status sdd_submit(sdd_ctx_t ctx, const sdd_request *req, sdd_result *res, sd
     const uint64_t id = ctx->next_ticket++;
     ctx->tickets[id] = T;
     ctx->queue.push_back(T);
+    ++ctx->epoch;
     if (!ctx->worker.joinable()) ctx->worker = std::thread(worker_main, ctx);
     *out = id;
   }
@@ -1767,12 +1943,18 @@ sdd_status sdd_cancel(sdd_ctx_t ctx, sdd_ticket_t t) {
   auto T = it->second;
   if (T->done) return fail(SDD_E_BUSY, "ticket %llu already finished", (unsigned long long)t);
   T->cancelled = true;
-  auto q = std::find(ctx->queue.begin(), ctx->queue.end(), T);
-  if (q != ctx->queue.end()) {   // not admitted yet: finish it now
-    ctx->queue.erase(q);
+  for (auto *dq : {&ctx->queue, &ctx->requeue}) {
+    auto q = std::find(dq->begin(), dq->end(), T);
+    if (q == dq->end()) continue;
+    // not admitted (or given back for re-admission): finish it now; the
+    // requests behind it may fit now
+    dq->erase(q);
     finish_ticket(ctx, *T, SDD_E_CANCELLED, nullptr);
     T->P.reset();
+    ++ctx->epoch;
     ctx->done_cv.notify_all();
+    ctx->cv.notify_all();
+    break;
   }
   return SDD_OK;
 }
@@ -1976,6 +2158,14 @@ sdd_status sdd_solve_kappa(sdd_ctx_t ctx, const sdd_kappa_request *r, sdd_result
   ctx->stats.last_threads = threads;
   ctx->stats.launches += 1;
   scatter_rows(n, rows.data(), res);
+  {
+    double gn = 0.0;
+    for (size_t k = 0; k + 1 < (size_t)8 * r->g_samples; k += 2)
+      gn = std::max(gn, std::hypot(r->g_tables[k], r->g_tables[k + 1]));
+    const double rho = std::max(std::hypot(r->lambda_re[0], r->lambda_im[0]),
+                                std::hypot(r->lambda_re[1], r->lambda_im[1])) * r->dt;
+    fill_diag(res->diag, rho, gn, n, rows.data());
+  }
   release();
   return SDD_OK;
 }
@@ -1985,7 +2175,7 @@ sdd_status sdd_request_footprint(sdd_ctx_t ctx, const sdd_request *req, uint64_t
   std::unique_ptr<Prepared> P;
   sdd_status st = prepare(ctx, req, P);
   if (st != SDD_OK) return st;
-  *bytes = footprint(ctx, *P);
+  *bytes = footprint(ctx, *P, true);
   return SDD_OK;
 }
 
@@ -2011,6 +2201,10 @@ sdd_status sdd_get_stats(sdd_ctx_t ctx, sdd_stats *out) {
   if (!ctx || !out) return fail(SDD_E_INVALID, "NULL argument");
   ExecGuard ex(ctx);
   *out = ctx->stats;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  out->served_in_flight_max = ctx->served_in_flight_max;
+  out->served_waits = ctx->served_waits;
+  out->served_requeues = ctx->served_requeues;
   return SDD_OK;
 }
 
@@ -2130,11 +2324,16 @@ struct sdd_batch {
   hipEvent_t ev[2] = {nullptr, nullptr};   // around each replay, on the context's stream
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  uint64_t held = 0;                       // workspace counted as held for the batch's life
 };
 
 static void batch_free(sdd_batch *b) {
   if (!b) return;
   sdd_ctx *ctx = b->ctx;
+  if (b->held) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->held_long -= std::min(ctx->held_long, b->held);
+  }
   // teardown: nothing to do on failure
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
@@ -2272,6 +2471,20 @@ sdd_status sdd_batch_create(sdd_ctx_t ctx, uint32_t n, const sdd_request *reqs, 
   if (e == hipSuccess) e = e2;
   if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
   if (e != hipSuccess) return bail(fail(SDD_E_DEVICE, "graph capture: %s", hipGetErrorString(e)));
+  // the batch holds its workspace until destroyed: served admission counts
+  // it as unavailable
+  uint64_t held = Arena::round(std::max<size_t>(n, 1) * sizeof(unsigned long long)) +
+                  Arena::round(std::max<uint64_t>(b->total_nodes, 1) * sizeof(NodeOut)) +
+                  Arena::round(std::max<uint64_t>(b->total_nodes, 1) * sizeof(NodeJob));
+  for (auto &P : b->Ps) held += pass_bytes(*P);
+  for (auto &g : b->groups)
+    held += Arena::round(g.P.size() * sizeof(DevReq)) + Arena::round(g.P.size() * sizeof(uint32_t)) +
+            Arena::round((g.P.size() + 1) * sizeof(uint32_t));
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->held_long += held;
+  }
+  b->held = held;
   *out = b;
   for (uint32_t i = 0; i < n; ++i) b->Ps[i]->slot = done_index[i];
   return SDD_OK;

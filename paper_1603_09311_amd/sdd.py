@@ -22,6 +22,7 @@ SDD_FP64, SDD_FP32_MIXED = 0, 1
 SDD_FLAG_NO_SIGMA_GRID = 1
 SDD_FLAG_EXIT_NAIVE = 2
 SDD_MAX_REGIONS = 16
+SDD_DIAG_DT_UNRESOLVED = 1
 
 
 class SddError(RuntimeError):
@@ -69,11 +70,16 @@ PATH_RECORD_DTYPE = np.dtype([("w_re", "<f8"), ("w_im", "<f8"), ("tau", "<f8"), 
 assert PATH_RECORD_DTYPE.itemsize == C.sizeof(sdd_path_record) == 32
 
 
+class sdd_diag(C.Structure):
+    _fields_ = [("rho_dt", C.c_double), ("flags", C.c_uint32), ("reserved", C.c_uint32), ("g_norm", C.c_double),
+                ("se_over_gnorm", C.c_double)]
+
+
 class sdd_result(C.Structure):
     _fields_ = [("mean", C.POINTER(C.c_double)), ("var", C.POINTER(C.c_double)), ("se", C.POINTER(C.c_double)),
                 ("paths_done", C.POINTER(C.c_uint64)), ("steps", C.POINTER(C.c_uint64)),
                 ("unfinished", C.POINTER(C.c_uint64)), ("mean_exit_time", C.POINTER(C.c_double)),
-                ("path_records", C.c_void_p)]
+                ("path_records", C.c_void_p), ("diag", C.POINTER(sdd_diag))]
 
 
 class sdd_tuning(C.Structure):
@@ -88,7 +94,8 @@ class sdd_tune_trial(C.Structure):
 class sdd_stats(C.Structure):
     _fields_ = [("last_walk_ms", C.c_double), ("last_reduce_ms", C.c_double), ("last_walk_steps", C.c_uint64),
                 ("last_walk_paths", C.c_uint64), ("last_blocks", C.c_uint32), ("last_threads", C.c_uint32),
-                ("launches", C.c_uint64)]
+                ("launches", C.c_uint64), ("served_in_flight_max", C.c_uint32), ("served_waits", C.c_uint32),
+                ("served_requeues", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 # (name, restype, argtypes) of every entry point in include/sdd.h
@@ -226,11 +233,13 @@ class _Res:
         self.unfinished = np.zeros(max(n, 1), np.uint64)
         self.mean_exit_time = np.zeros(max(n, 1))
         self.records = np.zeros(records, PATH_RECORD_DTYPE) if records else None
+        self.diag = sdd_diag()
         self.n = n
         self.s = sdd_result(_ptr(self.mean, C.c_double), _ptr(self.var, C.c_double), _ptr(self.se, C.c_double),
                             _ptr(self.paths_done, C.c_uint64), _ptr(self.steps, C.c_uint64),
                             _ptr(self.unfinished, C.c_uint64), _ptr(self.mean_exit_time, C.c_double),
-                            self.records.ctypes.data if self.records is not None and records else None)
+                            self.records.ctypes.data if self.records is not None and records else None,
+                            C.pointer(self.diag))
 
     def as_dict(self) -> Dict[str, np.ndarray]:
         n = self.n
@@ -240,6 +249,8 @@ class _Res:
                  unfinished=self.unfinished[:n].copy(), mean_exit_time=self.mean_exit_time[:n].copy())
         if self.records is not None:
             d["records"] = self.records
+        d["diag"] = {"rho_dt": self.diag.rho_dt, "dt_unresolved": bool(self.diag.flags & SDD_DIAG_DT_UNRESOLVED),
+                     "g_norm": self.diag.g_norm, "se_over_gnorm": self.diag.se_over_gnorm}
         return d
 
 

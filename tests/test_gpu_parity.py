@@ -164,17 +164,29 @@ def test_block_and_triangle_fp64_parity(ctx, orc):
         assert_fp64_parity(g, o)
 
 
+def _sample_paths(p, per, seed=3):
+    """(node, path) pairs: three random paths at every 8th node."""
+    rng = np.random.default_rng(seed)
+    return [(int(j), int(k)) for j in range(0, p.n_nodes, 8) for k in rng.choice(per, 3, replace=False)]
+
+
 def test_quarter_space_full_size_sampled_paths(ctx, orc):
     """The timed workload at full size and in the timed launch form (512
     nodes x 65536 paths, FP32-mixed, one prepared batch replayed as a HIP
     graph): every path finished; 192 paths (3 at every 8th node) walked one
     by one by the FP64 oracle with their own node and path indices take the
-    same number of steps to the same wall and agree in value to FP32
-    accuracy (a region decision that FP32 rounding moves near the contact
-    changes a value by at most a few phase increments, alpha dt / 2 <= 4e-3);
-    the per-node reduction equals the mean of the records."""
+    same number of steps to the same wall (all but at most two: a proposal
+    that FP32 rounding moves across a wall or a bridge threshold) and agree in
+    value.  The FP32 walk counts full steps per region exactly and forms the
+    phase in FP64, so a path's value differs from the oracle's only by FP32
+    rounding of its positions (about 1e-5 of a skin depth at the exit,
+    times |dg/dt| <= |k E0| = 0.16 on the walls) unless FP32 rounding moves a
+    proposal across the contact or the surface: then one full step's phase
+    goes to the other region, |delta S| <= max alpha dt / 2 = 4e-3.  Bound:
+    max alpha dt / 2 |g|max + 1e-4.  The per-node reduction equals the mean
+    of the records."""
     p = W.quarter_space()
-    log(f"quarter space full size: {p.n_nodes} nodes x {int(p.path_count[0])} paths")
+    log(f"quarter space full size fp32: {p.n_nodes} nodes x {int(p.path_count[0])} paths")
     b = ctx.batch([p], records=True)
     try:
         r = b.run()[0]
@@ -184,21 +196,64 @@ def test_quarter_space_full_size_sampled_paths(ctx, orc):
     per = int(p.path_count[0])
     assert rec.shape[0] == p.n_nodes * per
     assert np.all(r["unfinished"] == 0) and np.all(rec["wall"] >= 0)
-    rng = np.random.default_rng(3)
     same, n, dev = 0, 0, []
-    for j in range(0, p.n_nodes, 8):
-        for k in rng.choice(per, 3, replace=False):
-            o = orc.walk_path(p, int(j), int(k))
-            g = rec[j * per + k]
-            n += 1
-            if g["steps"] == o["steps"] and g["wall"] == o["wall"]:
-                same += 1
-                dev.append(abs(complex(g["w_re"], g["w_im"]) - complex(o["w_re"], o["w_im"])))
+    for j, k in _sample_paths(p, per):
+        o = orc.walk_path(p, j, k)
+        g = rec[j * per + k]
+        n += 1
+        if g["steps"] == o["steps"] and g["wall"] == o["wall"]:
+            same += 1
+            dev.append(abs(complex(g["w_re"], g["w_im"]) - complex(o["w_re"], o["w_im"])))
     dev = np.array(dev)
-    assert same >= 0.95 * n, (same, n)
-    assert np.median(dev) <= 1e-6 and dev.max() <= 2e-2, (np.median(dev), dev.max())
+    bound = p.alphas().max() * p.dt / 2.0 * p.g_norm + 1e-4
+    log(f"fp32 sampled paths: {same}/{n} same steps and wall, value deviation median {np.median(dev):.2e} "
+        f"max {dev.max():.2e} (bound {bound:.2e})")
+    assert same >= n - 2, (same, n)
+    assert np.median(dev) <= 1e-6 and dev.max() <= bound, (np.median(dev), dev.max(), bound)
     m = (rec["w_re"] + 1j * rec["w_im"]).reshape(p.n_nodes, per).mean(axis=1)
     assert np.allclose(m, r["mean"], rtol=1e-12, atol=1e-15)
+    d = r["diag"]
+    assert d["rho_dt"] == pytest.approx(p.alphas().max() * p.dt / 2.0, rel=1e-12) and not d["dt_unresolved"]
+
+
+def test_quarter_space_fp64_full_size_and_fp32_per_node(ctx, orc):
+    """The timed workload at full size with the FP64 persistent walker (the
+    parity form, 512 nodes x 65536 paths, 1.9e12 steps, prepared batch
+    replayed as a HIP graph): 192 sampled paths walked one by one by the
+    oracle under their own indices take the same steps to the same wall with
+    weights equal to 1e-11.  Then the headline FP32-mixed result at full size
+    against this FP64 result, node by node: every component within 3 FP64
+    standard errors and the sum of squared z-scores inside the 99.9%
+    chi-square quantile (the two walks share their random numbers, so the
+    z-scores are far below 1)."""
+    p64 = W.quarter_space(precision=W.FP64)
+    per = int(p64.path_count[0])
+    log(f"quarter space full size fp64: {p64.n_nodes} nodes x {per} paths")
+    b = ctx.batch([p64], records=True)
+    try:
+        r64 = b.run()[0]
+    finally:
+        b.close()
+    rec = r64["records"]
+    assert np.all(r64["unfinished"] == 0) and np.all(rec["wall"] >= 0)
+    idx = _sample_paths(p64, per)
+    got = np.array([rec[j * per + k] for j, k in idx], dtype=rec.dtype)
+    want = np.zeros(len(idx), dtype=got.dtype)
+    for i, (j, k) in enumerate(idx):
+        o = orc.walk_path(p64, j, k)
+        want[i] = (o["w_re"], o["w_im"], o["tau"], o["steps"], o["wall"])
+    assert_records_match(got, want)
+    m = (rec["w_re"] + 1j * rec["w_im"]).reshape(p64.n_nodes, per).mean(axis=1)
+    assert np.allclose(m, r64["mean"], rtol=1e-12, atol=1e-15)
+    del rec, r64["records"]
+    log("quarter space full size fp32 for the per-node comparison")
+    r32 = ctx.solve(W.quarter_space())
+    d = r32["mean"] - r64["mean"]
+    z = np.concatenate([np.abs(d.real) / r64["se_re"], np.abs(d.imag) / r64["se_im"]])
+    log(f"fp32 vs fp64 at full size: max |z| {z.max():.4f}, sum z^2 {np.sum(z ** 2):.3f} over {z.size}")
+    assert z.max() <= 3.0
+    assert np.sum(z ** 2) <= stats.chi2.ppf(0.999, z.size)
+    assert np.array_equal(r32["paths_done"], r64["paths_done"])
 
 
 def test_block_four_frequencies_one_launch_fp32_within_3se(ctx, orc):
