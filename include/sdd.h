@@ -416,6 +416,31 @@ typedef struct {
  * passes 2^32, more than 2^40 paths), SDD_E_NOMEM (workspace), SDD_E_DEVICE. */
 sdd_status sdd_solve_kappa(sdd_ctx_t ctx, const sdd_kappa_request *req, sdd_result *res);
 
+/* For callers that cannot allocate device memory while they run (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): sdd_solve without the context's workspace.  Every device
+ * buffer the solve needs beyond the request's inputs and the results (the
+ * request descriptor, claim and done counters, boundary tables, nodes, sigma
+ * grid, tiles, one 32-byte record per path, reduction jobs and rows) is
+ * carved from a static device array of SDD_NOALLOC_SCRATCH_BYTES (64 MiB)
+ * that the library holds on each GPU it runs on until the process ends; the
+ * call makes no hipMalloc, hipFree or other allocating call.  The same
+ * kernels run in the same order as in sdd_solve, so the results are bitwise
+ * those of sdd_solve on the same request.
+ *   req   fixed-path request (target_rel_se == 0), host memory, validated
+ *         and copied as for sdd_solve;
+ *   res   as for sdd_solve (path_records allowed).
+ * Errors: SDD_E_INVALID as sdd_solve, and for target_rel_se > 0;
+ * SDD_E_NOMEM when the request needs more than the scratch holds (about 2
+ * million paths in all; the message gives the bytes needed); SDD_E_DEVICE.
+ * Every call on one GPU uses that GPU's one array, which keeps the last
+ * call's contents (counters are zeroed by a kernel at the start of each
+ * call): calls on one GPU, from any context or thread of the process, are
+ * serialised by a per-device lock held until the call's results are on the
+ * host; calls that overlapped on one GPU would race. */
+#define SDD_NOALLOC_SCRATCH_BYTES (64u << 20)
+sdd_status sdd_solve_noalloc(sdd_ctx_t ctx, const sdd_request *req, sdd_result *res);
+
 /* Bytes of workspace a request needs (tables, nodes, tiles, records; for a
  * target-SE request the pilot and the largest extension). */
 sdd_status sdd_request_footprint(sdd_ctx_t ctx, const sdd_request *req, uint64_t *bytes);

@@ -36,10 +36,51 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "sdd_device.h"
 #include "sdd_rng.h"
 
 namespace sdd {
+
+// ---------------------------------------------------------------------------
+// Static scratch of sdd_solve_noalloc: every device buffer such a solve needs
+// beyond its inputs and outputs (descriptor, counters, tables, nodes, sigma
+// grid, tiles, path records, reduction jobs and rows) is carved from this
+// one array, so that call allocates nothing.  Each GPU the library runs on
+// holds its own copy, at its own address, until the process ends.  Host code
+// never passes the array's name to a kernel or a copy: it uses the address
+// hipGetSymbolAddress returns on each device, taken once per device with that
+// device current (scratch_init, called by sdd_create).
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kMaxScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxScratchDevices] = {};
+static std::mutex g_scratch_use[kMaxScratchDevices];
+
+// The scratch address on `device`, which must be the current device.
+hipError_t scratch_init(int device, void **out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
+
+size_t scratch_bytes() { return kScratchBytes; }
+
+// Calls on one device share its scratch: each holds this lock until its
+// results are on the host.
+std::mutex &scratch_lock(int device) { return g_scratch_use[device]; }
 
 template <class R> struct ExitInfo {
   R f, t;     // fraction of the last step; tangential coordinate of the exit

@@ -40,6 +40,9 @@ int persist_blocks_per_cu(int precision, int sig, uint32_t threads);
 hipError_t launch_walk_kappa(int precision, const KReq *req_dev, uint32_t blocks, hipStream_t st);
 int kappa_blocks_per_cu(int precision);
 uint32_t kappa_threads();
+hipError_t scratch_init(int device, void **out);
+size_t scratch_bytes();
+std::mutex &scratch_lock(int device);
 }  // namespace sdd
 
 using namespace sdd;
@@ -236,6 +239,7 @@ struct sdd_ctx {
   // timing of the last walk / reduction launches (guarded by exec)
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   sdd_stats stats{};
+  char *scratch = nullptr;         // this device's static scratch (sdd_solve_noalloc)
   bool debug = false;              // SDD_DEBUG=1: per-slice trace of the served loop on stderr
 };
 
@@ -1614,6 +1618,11 @@ sdd_status sdd_create(int device, void *workspace_dev, size_t workspace_bytes, v
     return fail(SDD_E_DEVICE, "device %d is %s; this library is built for gfx950", device, prop.gcnArchName);
   auto ctx = std::make_unique<sdd_ctx>();
   for (auto &e : ctx->ev) HIP_TRY(hipEventCreate(&e));
+  {
+    void *sp = nullptr;
+    HIP_TRY(scratch_init(device, &sp));
+    ctx->scratch = reinterpret_cast<char *>(sp);
+  }
   ctx->device = device;
   ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
   ctx->cus = prop.multiProcessorCount;
@@ -2167,6 +2176,108 @@ sdd_status sdd_solve_kappa(sdd_ctx_t ctx, const sdd_kappa_request *r, sdd_result
     fill_diag(res->diag, rho, gn, n, rows.data());
   }
   release();
+  return SDD_OK;
+}
+
+// sdd_solve with every device buffer in the static scratch of this device
+// instead of the context's workspace; the same kernels in the same launch
+// sequence, so the results are bitwise those of sdd_solve.
+sdd_status sdd_solve_noalloc(sdd_ctx_t ctx, const sdd_request *req, sdd_result *res) {
+  if (!ctx || !req || !res) return fail(SDD_E_INVALID, "NULL argument");
+  if (req->target_rel_se > 0.0) return fail(SDD_E_INVALID, "sdd_solve_noalloc takes fixed path counts");
+  if (!res->mean && req->n_nodes) return fail(SDD_E_INVALID, "result mean is NULL");
+  std::unique_ptr<Prepared> P;
+  sdd_status st = prepare(ctx, req, P);
+  if (st != SDD_OK) return st;
+  if (!ctx->scratch) return fail(SDD_E_DEVICE, "no static scratch on device %d", ctx->device);
+  const uint32_t n = req->n_nodes;
+  build_tiles(*P, tile_size(ctx, *P), launch_waves_estimate(ctx));
+  // layout of the scratch, 256-byte aligned pieces
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    const size_t o = off;
+    off += Arena::round(b ? b : 1);
+    return o;
+  };
+  const size_t o_req = take(sizeof(DevReq)), o_ctr = take(sizeof(uint32_t)),
+               o_done = take(sizeof(unsigned long long)), o_ws = take(2 * sizeof(uint32_t)),
+               o_g = take(P->g.size() * sizeof(double)), o_nodes = take(P->nodes.size() * sizeof(double)),
+               o_grid = take(P->grid.size() * sizeof(SigmaCell)), o_tiles = take(P->tiles.size() * sizeof(DevTile)),
+               o_recs = take(P->n_paths * sizeof(PathRec)), o_jobs = take((size_t)n * sizeof(NodeJob)),
+               o_out = take((size_t)n * sizeof(NodeOut));
+  if (off > scratch_bytes())
+    return fail(SDD_E_NOMEM, "request needs %zu bytes of static scratch; sdd_solve_noalloc has %zu", off,
+                scratch_bytes());
+  if (n == 0) {
+    scatter(*P, nullptr, res);
+    return SDD_OK;
+  }
+  ExecGuard ex(ctx);
+  HIP_TRY(hipSetDevice(ctx->device));
+  std::lock_guard<std::mutex> use(scratch_lock(ctx->device));
+  char *base = ctx->scratch;
+  DevReq q = P->dreq;
+  q.g = reinterpret_cast<const double *>(base + o_g);
+  q.nodes = reinterpret_cast<const double *>(base + o_nodes);
+  q.tiles = reinterpret_cast<const DevTile *>(base + o_tiles);
+  q.recs = reinterpret_cast<PathRec *>(base + o_recs);
+  q.grid = P->grid.empty() ? nullptr : reinterpret_cast<const SigmaCell *>(base + o_grid);
+  q.n_tiles = (uint32_t)P->tiles.size();
+  q.tile_counter = reinterpret_cast<uint32_t *>(base + o_ctr);
+  q.done_counter = reinterpret_cast<unsigned long long *>(base + o_done);
+  uint32_t blocks, threads;
+  launch_shape(ctx, (int)q.precision, q.sig, blocks, threads);
+  const uint32_t ws[2] = {0u, blocks * (threads / 64)};
+  std::vector<NodeJob> jobs(n);
+  for (uint32_t j = 0; j < n; ++j) {
+    jobs[j] = NodeJob{};
+    jobs[j].recs0 = reinterpret_cast<const PathRec *>(base + o_recs) + P->rec_off[j];
+    jobs[j].count0 = P->pcnt[j];
+    jobs[j].out = reinterpret_cast<NodeOut *>(base + o_out) + j;
+  }
+  std::vector<NodeOut> rows(n);
+  unsigned long long done = 0;
+  hipStream_t s = ctx->stream;
+  hipError_t e = hipMemcpyAsync(base + o_g, P->g.data(), P->g.size() * sizeof(double), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(base + o_nodes, P->nodes.data(), P->nodes.size() * sizeof(double), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !P->grid.empty())
+    e = hipMemcpyAsync(base + o_grid, P->grid.data(), P->grid.size() * sizeof(SigmaCell), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !P->tiles.empty())
+    e = hipMemcpyAsync(base + o_tiles, P->tiles.data(), P->tiles.size() * sizeof(DevTile), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(base + o_req, &q, sizeof(DevReq), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(base + o_ws, ws, sizeof(ws), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(base + o_jobs, jobs.data(), n * sizeof(NodeJob), hipMemcpyHostToDevice, s);
+  // the counters keep the previous call's values: a fill kernel zeroes them
+  if (e == hipSuccess)
+    e = launch_reset(reinterpret_cast<uint32_t *>(base + o_ctr), reinterpret_cast<unsigned long long *>(base + o_done),
+                     1u, s);
+  if (e == hipSuccess) e = hipEventRecord(ctx->ev[0], s);
+  if (e == hipSuccess)
+    e = launch_walk_persist((int)q.precision, q.sig, reinterpret_cast<const DevReq *>(base + o_req), 1u,
+                            reinterpret_cast<const uint32_t *>(base + o_ws), 0u, refill_mask(ctx), blocks, threads, s);
+  if (e == hipSuccess) e = hipEventRecord(ctx->ev[1], s);
+  if (e == hipSuccess) e = launch_reduce(reinterpret_cast<const NodeJob *>(base + o_jobs), n, s);
+  if (e == hipSuccess) e = hipEventRecord(ctx->ev[2], s);
+  if (e == hipSuccess) e = hipMemcpyAsync(rows.data(), base + o_out, n * sizeof(NodeOut), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&done, base + o_done, sizeof(done), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && res->path_records && P->n_paths)
+    e = hipMemcpyAsync(res->path_records, base + o_recs, P->n_paths * sizeof(PathRec), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(SDD_E_DEVICE, "sdd_solve_noalloc: %s", hipGetErrorString(e));
+  if (done != P->n_paths)
+    return fail(SDD_E_DEVICE, "%llu of %llu paths completed", done, (unsigned long long)P->n_paths);
+  float ms = 0.f, rms = 0.f;
+  if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]) == hipSuccess) ctx->stats.last_walk_ms = ms;
+  if (hipEventElapsedTime(&rms, ctx->ev[1], ctx->ev[2]) == hipSuccess) ctx->stats.last_reduce_ms = rms;
+  uint64_t steps = 0;
+  for (const NodeOut &o : rows) steps += o.steps;
+  ctx->stats.last_walk_steps = steps;
+  ctx->stats.last_walk_paths = P->n_paths;
+  ctx->stats.last_blocks = blocks;
+  ctx->stats.last_threads = threads;
+  ctx->stats.launches += 1;
+  scatter(*P, rows.data(), res);
   return SDD_OK;
 }
 

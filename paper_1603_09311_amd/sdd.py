@@ -23,6 +23,7 @@ SDD_FLAG_NO_SIGMA_GRID = 1
 SDD_FLAG_EXIT_NAIVE = 2
 SDD_MAX_REGIONS = 16
 SDD_DIAG_DT_UNRESOLVED = 1
+SDD_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class SddError(RuntimeError):
@@ -107,6 +108,7 @@ _PROTOS = [
     ("sdd_solve", C.c_int, [C.c_void_p, C.POINTER(sdd_request), C.POINTER(sdd_result)]),
     ("sdd_solve_batch", C.c_int, [C.c_void_p, C.c_uint32, C.POINTER(sdd_request), C.POINTER(sdd_result)]),
     ("sdd_solve_plain", C.c_int, [C.c_void_p, C.POINTER(sdd_request), C.POINTER(sdd_result)]),
+    ("sdd_solve_noalloc", C.c_int, [C.c_void_p, C.POINTER(sdd_request), C.POINTER(sdd_result)]),
     ("sdd_mt_te_response", C.c_int, [C.c_uint32, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                      C.POINTER(C.c_double), C.c_double, C.c_double, C.c_double,
                                      C.POINTER(C.c_double), C.POINTER(C.c_double)]),
@@ -380,6 +382,15 @@ class Context:
         q = _Req(p, self.model(p), precision, target_rel_se, flags)
         r = _Res(q.n, q.total if records else 0)
         _check(lib().sdd_solve(self.h, C.byref(q.s), C.byref(r.s)))
+        return r.as_dict()
+
+    def solve_noalloc(self, p, precision: Optional[int] = None, records: bool = False, flags: int = 0):
+        """sdd_solve with every device buffer in the library's static scratch
+        (sdd_solve_noalloc): no allocation during the call, bitwise the result
+        of solve()."""
+        q = _Req(p, self.model(p), precision, 0.0, flags)
+        r = _Res(q.n, q.total if records else 0)
+        _check(lib().sdd_solve_noalloc(self.h, C.byref(q.s), C.byref(r.s)))
         return r.as_dict()
 
     def solve_multi_freq(self, p, freqs: Sequence[float], g_tables: Sequence[np.ndarray],

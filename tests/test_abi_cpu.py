@@ -65,10 +65,11 @@ def test_struct_layouts_match_header(tmp_path):
                    'printf("%zu %zu %zu %zu\\n", sizeof(sdd_kappa_request), offsetof(sdd_kappa_request, g_tables),'
                    ' offsetof(sdd_kappa_request, dt), offsetof(sdd_kappa_request, precision));\n'
                    'printf("%zu %zu %zu %zu\\n", sizeof(sdd_diag), offsetof(sdd_diag, flags), offsetof(sdd_diag, g_norm),'
-                   ' offsetof(sdd_result, diag));\nreturn 0;}\n')
+                   ' offsetof(sdd_result, diag));\n'
+                   'printf("%u\\n", (unsigned)SDD_NOALLOC_SCRATCH_BYTES);\nreturn 0;}\n')
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
-    a, b, c, d = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")[:4]
+    a, b, c, d, e = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")[:5]
     want = [C.sizeof(t) for t in (sdd.sdd_region, sdd.sdd_model_desc, sdd.sdd_request, sdd.sdd_result,
                                   sdd.sdd_path_record, sdd.sdd_tuning, sdd.sdd_tune_trial, sdd.sdd_stats)]
     assert [int(x) for x in a.split()] == want
@@ -79,6 +80,7 @@ def test_struct_layouts_match_header(tmp_path):
     assert [int(x) for x in c.split()] == [C.sizeof(K), K.g_tables.offset, K.dt.offset, K.precision.offset]
     D = sdd.sdd_diag
     assert [int(x) for x in d.split()] == [C.sizeof(D), D.flags.offset, D.g_norm.offset, sdd.sdd_result.diag.offset]
+    assert int(e) == sdd.SDD_NOALLOC_SCRATCH_BYTES
 
 
 def test_product_path_never_reaches_the_oracle():
