@@ -6,12 +6,22 @@ reduction) through the C ABI: table/node upload, persistent walker, per-node
 reduction, results back on the host.  Prints ONE JSON line.
 
 Legs besides the timed workload (each bounded, each can be switched off):
+  --fp64    the same workload at full size with the FP64 persistent walker
+            (the parity form), and the FP32-mixed headline against it node
+            by node (its error against FP64, all 512 nodes);
+  --target  the same workload solved to a standard error of 1e-3 |g|inf per
+            node (pilot and extension): measured interface nodes per second
+            and the paths each node needed;
   --plain   the plain FP64 one-launch-per-node form and the FP64 persistent
             walker on a node subset (the comparison form);
-  --served  a short Poisson stream of mixed requests through the served
-            mode, for p50/p99 latency, beside the same stream through
-            blocking solves in arrival order and, for its first requests
-            (a bounded wall time), through the plain FP64 form;
+  --served  the served stream: Poisson arrivals of unit-square,
+            quarter-space and block requests, each solved to 1e-3 |g|inf,
+            at 0.5 and 0.8 of the closed-loop saturation rate (200 requests
+            each), through continuous batching, through blocking solves in
+            arrival order, and (the first requests, a bounded wall time)
+            through the plain FP64 form;
+  --triangles-full  triangle requests 0-15 at their own path counts in one
+            graph-replayed persistent launch;
   --mt      pointwise TE apparent resistivity and phase at the COMMEMI 2D-1
             sites (Table 2 of the paper as context);
   --multifreq  the block model at four frequencies: four requests in one
@@ -97,15 +107,43 @@ def load_traffic(workload: str):
     return d.get("traffic_bytes_per_launch")
 
 
-def nodes_per_s_at(res, steps_per_s: float, rel_se: float, gnorm: float) -> float:
-    """Interface nodes per second at SE <= rel_se |g|inf: each node needs
-    N = (s / (rel_se |g|inf))^2 paths (s^2 = var_re + var_im) of its measured
-    mean length."""
-    s2 = res["var_re"] + res["var_im"]
-    n_need = np.maximum(s2 / (rel_se * gnorm) ** 2, 1.0)
-    steps_per_path = res["steps"] / np.maximum(res["paths_done"] + res["unfinished"], 1)
-    total_steps = float(np.sum(n_need * steps_per_path))
-    return res["mean"].size / (total_steps / steps_per_s)
+def diag_of(results):
+    """The time-step resolution of a set of results: the largest phase a
+    full step adds (rho = max alpha dt / 2) and how many results are flagged
+    as not resolving it (rho > 0.1)."""
+    rs = results if isinstance(results, (list, tuple)) else [results]
+    rho = [r["diag"]["rho_dt"] for r in rs]
+    return {"rho_dt_max": float(max(rho)) if rho else 0.0,
+            "dt_unresolved": int(sum(r["diag"]["dt_unresolved"] for r in rs)), "results": len(rs)}
+
+
+def se_stats(res):
+    """Standard errors of a result: the largest SE / |g|inf (the scale of
+    the 1e-3 target) and each node's SE / |E| (median and largest)."""
+    rel = res["se"] / np.maximum(np.abs(res["mean"]), 1e-300)
+    return {"se_over_gnorm_max": float(res["diag"]["se_over_gnorm"]),
+            "se_over_abs_e_median": float(np.median(rel)), "se_over_abs_e_max": float(rel.max())}
+
+
+def fp32_vs_fp64(r32, r64):
+    """The FP32-mixed result against the FP64 one on the same random numbers,
+    per node and component, in FP64 standard errors."""
+    from scipy import stats as S
+    d = r32["mean"] - r64["mean"]
+    z = np.concatenate([np.abs(d.real) / r64["se_re"], np.abs(d.imag) / r64["se_im"]])
+    return {"components": int(z.size), "max_abs_z": float(z.max()), "count_abs_z_over_3": int((z > 3).sum()),
+            "sum_z2": float(np.sum(z ** 2)), "chi2_999_bound": float(S.chi2.ppf(0.999, z.size)),
+            "max_abs_diff": float(np.abs(d).max())}
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(p, budget_s: float = 15.0):
@@ -125,8 +163,18 @@ def cpu_baseline(p, budget_s: float = 15.0):
     r, _ = O.solve(sample, threads=threads)
     dt = time.perf_counter() - t0
     steps = float(r["steps"].sum())
+    # the homogeneous unit-square workload in full (8 nodes x 4096 paths, dt = 1e-4)
+    from paper_1603_09311_amd import workloads as W
+    c1 = W.unit_square(paths=4096, precision=W.FP64)
+    t0 = time.perf_counter()
+    r1, _ = O.solve(c1, threads=threads)
+    dt1 = time.perf_counter() - t0
+    s1 = float(r1["steps"].sum())
     return {"value": steps / dt, "unit": "walk-steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(idx)} of {p.n_nodes} nodes x {paths} paths ({steps:.3e} steps, {dt:.1f} s), FP64"}
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "sample": f"{len(idx)} of {p.n_nodes} nodes x {paths} paths ({steps:.3e} steps, {dt:.1f} s), FP64",
+            "unit_square_full": {"walk_steps": s1, "wall_s": dt1, "walk_steps_per_s": s1 / dt1,
+                                 "walk_steps_per_s_per_core": s1 / dt1 / threads}}
 
 
 def cpu_baseline_kappa(kp, budget_s: float = 5.0):
@@ -181,6 +229,7 @@ def kappa_leg(ctx, n: int = 51, paths: int = 10000, dt: float = 1e-4, repeats: i
                      "solve_wall_s_from_host_buffers": float(np.median(walls)),
                      "launch": {"blocks": st["last_blocks"], "threads": st["last_threads"]},
                      "max_abs_error": float(err.max()), "median_error_over_se": float(np.median(err / r["se"])),
+                     "time_step": diag_of(r),
                      "error_at_0.6_0.6": [float(abs((r["mean"][i06] - exact[i06]).real)),
                                           float(abs((r["mean"][i06] - exact[i06]).imag))]}
     d = res["fp32"]["mean"] - res["fp64"]["mean"]
@@ -190,79 +239,214 @@ def kappa_leg(ctx, n: int = 51, paths: int = 10000, dt: float = 1e-4, repeats: i
     return out
 
 
-def served_leg(ctx, n_requests: int, rate_hz: float, paths: int, plain_budget_s: float = 12.0):
-    """A Poisson trace of mixed requests (unit square, quarter-space and block
-    node subsets) through the served mode (continuous batching in time
-    slices), and two baselines on the same arrivals: blocking solves in
-    arrival order (one persistent launch per request, FIFO), and the plain
-    FP64 form (one launch per node, one thread per path) in arrival order.
-    The plain form is some hundred times slower, so it runs the trace's
-    first requests until plain_budget_s of wall time is spent, and the served
-    and FIFO latencies of the same requests are reported beside it.
-    Latency = result available - arrival time."""
-    from paper_1603_09311_amd import workloads as W
-    trace = W.served_trace(n_requests, rate_hz, seed=1, paths_override=paths)
-    nodes = sum(p.n_nodes for _, p in trace)
-    work = 0
+def _lat_stats(lat, wall=None):
+    lat = np.asarray(lat, dtype=np.float64)
+    out = {"requests": int(lat.size), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+           "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
+           "max_ms": float(lat.max() * 1e3)}
+    if wall is not None:
+        out["wall_s"] = wall
+    return out
 
-    def stats_of(lat, wall=None):
-        lat = np.array(lat)
-        out = {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-               "mean_ms": float(lat.mean() * 1e3)}
-        if wall is not None:
-            out["wall_s"] = wall
-        return out
 
-    # served: submit each request at its arrival time and poll every ticket
-    # in flight meanwhile (latency = completion seen by the poll - arrival)
+def _progress(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _served_run(ctx, trace, target, deadline_s, tag=""):
+    """Submit each request at its arrival time (continuous batching) and poll
+    every ticket in flight; latency = completion seen by the poll - arrival.
+    Past deadline_s the requests still in flight are cancelled and the run is
+    reported as incomplete (None)."""
     t0 = time.perf_counter()
-    done_at = {}
-    left = {}
-    nxt = 0
+    done_at, res, left, nxt = {}, {}, {}, 0
+    last = t0
     while nxt < len(trace) or left:
         now = time.perf_counter() - t0
+        if now > deadline_s:
+            for tk in left.values():
+                ctx.cancel(tk)
+            _progress(f"served {tag}: deadline {deadline_s:.0f} s passed with {len(done_at)} of {len(trace)} done")
+            return None
         while nxt < len(trace) and trace[nxt][0] <= now:
-            left[nxt] = ctx.submit(trace[nxt][1])
+            left[nxt] = ctx.submit(trace[nxt][1], target_rel_se=target)
             nxt += 1
         for i, tk in list(left.items()):
             r = ctx.poll(tk)
             if r is not None:
                 done_at[i] = time.perf_counter() - t0 - trace[i][0]
-                work += int(r["steps"].sum())
+                res[i] = r
                 del left[i]
+        if time.perf_counter() - last > 10.0:
+            last = time.perf_counter()
+            _progress(f"served {tag}: {len(done_at)} of {len(trace)} done, {len(left)} in flight, "
+                      f"{time.perf_counter() - t0:.1f} s")
         time.sleep(0.0002)
-    served_wall = time.perf_counter() - t0
-    served_lat = [done_at[i] for i in range(len(trace))]
-    served = stats_of(served_lat, served_wall)
-    served["nodes_per_s"] = nodes / served_wall
+    wall = time.perf_counter() - t0
+    return [done_at[i] for i in range(len(trace))], [res[i] for i in range(len(trace))], wall
 
-    def fifo(solve, budget=None):
+
+def _fifo_run(ctx, trace, solve, budget=None, tag=""):
+    """Blocking solves in arrival order (one launch sequence per request);
+    stops starting requests once `budget` seconds have passed."""
+    t0 = time.perf_counter()
+    lat, res = [], []
+    last = t0
+    for t_arr, p in trace:
+        now = time.perf_counter() - t0
+        if budget is not None and now > budget:
+            break
+        if time.perf_counter() - last > 10.0:
+            last = time.perf_counter()
+            _progress(f"fifo {tag}: {len(lat)} of {len(trace)} done, {now:.1f} s")
+        if t_arr > now:
+            time.sleep(t_arr - now)
+        res.append(solve(p))
+        lat.append(time.perf_counter() - t0 - t_arr)
+    return lat, res, time.perf_counter() - t0
+
+
+def served_leg(ctx, n_requests: int = 200, warm: int = 40, target: float = 1e-3, node_range=(2, 8),
+               plain_budget_s: float = 10.0):
+    """The served stream: Poisson arrivals (seed 1) of requests drawn
+    uniformly from the unit-square (8 nodes), quarter-space and block (one of
+    0.1, 1, 10, 100 Hz) families, the latter two on seeded node subsets of
+    node_range nodes, each solved to a standard error of `target` |g|inf per
+    node (4096-path pilot, then the paths the pilot's variance asks for, at
+    most 2^20).  The closed-loop saturation rate is measured first: `warm`
+    requests of another trace (seed 2) submitted at once, requests per second
+    to the last completion.  Then `n_requests` requests at 0.5 and at 0.8 of
+    that rate through the served mode (continuous batching in time slices)
+    and through blocking solves in arrival order (FIFO, one launch sequence
+    per request); and, for the first requests of the 0.8 trace that fit in
+    plain_budget_s of wall time, the plain FP64 one-launch-per-node form with
+    the path counts the served run gave each node.  Latency = result
+    available - arrival."""
+    from paper_1603_09311_amd import workloads as W
+    base = W.served_trace(n_requests, 1.0, seed=1, node_range=node_range)
+    warm_trace = W.served_trace(warm, 1.0, seed=2, node_range=node_range)
+    t0 = time.perf_counter()
+    tks = [ctx.submit(p, target_rel_se=target) for _, p in warm_trace]
+    for i, tk in enumerate(tks):
+        ctx.wait(tk, timeout_s=120)
+        if i % 10 == 9:
+            _progress(f"saturation run: {i + 1} of {warm} done, {time.perf_counter() - t0:.1f} s")
+    sat_wall = time.perf_counter() - t0
+    sat = warm / sat_wall
+    _progress(f"closed-loop saturation {sat:.2f} requests/s ({warm} requests, {sat_wall:.1f} s)")
+    kinds = {}
+    for _, p in base:
+        k = p.name.split("#")[0]
+        kinds[k] = kinds.get(k, 0) + 1
+    out = {"requests": n_requests, "target_se_over_gnorm": target, "node_range_quarter_space_block": list(node_range),
+           "families": kinds, "nodes": int(sum(p.n_nodes for _, p in base)),
+           "saturation": {"requests": warm, "wall_s": sat_wall, "requests_per_s": sat}}
+    for frac in (0.5, 0.8):
+        rate = frac * sat
+        trace = [(t / rate, p) for t, p in base]
+        got = _served_run(ctx, trace, target, deadline_s=2.5 * n_requests / rate + 30.0, tag=f"{frac:g}")
+        if got is None:
+            out[f"rate_{frac:g}_of_saturation"] = {"rate_hz": rate, "incomplete": True}
+            continue
+        lat, res, wall = got
+        _progress(f"served at {frac:g} of saturation: {wall:.1f} s")
+        steps = float(sum(r["steps"].sum() for r in res))
+        served = _lat_stats(lat, wall)
+        served.update({"nodes_per_s": out["nodes"] / wall, "walk_steps": steps, "walk_steps_per_s": steps / wall,
+                       "paths_per_node_median": float(np.median(np.concatenate([r["paths_done"] for r in res]))),
+                       "se_over_gnorm_max": float(max(r["diag"]["se_over_gnorm"] for r in res)),
+                       "time_step": diag_of(res)})
+        flat, fres, fwall = _fifo_run(ctx, trace, lambda p: ctx.solve(p, target_rel_se=target),
+                                      budget=2.5 * n_requests / rate + 30.0, tag=f"{frac:g}")
+        _progress(f"fifo at {frac:g} of saturation: {fwall:.1f} s, {len(flat)} requests")
+        fifo = _lat_stats(flat, fwall)
+        fifo["nodes_per_s"] = out["nodes"] / fwall
+        fifo["results_equal_served"] = bool(all(np.array_equal(a["mean"], b["mean"]) and
+                                                np.array_equal(a["paths_done"], b["paths_done"])
+                                                for a, b in zip(res, fres)))
+        fifo["requests_completed"] = len(flat)
+        key = f"rate_{frac:g}_of_saturation"
+        out[key] = {"rate_hz": rate, "served": served, "fifo_blocking": fifo}
+        if frac == 0.8:
+            plain_trace = [(t, p.replace(path_count=r["paths_done"].astype(np.uint32)))
+                           for (t, p), r in zip(trace, res)]
+            plat, pres, pwall = _fifo_run(ctx, plain_trace, ctx.solve_plain, plain_budget_s, tag="plain")
+            _progress(f"plain FP64 form: {len(plat)} requests in {pwall:.1f} s")
+            k = len(plat)
+            psteps = float(sum(r["steps"].sum() for r in pres))
+            plain = _lat_stats(plat, pwall) if k else {"requests": 0}
+            plain.update({"nodes_per_s": sum(p.n_nodes for _, p in trace[:k]) / pwall,
+                          "walk_steps_per_s": psteps / pwall, "budget_s": plain_budget_s,
+                          "served_same_requests": _lat_stats(lat[:k]) if k else None,
+                          "fifo_blocking_same_requests": _lat_stats(flat[:k]) if k else None})
+            out[key]["plain_fp64_one_launch_per_node"] = plain
+    top = out.get("rate_0.8_of_saturation", {}).get("served")
+    out["p50_ms"] = top["p50_ms"] if top else None
+    out["p99_ms"] = top["p99_ms"] if top else None
+    return out
+
+
+def fp64_full_leg(ctx, paths: int, r32):
+    """The timed workload at full size with the FP64 persistent walker (one
+    prepared batch replayed once), and the FP32-mixed headline result against
+    it node by node."""
+    from paper_1603_09311_amd import workloads as W
+    p64 = W.quarter_space(paths=paths, precision=W.FP64)
+    b = ctx.batch([p64])
+    try:
         t0 = time.perf_counter()
-        lat, steps = [], 0
-        for t_arr, p in trace:
-            now = time.perf_counter() - t0
-            if budget is not None and now > budget:
-                break
-            if t_arr > now:
-                time.sleep(t_arr - now)
-            r = solve(p)
-            lat.append(time.perf_counter() - t0 - t_arr)
-            steps += int(r["steps"].sum())
-        return lat, steps, time.perf_counter() - t0
+        r64 = b.run()[0]
+        wall = time.perf_counter() - t0
+        k_ms = ctx.stats()["last_walk_ms"]
+    finally:
+        b.close()
+    steps = float(r64["steps"].sum())
+    return {"walk_steps": steps, "replay_ms": k_ms, "walk_steps_per_s": steps / (k_ms * 1e-3), "wall_s": wall,
+            "time_step": diag_of(r64), "se": se_stats(r64),
+            "fp32_headline_vs_fp64": fp32_vs_fp64(r32, r64) if r32 is not None else None}
 
-    fifo_lat, _, fifo_wall = fifo(ctx.solve)
-    blocking = stats_of(fifo_lat, fifo_wall)
-    blocking["nodes_per_s"] = nodes / fifo_wall
-    plain_lat, plain_steps, plain_wall = fifo(ctx.solve_plain, plain_budget_s)
-    k = len(plain_lat)
-    plain = stats_of(plain_lat, plain_wall)
-    plain.update({"requests": k, "nodes_per_s": sum(p.n_nodes for _, p in trace[:k]) / plain_wall,
-                  "walk_steps_per_s": plain_steps / plain_wall,
-                  "served_same_requests": stats_of(served_lat[:k]),
-                  "fifo_blocking_same_requests": stats_of(fifo_lat[:k])})
-    return {"requests": n_requests, "rate_hz": rate_hz, "paths_per_node": paths, "nodes": nodes, "walk_steps": work,
-            "p50_ms": served["p50_ms"], "p99_ms": served["p99_ms"], "served": served,
-            "fifo_blocking_baseline": blocking, "plain_fp64_fifo_baseline": plain}
+
+def target_se_leg(ctx, target: float = 1e-3):
+    """The timed workload (512 nodes, FP32-mixed) solved to a standard error
+    of `target` |g|inf per node: a 4096-path pilot, then the paths each node's
+    pilot variance asks for (at most 2^20); measured interface nodes per
+    second (wall time of the blocking solve, inputs from host buffers)."""
+    from paper_1603_09311_amd import workloads as W
+    import torch
+    p = W.quarter_space(precision=W.FP32_MIXED)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = ctx.solve(p, target_rel_se=target)
+    wall = time.perf_counter() - t0
+    steps = float(r["steps"].sum())
+    n = r["paths_done"]
+    return {"nodes": p.n_nodes, "target_se_over_gnorm": target, "wall_s": wall, "walk_steps": steps,
+            "walk_steps_per_s": steps / wall, "interface_nodes_per_s": p.n_nodes / wall,
+            "paths_per_node": {"min": int(n.min()), "median": float(np.median(n)), "max": int(n.max()),
+                               "at_cap_2^20": int((n >= (1 << 20)).sum())},
+            "se": se_stats(r), "time_step": diag_of(r)}
+
+
+def triangles_full_leg(ctx, n_requests: int = 16):
+    """Triangle requests 0..n-1 at their own path counts (log-uniform 4096 to
+    262144 per node), FP32-mixed, in one persistent launch prepared as a
+    batch and replayed once as a HIP graph."""
+    from paper_1603_09311_amd import workloads as W
+    ps = [W.triangle_request(m, M=4096) for m in range(n_requests)]
+    b = ctx.batch(ps)
+    try:
+        t0 = time.perf_counter()
+        rs = b.run()
+        wall = time.perf_counter() - t0
+        k_ms = ctx.stats()["last_walk_ms"]
+    finally:
+        b.close()
+    steps = float(sum(r["steps"].sum() for r in rs))
+    nodes = sum(p.n_nodes for p in ps)
+    return {"requests": n_requests, "nodes": nodes, "paths": sum(p.total_paths for p in ps), "walk_steps": steps,
+            "replay_ms": k_ms, "walk_steps_per_s": steps / (k_ms * 1e-3), "interface_nodes_per_s": nodes / wall,
+            "frequencies_hz": sorted({p.freq_hz for p in ps}), "time_step": diag_of(rs),
+            "se_over_gnorm_max": float(max(r["diag"]["se_over_gnorm"] for r in rs))}
 
 
 def multifreq_leg(ctx, paths: int = 32768):
@@ -297,7 +481,7 @@ def multifreq_leg(ctx, paths: int = 32768):
             "one_walk_fanout": {"walk_steps": steps_f, "walk_kernel_ms": k_f,
                                 "walk_steps_per_s": steps_f / (k_f * 1e-3), "wall_s": wall_f,
                                 "node_frequency_estimates_per_s": est / wall_f},
-            "fanout_vs_batch_max_abs_z": z,
+            "fanout_vs_batch_max_abs_z": z, "time_step": diag_of(rb),
             "max_rel_se": float(max(np.max(r["se"]) for r in rb) / ps[0].g_norm)}
 
 
@@ -347,7 +531,7 @@ def triangle_leg(ctx, n_requests: int = 64, paths_scale: float = 1.0 / 64.0):
             "graph_batch_autotuned": {"wall_s": wall_tun, "walk_kernel_ms": k_tun,
                                       "walk_steps_per_s": steps / wall_tun, "tuning": chosen,
                                       "trials": len(trials), "tuned_on": big.name},
-            "results_identical": bool(same)}
+            "results_identical": bool(same), "time_step": diag_of(one)}
 
 
 # Table 2 of Sec. 4.3 (TE apparent resistivity, ohm m, COMMEMI 2D-1 at 10 Hz):
@@ -364,11 +548,12 @@ def mt_leg(ctx, seeds: int = 4, paths: int = 1 << 20, h: float = 0.05, dt: float
     independent seeds."""
     from paper_1603_09311_amd import sdd as S
     from paper_1603_09311_amd import workloads as W
-    rhos, phis, steps = [], [], 0.0
+    rhos, phis, steps, allr = [], [], 0.0, []
     t0 = time.perf_counter()
     for seed in range(seeds):
         ps = W.commemi_te_points(paths=paths, seed=seed, dt=dt, h=h)
         r = ctx.solve_batch(ps)
+        allr += r
         rho, phi = S.mt_te_response(*[x["mean"] for x in r], h, 1000.0, 10.0)
         rhos.append(rho)
         phis.append(phi)
@@ -380,7 +565,7 @@ def mt_leg(ctx, seeds: int = 4, paths: int = 1 << 20, h: float = 0.05, dt: float
             "rho_a_te": rhos.mean(0).round(3).tolist(), "rho_a_te_sd": rhos.std(0, ddof=1).round(3).tolist(),
             "phase_te_deg": phis.mean(0).round(3).tolist(), "phase_te_sd": phis.std(0, ddof=1).round(3).tolist(),
             "table2_commemi": TABLE2_TE_COMMEMI, "table2_stochastic": TABLE2_TE_STOCHASTIC,
-            "walk_steps": steps, "wall_s": wall, "walk_steps_per_s": steps / wall}
+            "walk_steps": steps, "wall_s": wall, "walk_steps_per_s": steps / wall, "time_step": diag_of(allr)}
 
 
 def sdd_leg(ctx, paths: int = 16384):
@@ -419,7 +604,7 @@ def sdd_leg(ctx, paths: int = 16384):
     idx = [int(np.argmin(abs(y - s))) for s in sites]
     return {"grid": [int(y.size), int(z.size)], "interface_nodes": int(len(ij)), "paths_per_node": paths,
             "walk_steps": float(r["steps"].sum()), "walk_s": t1 - t0, "rbffd_s": t2 - t1,
-            "max_interface_se": float(r["se"].max()),
+            "max_interface_se": float(r["se"].max()), "time_step": diag_of(r),
             "surface_sites_skin_depths": [float(y[i]) for i in idx],
             "rho_a_te": [round(float(rho[i]), 3) for i in idx], "phase_te_deg": [round(float(phi[i]), 3) for i in idx],
             "half_space_limits": {"left_rho_a": 100.0, "right_rho_a": 10.0, "phase_deg": 45.0}}
@@ -433,15 +618,18 @@ def main():
     ap.add_argument("--paths", type=int, default=65536, help="paths per node of the timed workload")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the full-size FP64 leg")
+    ap.add_argument("--no-target", action="store_true", help="skip the 1e-3 target-SE leg")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-triangles-full", action="store_true", help="skip triangle requests 0-15 at full size")
     ap.add_argument("--no-mt", action="store_true", help="skip the pointwise MT response leg")
     ap.add_argument("--no-sdd", action="store_true", help="skip the domain decomposition leg")
     ap.add_argument("--no-kappa", action="store_true", help="skip the discontinuous-kappa leg")
     ap.add_argument("--no-multifreq", action="store_true", help="skip the multi-frequency leg")
     ap.add_argument("--no-triangles", action="store_true", help="skip the uneven triangle batch leg")
-    ap.add_argument("--served-requests", type=int, default=24)
-    ap.add_argument("--served-rate", type=float, default=8.0)
+    ap.add_argument("--served-requests", type=int, default=200)
+    ap.add_argument("--served-warm", type=int, default=40)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the walk would shard by node and "
@@ -490,8 +678,6 @@ def main():
     value = steps_per_solve / (elapsed / args.steps)
     walk_ms = float(np.mean(kms))
     achieved = OPS_PER_STEP * steps_per_solve / (walk_ms * 1e-3)
-    gnorm = p.g_norm
-    nodes_s = nodes_per_s_at(res, value, 1e-3, gnorm)
     out = {
         "metric": METRIC, "value": value, "unit": "walk-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
@@ -500,9 +686,9 @@ def main():
                    "dt": p.dt, "domain": [p.y_lo, p.y_hi, p.z_lo, p.z_hi], "freq_hz": p.freq_hz,
                    "precision": "fp32_mixed_walk_fp64_reduce" if prec == W.FP32_MIXED else "fp64",
                    "walk_steps_per_solve": steps_per_solve},
-        "interface_nodes_per_s_at_1e-3": nodes_s,
         "interface_nodes_per_s_as_run": p.n_nodes / (elapsed / args.steps),
-        "max_rel_se_as_run": float(np.max(res["se"]) / gnorm),
+        "se_as_run": se_stats(res),
+        "time_step": diag_of(res),
         "walk_kernel_ms": walk_ms,
         "walk_steps_per_s_from_host_buffers": pcie_rate,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
@@ -515,6 +701,15 @@ def main():
     if out["roofline"]["traffic"] is not None:
         out["hbm_gb_per_s"] = out["roofline"]["traffic"] / (walk_ms * 1e-3) / 1e9
 
+    if not args.no_fp64 and prec == W.FP32_MIXED:
+        out["fp64_full_size"] = fp64_full_leg(ctx, args.paths, res)
+        log(f"fp64 full size: {out['fp64_full_size']}")
+
+    if not args.no_target:
+        out["target_se_1e-3"] = target_se_leg(ctx)
+        out["interface_nodes_per_s_at_se_1e-3_gnorm"] = out["target_se_1e-3"]["interface_nodes_per_s"]
+        log(f"target SE 1e-3: {out['target_se_1e-3']}")
+
     if not args.no_plain:
         sub = W.quarter_space(paths=args.paths, precision=W.FP64).subset(np.arange(0, 512, 64))
         r = ctx.solve_plain(sub)
@@ -525,25 +720,25 @@ def main():
         sub32 = sub.replace(precision=W.FP32_MIXED)
         r32 = ctx.solve(sub32)
         t_p32 = ctx.stats()["last_walk_ms"]
-        d32 = r32["mean"] - r64["mean"]
-        fp32_z = float(max(np.max(np.abs(d32.real) / r64["se_re"]), np.max(np.abs(d32.imag) / r64["se_im"])))
         out["comparison"] = {
             "subset": f"{sub.n_nodes} nodes x {args.paths} paths",
             "plain_fp64_walk_steps_per_s": s_plain / (t_plain * 1e-3),
             "persistent_fp64_walk_steps_per_s": s_plain / (t_p64 * 1e-3),
             "persistent_fp32_walk_steps_per_s": s_plain / (t_p32 * 1e-3),
             "fp64_persistent_equals_plain": bool(np.array_equal(r["mean"], r64["mean"])),
-            # the FP32-mixed walk against the FP64 walk on the same streams, per node and
-            # component, in units of the FP64 standard error
-            "fp32_vs_fp64_max_abs_z": fp32_z,
+            "fp32_vs_fp64": fp32_vs_fp64(r32, r64),
         }
         log(f"comparison: {out['comparison']}")
 
     if not args.no_served:
-        out["served"] = served_leg(ctx, args.served_requests, args.served_rate, 4096)
+        out["served"] = served_leg(ctx, args.served_requests, args.served_warm)
         log(f"served: {out['served']}")
         out["p50_ms"] = out["served"]["p50_ms"]
         out["p99_ms"] = out["served"]["p99_ms"]
+
+    if not args.no_triangles_full:
+        out["triangle_batch_full_size"] = triangles_full_leg(ctx)
+        log(f"triangles at full size: {out['triangle_batch_full_size']}")
 
     if not args.no_multifreq:
         out["multi_frequency"] = multifreq_leg(ctx)
