@@ -24,6 +24,9 @@ Legs besides the timed workload (each bounded, each can be switched off):
             graph-replayed persistent launch;
   --mt      pointwise TE apparent resistivity and phase at the COMMEMI 2D-1
             sites (Table 2 of the paper as context);
+  --generic the walker's generic signature (a seeded multi-body model) with
+            the sigma grid in LDS, in global memory and the primitive loop,
+            against the specialised walker, time per step;
   --multifreq  the block model at four frequencies: four requests in one
             launch against one walk weighted for all four;
   --triangles  the triangle family as one uneven batch: a launch per
@@ -449,6 +452,46 @@ def triangles_full_leg(ctx, n_requests: int = 16):
             "se_over_gnorm_max": float(max(r["diag"]["se_over_gnorm"] for r in rs))}
 
 
+def generic_leg(ctx, paths: int = 16384, repeats: int = 3):
+    """The walker's generic signature on a seeded multi-body model (air, four
+    boxes and two triangles), 128 surface nodes x `paths`, FP32-mixed, with
+    the region lookup from the sigma grid staged in LDS (the default), from
+    the grid in global memory and from the loop over the primitives; beside
+    it the specialised walker (air + one box) on the block model's same 128
+    surface nodes.  Time per walk-step of each (walk kernel, HIP events,
+    median of `repeats`), and whether the three lookups give the same
+    results bit for bit."""
+    from paper_1603_09311_amd import sdd as S
+    from paper_1603_09311_amd import workloads as W
+    gen = W.multi_body(seed=0, paths=paths)
+    blk = W.block_in_half_space(1.0, paths=paths, precision=W.FP32_MIXED).subset(np.arange(512, 1024, 4))
+    out = {"model": gen.name, "primitives": len(gen.regions), "nodes": gen.n_nodes, "paths_per_node": paths}
+    res = {}
+    for name, p, flags in (("specialised_air_box", blk, 0), ("generic_lds_grid", gen, 0),
+                           ("generic_global_grid", gen, S.SDD_FLAG_NO_LDS_GRID),
+                           ("generic_primitive_loop", gen, S.SDD_FLAG_NO_SIGMA_GRID)):
+        kms = []
+        for _ in range(repeats):
+            r = ctx.solve(p, flags=flags)
+            kms.append(ctx.stats()["last_walk_ms"])
+        st = ctx.stats()
+        steps = float(r["steps"].sum())
+        k = float(np.median(kms))
+        res[name] = r
+        out[name] = {"walk_kernel_ms": k, "walk_steps": steps, "ns_per_walk_step": k * 1e6 / steps,
+                     "walk_steps_per_s": steps / (k * 1e-3), "launch": {"blocks": st["last_blocks"],
+                                                                        "threads": st["last_threads"]}}
+    base = out["specialised_air_box"]["ns_per_walk_step"]
+    for name in ("generic_lds_grid", "generic_global_grid", "generic_primitive_loop"):
+        out[name]["time_per_step_vs_specialised"] = out[name]["ns_per_walk_step"] / base
+    a = res["generic_lds_grid"]
+    out["lookups_bitwise_equal"] = bool(all(np.array_equal(a[k], res[n][k]) for n in ("generic_global_grid",
+                                                                                    "generic_primitive_loop")
+                                            for k in ("mean", "var_re", "var_im", "steps")))
+    out["time_step"] = diag_of(a)
+    return out
+
+
 def multifreq_leg(ctx, paths: int = 32768):
     """The block-in-half-space model at 0.1, 1, 10 and 100 Hz (FP32-mixed,
     1024 nodes on the block edges and the surface, `paths` per node): the
@@ -627,6 +670,7 @@ def main():
     ap.add_argument("--no-sdd", action="store_true", help="skip the domain decomposition leg")
     ap.add_argument("--no-kappa", action="store_true", help="skip the discontinuous-kappa leg")
     ap.add_argument("--no-multifreq", action="store_true", help="skip the multi-frequency leg")
+    ap.add_argument("--no-generic", action="store_true", help="skip the generic-signature leg")
     ap.add_argument("--no-triangles", action="store_true", help="skip the uneven triangle batch leg")
     ap.add_argument("--served-requests", type=int, default=200)
     ap.add_argument("--served-warm", type=int, default=40)
@@ -739,6 +783,10 @@ def main():
     if not args.no_triangles_full:
         out["triangle_batch_full_size"] = triangles_full_leg(ctx)
         log(f"triangles at full size: {out['triangle_batch_full_size']}")
+
+    if not args.no_generic:
+        out["generic_signature"] = generic_leg(ctx)
+        log(f"generic signature: {out['generic_signature']}")
 
     if not args.no_multifreq:
         out["multi_frequency"] = multifreq_leg(ctx)

@@ -55,9 +55,11 @@ typedef enum {
  * identical decisions to an FP64 reference on the same streams).
  * SDD_FP32_MIXED: positions, normals, exit test and region lookup in FP32,
  * the phase integral as exact per-region step counts formed in FP64 (models
- * of air plus at most one half-space, box or triangle) or in compensated
- * FP32 (hi + lo; other models), the per-path weight and the per-node
- * reduction in FP64.  Both precisions draw the same random numbers. */
+ * of air plus at most one half-space, box or triangle) or as an exact 64-bit
+ * fixed-point sum of each region's phase per step (other models; each
+ * region's phase rounded once to 2^-31 of the largest), the per-path weight
+ * and the per-node reduction in FP64.  Both precisions draw the same random
+ * numbers. */
 typedef enum { SDD_FP64 = 0, SDD_FP32_MIXED = 1 } sdd_precision;
 
 /* Conductivity primitives (Sec. 2.2: piecewise-constant sub-domains).
@@ -116,7 +118,7 @@ typedef struct {
     uint64_t seed;
     uint32_t stream;            /* < 2^31 */
     uint32_t max_steps;         /* proposals per path before it counts as unfinished; 0 = 2e9 */
-    uint32_t flags;             /* 0, or SDD_FLAG_NO_SIGMA_GRID | SDD_FLAG_EXIT_NAIVE */
+    uint32_t flags;             /* 0, or SDD_FLAG_NO_SIGMA_GRID | SDD_FLAG_EXIT_NAIVE | SDD_FLAG_NO_LDS_GRID */
     uint32_t reserved;          /* 0 */
     double target_rel_se;       /* 0: fixed paths.  > 0: a 4096-path pilot per node, then
                                    extended on the same streams to N = ceil((s/(target*|g|inf))^2)
@@ -130,9 +132,14 @@ typedef struct {
  * one half-space, box or triangle) looks regions up by the loop over its
  * primitives instead of the sigma grid: a grid of 256 cells along the longer
  * side, each holding its region or the one boundary inequality that crosses
- * it (cells crossed by more than one use the loop).  Both give the same
- * region for every point, hence the same results; the grid is faster. */
-enum { SDD_FLAG_NO_SIGMA_GRID = 1, SDD_FLAG_EXIT_NAIVE = 2 };
+ * it (cells crossed by more than one use the loop).  When every request of a
+ * launch shares one grid (the same model, time step and frequency) and the
+ * grid has at most 255 distinct cells, each block of the walker stages it in
+ * LDS (a byte per cell and a table of the distinct cells); otherwise the
+ * walker reads it from global memory.  SDD_FLAG_NO_LDS_GRID keeps a request's
+ * grid in global memory.  All three give the same region for every point,
+ * hence the same results; LDS is the fastest, the loop the slowest. */
+enum { SDD_FLAG_NO_SIGMA_GRID = 1, SDD_FLAG_EXIT_NAIVE = 2, SDD_FLAG_NO_LDS_GRID = 4 };
 
 /* SDD_FLAG_EXIT_NAIVE: an ablation of the exit rule of Sec. 3.1.  A path
  * leaves the domain only when a proposal lands outside it (the crossing case

@@ -16,8 +16,12 @@ constexpr uint32_t kNoRequest = 0xFFFFFFFFu;
 enum PrimKind : int32_t { kHalfZ = 0, kHalfY = 1, kBox = 2, kTriangle = 3 };
 
 // Model signatures with a specialised, branch-free region lookup; any other
-// model uses the generic loop over its primitives.
-enum ModelSig : int32_t { kSigNone = 0, kSigZ = 1, kSigZY = 2, kSigZBox = 3, kSigZTri = 4, kSigGeneric = 5 };
+// model uses the generic lookup: the sigma grid (in global memory, or staged
+// in LDS when every request of a launch shares one grid: kSigGenericLds) or
+// the loop over its primitives.
+enum ModelSig : int32_t {
+  kSigNone = 0, kSigZ = 1, kSigZY = 2, kSigZBox = 3, kSigZTri = 4, kSigGeneric = 5, kSigGenericLds = 6
+};
 
 // Resident conductivity model (workspace copy made by sdd_model_create).
 struct DevModel {
@@ -91,19 +95,29 @@ struct FanJob {
 };
 
 // One cell of the sigma grid of the FP32 walk's generic signature (32 B):
-// the region of a point of the cell is rate_in if the point passes the cell's
-// test, else rate_out.  The test is the edge function
+// the phase increment of a full step ending at a point (a, b) of the cell
+// (fixed point: units of 2^-phase_shift) is inc_ge if the edge function
 //   e = dy (b - v1) - dz (a - v0)
-// in FP32, the same expression the primitive loop evaluates, compared with 0
-// by `mode` (0: e < 0, 1: e >= 0, 2: e <= 0).  A pure cell has a zero line
-// and mode 1 (e is +-0, so the test passes) and rate_in = rate_out.  A cell
-// with flags & kCellLoop set is crossed by more than one boundary: its points
-// take the primitive loop.
-constexpr uint32_t kCellLoop = 1u;
+// is >= 0, else inc_lt.  e is evaluated in FP32 in the primitive loop's own
+// expression, or negated (dy, dz negated: the FP32 result is exactly -e), so
+// that each of the loop's tests (e < 0, e >= 0, e <= 0) reads "e >= 0" with
+// the two increments in the right order.  A pure cell has a zero line (e is
+// +-0) and equal increments.  A cell whose primitives test two lines has bit
+// 30 of inc_ge set (kCellTwo; increments are below 2^30): its increment is
+// inc_ge or inc_lt when e2 < 0 and the extension entry's inc_ge (e >= 0) or
+// inc_lt (e < 0) when e2 >= 0, e2 the extension entry's line; pad[0] is the
+// extension's index.  A cell with more lines has bit 31 set (kCellLoop): its
+// points take the primitive loop.  The LDS form of a grid stores each
+// distinct cell once (a class table of at most 255 SigmaCells, then the
+// extension entries) and one class byte per cell.
+constexpr uint32_t kCellLoop = 0x80000000u;
+constexpr uint32_t kCellTwo = 0x40000000u;
+constexpr uint32_t kCellFlags = kCellLoop | kCellTwo;
+constexpr uint32_t kMaxLdsClasses = 255;
 struct SigmaCell {
-  uint32_t flags, mode;
-  float rate_in, rate_out;
+  uint32_t inc_ge, inc_lt;
   float v0, v1, dy, dz;
+  uint32_t pad[2];
 };
 
 // Per-request device descriptor.
@@ -124,7 +138,11 @@ struct DevReq {
   float fthr;          // 12.05 > 24 / 2, compared with 2 d0 d1 (FP32 uniforms are >= 2^-24)
   float fscr;          // fthr / 2, compared with d0 d1' in the per-step screen
   float fscr_root;     // least float r with fl(r r) > fscr: distances all > r pass both screens of a pair
-  float fc[kMaxRegions + 3];
+  // generic signature: the phase of a full step in region r as the integer
+  // cfx[r] = round(c[r] 2^phase_shift) (the largest in [2^29, 2^30]), summed
+  // exactly in 64 bits along a path
+  uint32_t cfx[kMaxRegions + 3];
+  int32_t phase_shift;
   // model signature (which specialised region lookup the walkers use) and its
   // FP32 parameters in centred coordinates (units of K):
   //   kSigZ:    [z0]                      air above z0
@@ -160,8 +178,14 @@ struct DevReq {
   // sigma grid of the FP32 generic signature (null: the primitive loop); cell
   // (i, j) = (trunc(a gsy + goy), trunc(b gsz + goz)) clamped, at grid[j gy + i]
   const SigmaCell *grid;
+  const SigmaCell *grid_ext;   // extension entries of the two-line cells
   uint32_t gy, gz;
   float gsy, goy, gsz, goz;
+  float gmy, gmz;       // gy - 1, gz - 1: the cell index clamped in FP32
+  // the grid's LDS form (kSigGenericLds): lds_classes SigmaCells, then gy gz
+  // class bytes, lds_bytes in all (a multiple of 16)
+  const uint8_t *lds_src;
+  uint32_t lds_bytes, lds_classes;
   const double *nodes;  // n x (y, z)
   const double *g;      // 4 x (M + 1) x (re, im)
   const DevTile *tiles;

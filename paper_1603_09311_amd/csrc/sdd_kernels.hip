@@ -92,10 +92,11 @@ template <class R> struct ExitInfo {
 // Primitives in list order, the first match wins, else the background.
 // ---------------------------------------------------------------------------
 
-// Generic: loop over the primitives (kinds and parameters wave-uniform).
-template <class R, int STRIDE>
-__device__ __forceinline__ R region_c_generic(int np, const int32_t *kind, const R *prm, const R *cv, R y, R z) {
-  R c = cv[np];
+// Generic: loop over the primitives (kinds and parameters wave-uniform);
+// cv[k] is the value of region k (an FP64 rate, or a fixed-point increment).
+template <class R, int STRIDE, class V>
+__device__ __forceinline__ V region_c_generic(int np, const int32_t *kind, const R *prm, const V *cv, R y, R z) {
+  V c = cv[np];
   for (int k = np - 1; k >= 0; --k) {
     const int kd = kind[k];
     const R *v = prm + k * STRIDE;
@@ -191,27 +192,39 @@ __device__ __forceinline__ int region_index_generic(int np, const int32_t *kind,
   return idx;
 }
 
+// The LDS form of the sigma grid (kSigGenericLds): the class table (SigmaCells)
+// followed by one class byte per cell, staged by each block at the start of
+// the launch.
+extern __shared__ __attribute__((aligned(16))) uint8_t g_lds[];
+
 // FP32 region tests in centred coordinates; the triangle as three linear
 // forms.  The specialised signatures have at most three regions: primitive 0
 // (air above z0), primitive 1 (half-plane, box or triangle) and the
 // background.  Their walkers count full steps per region instead of summing
 // phase increments: the phase of n full steps is then exactly
 // c0 n0 + c1 n1 + cb (n - n0 - n1), formed in FP64 when the path exits.  The
-// generic signature sums FP32 increments (compensated).
+// generic signature adds each step's fixed-point increment (the region's
+// phase in units of 2^-phase_shift, an integer below 2^31) to a 64-bit sum,
+// which is exact: only the one rounding of each region's phase to an integer
+// remains, below 2^-32 of the largest per step.
 template <int SIG> struct Reg32 {
-  static constexpr bool kCounted = SIG != kSigGeneric;
+  static constexpr bool kGeneric = SIG == kSigGeneric || SIG == kSigGenericLds;
+  static constexpr bool kCounted = !kGeneric;
   float p[10];
   // generic signature: the sigma grid
-  const SigmaCell *grid;
-  uint32_t gy, gz;
-  float gsy, goy, gsz, goz;
+  const SigmaCell *grid, *grid_ext;
+  uint32_t gy, lds_classes;
+  float gsy, goy, gsz, goz, gmy, gmz;
   __device__ __forceinline__ void load(const DevReq &Q) {
-    if constexpr (SIG == kSigGeneric) {
+    if constexpr (kGeneric) {
       grid = Q.grid;
-      gy = Q.gy; gz = Q.gz;
+      grid_ext = Q.grid_ext;
+      gy = Q.gy;
       gsy = Q.gsy; goy = Q.goy; gsz = Q.gsz; goz = Q.goz;
+      gmy = Q.gmy; gmz = Q.gmz;
+      lds_classes = Q.lds_classes;
     }
-    if constexpr (SIG != kSigNone && SIG != kSigGeneric) p[0] = unif(Q.sigp[0]);
+    if constexpr (SIG != kSigNone && !kGeneric) p[0] = unif(Q.sigp[0]);
     if constexpr (SIG == kSigZY || SIG == kSigZBox || SIG == kSigZTri) {
 #pragma unroll
       for (int i = 1; i < 10; ++i) p[i] = unif(Q.sigp[i]);
@@ -239,7 +252,7 @@ template <int SIG> struct Reg32 {
   __device__ __forceinline__ int index(const DevReq &Q, float a, float b) const {
     if constexpr (SIG == kSigNone) {
       return 2;
-    } else if constexpr (SIG == kSigGeneric) {
+    } else if constexpr (kGeneric) {
       return region_index_generic<float, 8>((int)Q.nprims, Q.kind, &Q.pf[0][0], a, b);
     } else {
       if (b < unif(p[0])) return 0;
@@ -252,7 +265,7 @@ template <int SIG> struct Reg32 {
   // The counts are g = steps outside primitive 0 (below the air) and
   // m = those of them inside primitive 1.
   __device__ __forceinline__ void count(float a, float b, uint32_t &g, uint32_t &m) const {
-    if constexpr (SIG != kSigNone && SIG != kSigGeneric) {
+    if constexpr (SIG != kSigNone && !kGeneric) {
       const float z0 = unif(p[0]);
       const bool ground = b >= z0;
       if constexpr (SIG != kSigZ) {
@@ -262,10 +275,9 @@ template <int SIG> struct Reg32 {
       g += (uint32_t)ground;
     }
   }
-  // FP64 phase rate of region index k
+  // FP64 phase rate of region index k (specialised signatures)
   __device__ __forceinline__ double rate(const DevReq &Q, int k) const {
-    if constexpr (SIG == kSigGeneric) return Q.c[k];
-    else return k == 2 ? Q.c[Q.nprims] : Q.c[k];
+    return k == 2 ? Q.c[Q.nprims] : Q.c[k];
   }
   // phase of n full steps from the counts g, m
   __device__ __forceinline__ double phase(const DevReq &Q, uint32_t g, uint32_t m, uint32_t n) const {
@@ -278,28 +290,56 @@ template <int SIG> struct Reg32 {
       return (unid(Q.c[0]) * (double)(n - g) + unid(Q.c[1]) * (double)m) + cb * (double)(g - m);
     }
   }
-  // generic signature: FP32 rate of the region containing (a, b).  With the
-  // sigma grid: one cell read and one edge function (the primitive loop only
-  // in cells crossed by more than one boundary); the same result as the loop
-  // for every point (the host classifies cells with margins for the FP32
-  // rounding of the cell index and of the edge functions).
-  __device__ __forceinline__ float rate32(const DevReq &Q, float a, float b) const {
-    if (grid == nullptr) return region_c_generic<float, 8>((int)Q.nprims, Q.kind, &Q.pf[0][0], Q.fc, a, b);
-    int i = (int)__builtin_fmaf(a, gsy, goy);
-    int j = (int)__builtin_fmaf(b, gsz, goz);
-    i = min(max(i, 0), (int)gy - 1);
-    j = min(max(j, 0), (int)gz - 1);
-    // both halves of the cell in flight together, through the global address
-    // space (one memory latency per step)
-    typedef const __attribute__((address_space(1))) uint32_t *gptr;
-    const gptr w = (gptr)(grid + ((uint32_t)j * gy + (uint32_t)i));
-    const uint32_t flags = w[0], mode = w[1], rin = w[2], rout = w[3];
-    const float v0 = __builtin_bit_cast(float, w[4]), v1 = __builtin_bit_cast(float, w[5]);
-    const float dy = __builtin_bit_cast(float, w[6]), dz = __builtin_bit_cast(float, w[7]);
+  // generic signature: the fixed-point increment of the region containing
+  // (a, b).  With the sigma grid: one cell read and one edge function (the
+  // primitive loop only in cells crossed by more than one boundary); the same
+  // region as the loop for every point (the host classifies cells with
+  // margins for the FP32 rounding of the cell index and of the edge
+  // functions).  The cell comes from LDS (kSigGenericLds: a class byte, then
+  // the class's SigmaCell) or from the global grid.
+  __device__ __forceinline__ uint32_t inc32(const DevReq &Q, float a, float b) const {
+    if constexpr (SIG == kSigGeneric) {
+      if (grid == nullptr) return region_c_generic<float, 8>((int)Q.nprims, Q.kind, &Q.pf[0][0], Q.cfx, a, b);
+    }
+    // cell (trunc(a gsy + goy), trunc(b gsz + goz)) clamped to the grid:
+    // clamping in FP32 before the truncation gives the same cell
+    const uint32_t i = (uint32_t)__builtin_amdgcn_fmed3f(__builtin_fmaf(a, gsy, goy), 0.f, gmy);
+    const uint32_t j = (uint32_t)__builtin_amdgcn_fmed3f(__builtin_fmaf(b, gsz, goz), 0.f, gmz);
+    const uint32_t cell = __umul24(j, gy) + i;
+    uint32_t inc_ge, inc_lt, xi;
+    float v0, v1, dy, dz;
+    if constexpr (SIG == kSigGenericLds) {
+      const uint32_t cls = g_lds[(size_t)lds_classes * sizeof(SigmaCell) + cell];
+      const uint4 h0 = *reinterpret_cast<const uint4 *>(g_lds + (size_t)cls * sizeof(SigmaCell));
+      inc_ge = h0.x; inc_lt = h0.y;
+      v0 = __builtin_bit_cast(float, h0.z); v1 = __builtin_bit_cast(float, h0.w);
+      const uint4 h1 = *reinterpret_cast<const uint4 *>(g_lds + (size_t)cls * sizeof(SigmaCell) + 16);
+      dy = __builtin_bit_cast(float, h1.x); dz = __builtin_bit_cast(float, h1.y);
+      xi = h1.z;
+    } else {
+      // the cell's 28 bytes in flight together, through the global address
+      // space (one memory latency per step)
+      typedef const __attribute__((address_space(1))) uint32_t *gptr;
+      const gptr w = (gptr)(grid + cell);
+      inc_ge = w[0]; inc_lt = w[1];
+      v0 = __builtin_bit_cast(float, w[2]); v1 = __builtin_bit_cast(float, w[3]);
+      dy = __builtin_bit_cast(float, w[4]); dz = __builtin_bit_cast(float, w[5]);
+      xi = w[6];
+    }
     const float e = dy * (b - v1) - dz * (a - v0);
-    const bool in = mode == 0u ? (e < 0.f) : (mode == 1u ? (e >= 0.f) : (e <= 0.f));
-    float c = __builtin_bit_cast(float, in ? rin : rout);
-    if (flags & kCellLoop) c = region_c_generic<float, 8>((int)Q.nprims, Q.kind, &Q.pf[0][0], Q.fc, a, b);
+    uint32_t c = e >= 0.f ? inc_ge : inc_lt;
+    if (inc_ge & kCellFlags) {   // a few cells: two lines, or the primitive loop
+      if (inc_ge & kCellTwo) {
+        const SigmaCell *X;
+        if constexpr (SIG == kSigGenericLds) X = reinterpret_cast<const SigmaCell *>(g_lds) + xi;
+        else X = grid_ext + xi;
+        const float e2 = X->dy * (b - X->v1) - X->dz * (a - X->v0);
+        if (e2 >= 0.f) c = e >= 0.f ? X->inc_ge : X->inc_lt;
+        else c = e >= 0.f ? (inc_ge & ~kCellFlags) : inc_lt;
+      } else {
+        c = region_c_generic<float, 8>((int)Q.nprims, Q.kind, &Q.pf[0][0], Q.cfx, a, b);
+      }
+    }
     return c;
   }
 };
@@ -510,7 +550,8 @@ struct W32 {
   float a, b;       // y - ymid, z - zmid
   float d0y, d0z;   // h - |a|, h - |b|
   uint32_t n0, n1;  // counted signatures: full steps below the air / those in primitive 1
-  float shi, slo;   // phase S = shi + slo (generic signature, compensated)
+  uint64_t sfx;     // generic signature: phase of the full steps, units of 2^-phase_shift
+  uint32_t cinc;    // generic signature: increment of the current point's region
   uint32_t n, path, node;
   uint64_t rec;
   uint64_t P;
@@ -572,8 +613,8 @@ __device__ __forceinline__ void start32(const DevReq &Q, const U32<SIG> &U, W32 
   W.d0z = U.hz - fabsf(W.b);
   W.n0 = 0;
   W.n1 = 0;
-  W.shi = 0.f;
-  W.slo = 0.f;
+  W.sfx = 0;
+  if constexpr (Reg32<SIG>::kGeneric) W.cinc = U.reg.inc32(Q, W.a, W.b);
   W.n = 0;
   W.path = path;
   W.node = node;
@@ -627,26 +668,27 @@ __device__ __forceinline__ bool exit32(const DevReq &Q, const U32<SIG> &U, const
   X.n = nstep;
   // phase of the nstep full steps, plus the partial step charged to the
   // region of the last inside point
-  const double S = Reg32<SIG>::kCounted ? U.reg.phase(Q, W.n0, W.n1, nstep)
-                                        : (double)W.shi + (double)W.slo;
-  X.S = S + U.reg.rate(Q, U.reg.index(Q, W.a, W.b)) * (double)f;
+  if constexpr (Reg32<SIG>::kCounted) {
+    X.S = U.reg.phase(Q, W.n0, W.n1, nstep) + U.reg.rate(Q, U.reg.index(Q, W.a, W.b)) * (double)f;
+  } else {
+    X.S = __builtin_ldexp((double)W.sfx + (double)W.cinc * (double)f, -Q.phase_shift);
+  }
   return true;
 }
 
 // A full step to (an, bn): the walker moves there and the step's phase goes
 // to the region of that point (right-point rule): a step count per region,
-// or (generic signature) a compensated FP32 sum (Fast2Sum: S_hi grows from 0
-// by increments c >= 0).
+// or (generic signature) the region's fixed-point increment added to the
+// 64-bit sum.
 template <int SIG>
 __device__ __forceinline__ void advance32(const DevReq &Q, const U32<SIG> &U, W32 &W, float an, float bn, float e1y,
                                           float e1z) {
   if constexpr (Reg32<SIG>::kCounted) {
     U.reg.count(an, bn, W.n0, W.n1);
   } else {
-    const float c = U.reg.rate32(Q, an, bn);
-    const float s = W.shi + c;
-    W.slo += c - (s - W.shi);
-    W.shi = s;
+    const uint32_t c = U.reg.inc32(Q, an, bn);
+    W.sfx += c;
+    W.cinc = c;
   }
   W.a = an;
   W.b = bn;
@@ -765,19 +807,22 @@ template <int SIG> struct F32 {
   static __device__ __forceinline__ PathRec finish(const DevReq &Q, const Walker &, const Exit &X) {
     return finish32(Q, X);
   }
-  // counts and FP32 values all widen to doubles exactly
+  // counts and FP32 values all widen to doubles exactly; the generic
+  // signature's 64-bit phase sum and increment go to the integer fields
   static __device__ __forceinline__ void save(const Walker &W, SuspRec &s) {
     s.x = (double)W.a; s.y = (double)W.b;
-    s.s_hi = Reg32<SIG>::kCounted ? (double)W.n0 : (double)W.shi;
-    s.s_lo = Reg32<SIG>::kCounted ? (double)W.n1 : (double)W.slo;
-    s.rec = W.rec; s.n = W.n; s.path = W.path; s.node = W.node; s.pad = 0; s.pad1 = 0;
+    s.s_hi = Reg32<SIG>::kCounted ? (double)W.n0 : 0.0;
+    s.s_lo = Reg32<SIG>::kCounted ? (double)W.n1 : 0.0;
+    s.rec = W.rec; s.n = W.n; s.path = W.path; s.node = W.node;
+    s.pad = Reg32<SIG>::kCounted ? 0u : W.cinc;
+    s.pad1 = Reg32<SIG>::kCounted ? 0ull : W.sfx;
   }
   static __device__ __forceinline__ void resume(const DevReq &Q, const Uni &U, Walker &W, const SuspRec &s) {
     W.a = (float)s.x; W.b = (float)s.y;
     if constexpr (Reg32<SIG>::kCounted) {
       W.n0 = (uint32_t)s.s_hi; W.n1 = (uint32_t)s.s_lo;
     } else {
-      W.shi = (float)s.s_hi; W.slo = (float)s.s_lo;
+      W.sfx = s.pad1; W.cinc = s.pad;
     }
     W.rec = s.rec; W.n = s.n; W.path = s.path; W.node = s.node;
     W.d0y = U.hy - fabsf(W.a);
@@ -1044,6 +1089,22 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))
   persist_body<F32, SIG>(reqs, n_req, wave_start, budget, refill_mask);
 }
 
+// The generic signature with the sigma grid staged in LDS: every request of
+// the launch shares one grid (the same model, time step and frequency), whose
+// class table and class bytes each block copies into LDS once.  Blocks of 768
+// threads, two per CU (the LDS form of a 256 x 224 grid is about 60 KB), so
+// a CU holds 24 waves as the 256-thread walkers do.
+constexpr uint32_t kLdsThreads = 768;
+__global__ void __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(6, 8))) walk_persist_f32_lds(const DevReq *__restrict__ reqs, uint32_t n_req,
+                                                                     const uint32_t *__restrict__ wave_start,
+                                                                     uint32_t budget, uint32_t refill_mask) {
+  const uint4 *src = reinterpret_cast<const uint4 *>(reqs[0].lds_src);
+  const uint32_t n16 = reqs[0].lds_bytes / 16u;
+  for (uint32_t i = threadIdx.x; i < n16; i += blockDim.x) reinterpret_cast<uint4 *>(g_lds)[i] = src[i];
+  __syncthreads();
+  persist_body<F32, kSigGenericLds>(reqs, n_req, wave_start, budget, refill_mask);
+}
+
 using PersistKernel = void (*)(const DevReq *, uint32_t, const uint32_t *, uint32_t, uint32_t);
 
 template <int SIG> struct K64 { static constexpr PersistKernel fn = walk_persist_f64<SIG>; };
@@ -1063,6 +1124,7 @@ static PersistKernel pick_kernel(int sig) {
 }
 
 static PersistKernel persist_kernel(int precision, int sig) {
+  if (precision != 0 && sig == kSigGenericLds) return walk_persist_f32_lds;
   return precision == 0 ? pick_kernel<K64>(sig) : pick_kernel<K32>(sig);
 }
 
@@ -1212,20 +1274,24 @@ hipError_t launch_walk_plain(const DevReq *req_dev, uint32_t node, uint32_t p0, 
   return hipGetLastError();
 }
 
+// lds_bytes: the dynamic LDS of the kSigGenericLds walker (the grid's LDS
+// form), 0 for every other build.
 hipError_t launch_walk_persist(int precision, int sig, const DevReq *reqs_dev, uint32_t n_req,
                                const uint32_t *wave_start_dev, uint32_t budget, uint32_t refill_mask, uint32_t blocks,
-                               uint32_t threads, hipStream_t st) {
-  hipLaunchKernelGGL(persist_kernel(precision, sig), dim3(blocks), dim3(threads), 0, st, reqs_dev, n_req,
+                               uint32_t threads, uint32_t lds_bytes, hipStream_t st) {
+  hipLaunchKernelGGL(persist_kernel(precision, sig), dim3(blocks), dim3(threads), lds_bytes, st, reqs_dev, n_req,
                      wave_start_dev, budget, refill_mask);
   return hipGetLastError();
 }
 
-int persist_blocks_per_cu(int precision, int sig, uint32_t threads) {
+int persist_blocks_per_cu(int precision, int sig, uint32_t threads, uint32_t lds_bytes) {
   int nb = 0;
-  const hipError_t e =
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persist_kernel(precision, sig), (int)threads, 0);
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persist_kernel(precision, sig), (int)threads,
+                                                                    lds_bytes);
   return e == hipSuccess ? nb : 0;
 }
+
+uint32_t lds_walker_threads() { return kLdsThreads; }
 
 hipError_t launch_reduce_fanout(const FanJob *jobs_dev, uint32_t n_jobs, int M, double y_lo, double y_hi, double z_lo,
                                 double z_hi, hipStream_t st) {

@@ -31,12 +31,13 @@ hipError_t launch_walk_plain(const DevReq *req_dev, uint32_t node, uint32_t p0, 
                              hipStream_t st);
 hipError_t launch_walk_persist(int precision, int sig, const DevReq *reqs_dev, uint32_t n_req,
                                const uint32_t *wave_start_dev, uint32_t budget, uint32_t refill_mask, uint32_t blocks,
-                               uint32_t threads, hipStream_t st);
+                               uint32_t threads, uint32_t lds_bytes, hipStream_t st);
 hipError_t launch_reduce(const NodeJob *jobs_dev, uint32_t n_jobs, hipStream_t st);
 hipError_t launch_reduce_fanout(const FanJob *jobs_dev, uint32_t n_jobs, int M, double y_lo, double y_hi, double z_lo,
                                 double z_hi, hipStream_t st);
 hipError_t launch_reset(uint32_t *tile_counters, unsigned long long *done, uint32_t n, hipStream_t st);
-int persist_blocks_per_cu(int precision, int sig, uint32_t threads);
+int persist_blocks_per_cu(int precision, int sig, uint32_t threads, uint32_t lds_bytes);
+uint32_t lds_walker_threads();
 hipError_t launch_walk_kappa(int precision, const KReq *req_dev, uint32_t blocks, hipStream_t st);
 int kappa_blocks_per_cu(int precision);
 uint32_t kappa_threads();
@@ -166,9 +167,11 @@ struct Prepared {
   uint64_t n_paths = 0;            // paths in this pass
   std::vector<uint64_t> rec_off;   // per node record offset of this pass
   std::vector<SigmaCell> grid;     // sigma grid (FP32 generic signature), empty if none
+  std::vector<SigmaCell> grid_ext; // its two-line cells' extension entries
+  std::vector<uint8_t> lds;        // its LDS form (class table, class bytes), empty if none
   // device allocations
   char *d_g = nullptr, *d_nodes = nullptr, *d_tiles = nullptr, *d_recs = nullptr;
-  char *d_grid = nullptr;
+  char *d_grid = nullptr, *d_grid_ext = nullptr, *d_lds = nullptr;
   char *d_recs_pilot = nullptr;    // pilot records kept for the final reduction
   std::vector<uint64_t> pilot_off; // per node pilot record offset
   std::vector<uint32_t> pilot_cnt;
@@ -200,6 +203,7 @@ struct sdd_ctx {
   hipStream_t stream = nullptr;
   Arena arena;
   int cus = 0;
+  size_t lds_per_block = 0;        // the device's LDS limit per block (the LDS-grid walker)
   sdd_tuning tuning{256, 0, 512, 4096, 1};
   std::mutex exec;                 // one launch sequence at a time on the stream
   std::atomic<int> exec_waiters{0};   // callers (not the served worker) waiting for exec
@@ -291,7 +295,7 @@ static sdd_status validate(sdd_ctx *ctx, const sdd_request *r, const HostModel *
   if (r->freq_hz < 0.0 || !std::isfinite(r->freq_hz)) return fail(SDD_E_INVALID, "freq_hz must be >= 0");
   if (r->freq_hz == 0.0 && (!(r->alpha_direct >= 0.0) || !std::isfinite(r->alpha_direct)))
     return fail(SDD_E_INVALID, "alpha_direct must be >= 0 when freq_hz == 0");
-  if (r->flags & ~(uint32_t)(SDD_FLAG_NO_SIGMA_GRID | SDD_FLAG_EXIT_NAIVE))
+  if (r->flags & ~(uint32_t)(SDD_FLAG_NO_SIGMA_GRID | SDD_FLAG_EXIT_NAIVE | SDD_FLAG_NO_LDS_GRID))
     return fail(SDD_E_INVALID, "unknown flags");
   if (!(r->target_rel_se >= 0.0) || !std::isfinite(r->target_rel_se))
     return fail(SDD_E_INVALID, "target_rel_se must be >= 0");
@@ -375,42 +379,77 @@ GSign classify(const GLine &L, double a0, double a1, double b0, double b1) {
   return kGCross;
 }
 
-// status of one primitive over the cell; for kGOne, the crossing line and
-// the mode of its test
-GStat prim_status(int kind, const GLine *L, int nl, double a0, double a1, double b0, double b1, GLine &one) {
+// One test of a point against a line: t = (e' >= 0), e' the edge function
+// (negated when neg: exactly -e in FP32), and the primitive's condition is t
+// (inv = false) or not t (inv = true).  The loop's three tests read:
+// e >= 0 (t), e < 0 (not t), e <= 0 (t on the negated line).
+struct LineTest {
+  GLine line;
+  bool neg, inv;
+};
+
+// A primitive over a cell: outside everywhere, inside everywhere, or inside
+// iff every one of its crossing tests holds (n of them).
+struct PrimCell {
+  int status;   // kGOut, kGIn, or kGOne for a conjunction of tests
+  int n;
+  LineTest t[4];
+};
+
+PrimCell prim_cell(int kind, const GLine *L, int nl, double a0, double a1, double b0, double b1) {
+  PrimCell P{kGOut, 0, {}};
   GSign c[4];
   for (int i = 0; i < nl; ++i) c[i] = classify(L[i], a0, a1, b0, b1);
   if (kind == SDD_TRIANGLE) {
-    int pos = 0, neg = 0, cross = 0, ci = -1;
+    int pos = 0, neg = 0, cross = 0;
     for (int i = 0; i < 3; ++i) {
       if (c[i] == kGPos) ++pos;
       else if (c[i] == kGNeg) ++neg;
-      else { ++cross; ci = i; }
+      else ++cross;
     }
-    if (pos && neg) return kGOut;    // no point has all three edge signs equal
-    if (cross == 0) return kGIn;
-    if (cross > 1) return kGMany;
-    one = L[ci];
-    one.mode = pos ? 1u : 2u;        // inside iff e >= 0 (others > 0) or e <= 0 (others < 0)
-    return kGOne;
+    if (pos && neg) return P;                     // no point has all three edge signs equal
+    if (cross == 0) { P.status = kGIn; return P; }
+    if (cross == 3) { P.status = kGMany; return P; }   // inside: all e >= 0 or all e <= 0 (not one conjunction)
+    P.status = kGOne;
+    for (int i = 0; i < 3; ++i)
+      if (c[i] == kGCross) P.t[P.n++] = LineTest{L[i], neg > 0, false};   // all e >= 0 (pos) or all e <= 0 (neg)
+    return P;
   }
-  int cross = 0, ci = -1;
   for (int i = 0; i < nl; ++i) {
     const bool holds = L[i].mode == 0u ? c[i] == kGNeg : c[i] == kGPos;
     const bool fails = L[i].mode == 0u ? c[i] == kGPos : c[i] == kGNeg;
-    if (fails) return kGOut;
-    if (!holds) { ++cross; ci = i; }
+    if (fails) return P;
+    if (!holds) P.t[P.n++] = LineTest{L[i], false, L[i].mode == 0u};
   }
-  if (cross == 0) return kGIn;
-  if (cross > 1) return kGMany;
-  one = L[ci];
-  return kGOne;
+  P.status = P.n == 0 ? kGIn : kGOne;
+  return P;
+}
+
+bool same_line(const LineTest &x, const LineTest &y) {
+  return x.neg == y.neg && x.line.v0 == y.line.v0 && x.line.v1 == y.line.v1 && x.line.dy == y.line.dy &&
+         x.line.dz == y.line.dz;
 }
 }  // namespace
 
 static constexpr uint32_t kGridCells = 65536;
 
-static void build_sigma_grid(DevReq &q, std::vector<SigmaCell> &grid) {
+// The cell's line in SigmaCell form (negated when the test needs it).
+static void put_line(SigmaCell &C, const LineTest &t) {
+  C.v0 = t.line.v0;
+  C.v1 = t.line.v1;
+  C.dy = t.neg ? -t.line.dy : t.line.dy;
+  C.dz = t.neg ? -t.line.dz : t.line.dz;
+}
+
+// Sigma grid of the FP32 walk's generic signature.  Per cell: the primitives
+// in list order up to the first one that holds on the whole cell; those that
+// cross it are conjunctions of line tests; if all their tests use at most two
+// distinct lines, the cell's increment is a function of the two signs
+// (e1 >= 0, e2 >= 0), evaluated for the four combinations with the
+// primitives' first-match rule.  Cells with more lines take the primitive
+// loop.  Two-line cells keep their second line and the increments of
+// e2 >= 0 in an entry of `ext`.
+static void build_sigma_grid(DevReq &q, std::vector<SigmaCell> &grid, std::vector<SigmaCell> &ext) {
   const int np = (int)q.nprims;
   GLine lines[kMaxPrims][4];
   int nl[kMaxPrims];
@@ -427,11 +466,16 @@ static void build_sigma_grid(DevReq &q, std::vector<SigmaCell> &grid) {
   }
   q.gy = gy;
   q.gz = gz;
+  q.gmy = (float)(gy - 1);
+  q.gmz = (float)(gz - 1);
   q.gsy = (float)((double)gy / (2.0 * hy));
   q.goy = (float)(hy * (double)q.gsy);
   q.gsz = (float)((double)gz / (2.0 * hz));
   q.goz = (float)(hz * (double)q.gsz);
   grid.assign((size_t)gy * gz, SigmaCell{});
+  ext.clear();
+  std::map<std::vector<uint8_t>, uint32_t> ext_index;
+  PrimCell pc[kMaxPrims];
   for (uint32_t j = 0; j < gz; ++j) {
     // the points the kernel maps to row j: j <= b gsz + goz < j + 1
     const double b0 = ((double)j - (double)q.goz) / (double)q.gsz;
@@ -442,41 +486,111 @@ static void build_sigma_grid(DevReq &q, std::vector<SigmaCell> &grid) {
       const double a1 = ((double)i + 1.0 - (double)q.goy) / (double)q.gsy;
       const double da = 1e-3 * (a1 - a0);
       SigmaCell &C = grid[(size_t)j * gy + i];
-      int pend = -1;
-      GLine pl{};
+      // the primitives that matter, and the distinct lines their tests use
+      int last = np;   // first primitive holding on the whole cell (np: none)
       bool loop = false;
-      int region = np;   // background unless a primitive decides
+      LineTest L[2];
+      int nlines = 0;
       for (int k = 0; k < np && !loop; ++k) {
-        GLine one{};
-        const GStat st = prim_status(q.kind[k], lines[k], nl[k], a0 - da, a1 + da, b0 - db, b1 + db, one);
-        if (st == kGOut) continue;
-        if (st == kGMany) { loop = true; break; }
-        if (st == kGOne) {
-          if (pend >= 0) { loop = true; break; }
-          pend = k;
-          pl = one;
-          continue;
+        pc[k] = prim_cell(q.kind[k], lines[k], nl[k], a0 - da, a1 + da, b0 - db, b1 + db);
+        if (pc[k].status == kGMany) { loop = true; break; }
+        if (pc[k].status == kGIn) { last = k; break; }
+        for (int m = 0; m < pc[k].n && !loop; ++m) {
+          int f = -1;
+          for (int l = 0; l < nlines; ++l)
+            if (same_line(L[l], pc[k].t[m])) f = l;
+          if (f < 0) {
+            if (nlines == 2) loop = true;
+            else L[nlines++] = pc[k].t[m];
+          }
         }
-        region = k;   // kGIn: the first primitive that holds on the whole cell
-        break;
       }
       if (loop) {
-        C.flags = kCellLoop;
+        C.inc_ge = kCellLoop;
         continue;
       }
-      C.flags = 0u;
-      if (pend >= 0) {
-        C.mode = pl.mode;
-        C.v0 = pl.v0; C.v1 = pl.v1; C.dy = pl.dy; C.dz = pl.dz;
-        C.rate_in = q.fc[pend];
-        C.rate_out = q.fc[region];
+      // the increment for each sign combination (t1, t2): the first primitive
+      // (up to `last`) whose tests all hold, else `last`'s region (the
+      // background when last == np)
+      uint32_t T[4];
+      for (int combo = 0; combo < 4; ++combo) {
+        const bool t[2] = {(combo & 1) != 0, (combo & 2) != 0};
+        int region = last;
+        for (int k = 0; k < last; ++k) {
+          if (pc[k].status != kGOne) continue;
+          bool all = true;
+          for (int m = 0; m < pc[k].n; ++m) {
+            const LineTest &x = pc[k].t[m];
+            const int l = same_line(L[0], x) ? 0 : 1;
+            all = all && (t[l] != x.inv);
+          }
+          if (all) { region = k; break; }
+        }
+        T[combo] = q.cfx[region];
+      }
+      if (nlines == 0) {
+        C.v0 = C.v1 = C.dy = C.dz = 0.f;   // e = +-0 >= 0
+        C.inc_ge = C.inc_lt = T[0];
+      } else if (nlines == 1 || (T[0] == T[2] && T[1] == T[3])) {
+        put_line(C, L[0]);
+        C.inc_ge = T[1];
+        C.inc_lt = T[0];
       } else {
-        C.mode = 1u;   // e = +-0 >= 0: rate_in
-        C.v0 = C.v1 = C.dy = C.dz = 0.f;
-        C.rate_in = C.rate_out = q.fc[region];
+        put_line(C, L[0]);
+        C.inc_ge = T[1] | kCellTwo;
+        C.inc_lt = T[0];
+        SigmaCell E{};
+        put_line(E, L[1]);
+        E.inc_ge = T[3];   // e1 >= 0, e2 >= 0
+        E.inc_lt = T[2];   // e1 < 0, e2 >= 0
+        const uint8_t *eb = reinterpret_cast<const uint8_t *>(&E);
+        std::vector<uint8_t> key(eb, eb + sizeof(E));
+        auto it = ext_index.find(key);
+        if (it == ext_index.end()) {
+          it = ext_index.emplace(key, (uint32_t)ext.size()).first;
+          ext.push_back(E);
+        }
+        C.pad[0] = it->second;
       }
     }
   }
+}
+
+// The LDS form of a sigma grid: its distinct cells once (a class table),
+// then the two-line cells' extension entries (each cell's pad[0] renumbered
+// to its entry's place in this table), then one class byte per cell; empty
+// when the grid has more than kMaxLdsClasses distinct cells or the form
+// would not fit in max_bytes of LDS.  n_table is the number of 32-byte
+// entries before the class bytes.  Padded to a multiple of 16 bytes.
+static void build_lds_form(const std::vector<SigmaCell> &grid, const std::vector<SigmaCell> &ext, size_t max_bytes,
+                           std::vector<uint8_t> &out, uint32_t &n_table) {
+  out.clear();
+  n_table = 0;
+  std::vector<SigmaCell> classes;
+  std::map<std::vector<uint8_t>, uint32_t> index;
+  std::vector<uint8_t> ids(grid.size());
+  for (size_t c = 0; c < grid.size(); ++c) {
+    const uint8_t *b = reinterpret_cast<const uint8_t *>(&grid[c]);
+    std::vector<uint8_t> key(b, b + sizeof(SigmaCell));
+    auto it = index.find(key);
+    if (it == index.end()) {
+      if (classes.size() == kMaxLdsClasses) return;
+      it = index.emplace(key, (uint32_t)classes.size()).first;
+      classes.push_back(grid[c]);
+    }
+    ids[c] = (uint8_t)it->second;
+  }
+  for (SigmaCell &C : classes)
+    if ((C.inc_ge & kCellFlags) == kCellTwo) C.pad[0] += (uint32_t)classes.size();
+  const size_t n = classes.size() + ext.size();
+  const size_t bytes = (n * sizeof(SigmaCell) + ids.size() + 15) / 16 * 16;
+  if (bytes > max_bytes) return;
+  n_table = (uint32_t)n;
+  out.resize(n * sizeof(SigmaCell) + ids.size());
+  std::memcpy(out.data(), classes.data(), classes.size() * sizeof(SigmaCell));
+  if (!ext.empty()) std::memcpy(out.data() + classes.size() * sizeof(SigmaCell), ext.data(), ext.size() * sizeof(SigmaCell));
+  std::memcpy(out.data() + n * sizeof(SigmaCell), ids.data(), ids.size());
+  out.resize(bytes, 0);
 }
 
 static void fill_devreq(Prepared &P) {
@@ -567,7 +681,17 @@ static void fill_devreq(Prepared &P) {
   }
   q.fscr_root = sqrtf(q.fscr);
   while (!(q.fscr_root * q.fscr_root > q.fscr)) q.fscr_root = nextafterf(q.fscr_root, INFINITY);
-  for (uint32_t k = 0; k <= np; ++k) q.fc[k] = (float)q.c[k];
+  // fixed-point phase increments of the generic FP32 walk: the largest one in
+  // [2^29, 2^30] (bit 31 is the sigma grid's loop mark), so a 64-bit sum holds
+  // 2^32 steps exactly
+  {
+    double cmax = 0.0;
+    for (uint32_t k = 0; k <= np; ++k) cmax = std::max(cmax, q.c[k]);
+    int e = 0;
+    if (cmax > 0.0) (void)std::frexp(cmax, &e);
+    q.phase_shift = cmax > 0.0 ? 30 - e : 0;
+    for (uint32_t k = 0; k <= np; ++k) q.cfx[k] = (uint32_t)std::llround(std::ldexp(q.c[k], q.phase_shift));
+  }
   q.key0 = (uint32_t)(r.seed & 0xFFFFFFFFu);
   q.key1 = (uint32_t)(r.seed >> 32);
   q.ctr3 = 2u * r.stream;
@@ -579,9 +703,18 @@ static void fill_devreq(Prepared &P) {
   q.M = r.g_samples - 1;
   q.model = reinterpret_cast<const DevModel *>(m.dev);
   P.grid.clear();
+  P.grid_ext.clear();
+  P.lds.clear();
   q.grid = nullptr;
-  if (q.sig == kSigGeneric && r.precision == SDD_FP32_MIXED && !(r.flags & SDD_FLAG_NO_SIGMA_GRID) && np > 0)
-    build_sigma_grid(q, P.grid);
+  q.grid_ext = nullptr;
+  q.lds_src = nullptr;
+  q.lds_bytes = q.lds_classes = 0;
+  if (q.sig == kSigGeneric && r.precision == SDD_FP32_MIXED && !(r.flags & SDD_FLAG_NO_SIGMA_GRID) && np > 0) {
+    build_sigma_grid(q, P.grid, P.grid_ext);
+    if (!(r.flags & SDD_FLAG_NO_LDS_GRID))
+      build_lds_form(P.grid, P.grid_ext, P.owner->lds_per_block, P.lds, q.lds_classes);
+    q.lds_bytes = (uint32_t)P.lds.size();
+  }
 }
 
 // Copy the request's inputs; set up the first pass's path ranges.
@@ -693,7 +826,8 @@ static uint32_t tile_size(sdd_ctx *ctx, const Prepared &P) {
 
 static size_t pass_bytes(const Prepared &P) {
   return Arena::round(P.g.size() * 8) + Arena::round(P.nodes.size() * 8 + 16) +
-         Arena::round(P.grid.size() * sizeof(SigmaCell)) +
+         Arena::round(P.grid.size() * sizeof(SigmaCell)) + Arena::round(P.grid_ext.size() * sizeof(SigmaCell)) +
+         Arena::round(P.lds.size()) +
          Arena::round(P.tiles.size() * sizeof(DevTile) + 16) + Arena::round(P.n_paths * sizeof(PathRec) + 16);
 }
 
@@ -703,7 +837,9 @@ static void release_pass(sdd_ctx *ctx, Prepared &P) {
   ctx->release(P.d_tiles);
   ctx->release(P.d_recs);
   ctx->release(P.d_grid);
-  P.d_g = P.d_nodes = P.d_tiles = P.d_recs = P.d_grid = nullptr;
+  ctx->release(P.d_grid_ext);
+  ctx->release(P.d_lds);
+  P.d_g = P.d_nodes = P.d_tiles = P.d_recs = P.d_grid = P.d_grid_ext = P.d_lds = nullptr;
 }
 
 static void release_all(sdd_ctx *ctx, Prepared &P) {
@@ -720,7 +856,10 @@ static sdd_status upload_pass(sdd_ctx *ctx, Prepared &P) {
   P.d_tiles = ctx->alloc(P.tiles.size() * sizeof(DevTile) + 16);
   P.d_recs = ctx->alloc(P.n_paths * sizeof(PathRec) + 16);
   if (!P.grid.empty()) P.d_grid = ctx->alloc(P.grid.size() * sizeof(SigmaCell));
-  if (!P.d_g || !P.d_nodes || !P.d_tiles || !P.d_recs || (!P.grid.empty() && !P.d_grid)) {
+  if (!P.lds.empty()) P.d_lds = ctx->alloc(P.lds.size());
+  if (!P.grid_ext.empty()) P.d_grid_ext = ctx->alloc(P.grid_ext.size() * sizeof(SigmaCell));
+  if (!P.d_g || !P.d_nodes || !P.d_tiles || !P.d_recs || (!P.grid.empty() && !P.d_grid) ||
+      (!P.lds.empty() && !P.d_lds) || (!P.grid_ext.empty() && !P.d_grid_ext)) {
     release_pass(ctx, P);
     size_t largest;
     {
@@ -746,6 +885,17 @@ static sdd_status upload_pass(sdd_ctx *ctx, Prepared &P) {
     HIP_TRY(hipMemcpyAsync(P.d_grid, P.grid.data(), P.grid.size() * sizeof(SigmaCell), hipMemcpyHostToDevice,
                            ctx->stream));
     P.dreq.grid = reinterpret_cast<const SigmaCell *>(P.d_grid);
+  }
+  P.dreq.grid_ext = nullptr;
+  if (!P.grid_ext.empty()) {
+    HIP_TRY(hipMemcpyAsync(P.d_grid_ext, P.grid_ext.data(), P.grid_ext.size() * sizeof(SigmaCell),
+                           hipMemcpyHostToDevice, ctx->stream));
+    P.dreq.grid_ext = reinterpret_cast<const SigmaCell *>(P.d_grid_ext);
+  }
+  P.dreq.lds_src = nullptr;
+  if (!P.lds.empty()) {
+    HIP_TRY(hipMemcpyAsync(P.d_lds, P.lds.data(), P.lds.size(), hipMemcpyHostToDevice, ctx->stream));
+    P.dreq.lds_src = reinterpret_cast<const uint8_t *>(P.d_lds);
   }
   return SDD_OK;
 }
@@ -781,11 +931,42 @@ static int common_sig(It begin, It end, Get get) {
   return sig == -2 ? -1 : sig;
 }
 
-static void launch_shape(sdd_ctx *ctx, int precision, int sig, uint32_t &blocks, uint32_t &threads) {
+// The walker build of a launch over passes of one precision: the model
+// signature every pass shares (or -1), turned into kSigGenericLds when every
+// pass is an FP32-mixed generic request with the same sigma grid (the same
+// model, time step and frequency: identical LDS forms and cell mapping); then
+// lds_bytes is the size of that form.
+static bool same_lds_grid(const Prepared &a, const Prepared &b) {
+  const DevReq &x = a.dreq, &y = b.dreq;
+  return a.lds == b.lds && x.lds_classes == y.lds_classes && x.gy == y.gy && x.gz == y.gz && x.gsy == y.gsy &&
+         x.goy == y.goy && x.gsz == y.gsz && x.goz == y.goz;
+}
+
+template <class It, class Get>
+static int launch_sig(It begin, It end, Get get, uint32_t &lds_bytes) {
+  lds_bytes = 0;
+  const int sig = common_sig(begin, end, [&](const auto &x) { return get(x)->dreq.sig; });
+  if (sig != kSigGeneric) return sig;
+  const Prepared *first = get(*begin);
+  if (first->dreq.precision != SDD_FP32_MIXED || first->lds.empty()) return sig;
+  for (It i = begin; i != end; ++i)
+    if (!same_lds_grid(*first, *get(*i))) return sig;
+  lds_bytes = (uint32_t)first->lds.size();
+  return kSigGenericLds;
+}
+
+static void launch_shape(sdd_ctx *ctx, int precision, int sig, uint32_t lds_bytes, uint32_t &blocks,
+                         uint32_t &threads) {
+  if (sig == kSigGenericLds) {   // its own block size; the tuned block shape is for the others
+    threads = lds_walker_threads();
+    const int occ = persist_blocks_per_cu(precision, sig, threads, lds_bytes);
+    blocks = (uint32_t)ctx->cus * (occ > 0 ? (uint32_t)occ : 1u);
+    return;
+  }
   threads = ctx->tuning.block_threads ? ctx->tuning.block_threads : 256u;
   uint32_t per_cu = ctx->tuning.blocks_per_cu;
   if (!per_cu) {
-    const int occ = persist_blocks_per_cu(precision, sig, threads);
+    const int occ = persist_blocks_per_cu(precision, sig, threads, 0);
     per_cu = occ > 0 ? (uint32_t)occ : 1u;
   }
   blocks = (uint32_t)ctx->cus * per_cu;
@@ -796,9 +977,9 @@ static void launch_shape(sdd_ctx *ctx, int precision, int sig, uint32_t &blocks,
 static sdd_status run_group(sdd_ctx *ctx, std::vector<Prepared *> &passes, int precision) {
   const uint32_t n = (uint32_t)passes.size();
   if (n == 0) return SDD_OK;
-  uint32_t blocks, threads;
-  const int sig = common_sig(passes.begin(), passes.end(), [](const Prepared *P) { return P->dreq.sig; });
-  launch_shape(ctx, precision, sig, blocks, threads);
+  uint32_t blocks, threads, lds_bytes;
+  const int sig = launch_sig(passes.begin(), passes.end(), [](const Prepared *P) { return P; }, lds_bytes);
+  launch_shape(ctx, precision, sig, lds_bytes, blocks, threads);
   const uint32_t waves = blocks * (threads / 64);
   BatchScratch B;
   B.d_reqs = ctx->alloc(n * sizeof(DevReq));
@@ -817,6 +998,7 @@ static sdd_status run_group(sdd_ctx *ctx, std::vector<Prepared *> &passes, int p
   double acc = 0.0;
   for (uint32_t i = 0; i < n; ++i) {
     dq[i] = passes[i]->dreq;
+    if (sig == kSigGenericLds) dq[i].sig = kSigGenericLds;
     dq[i].tile_counter = reinterpret_cast<uint32_t *>(B.d_ctr) + i;
     dq[i].done_counter = reinterpret_cast<unsigned long long *>(B.d_done) + i;
     ws[i] = total > 0 ? (uint32_t)std::llround(acc / total * waves) : 0u;
@@ -837,7 +1019,7 @@ static sdd_status run_group(sdd_ctx *ctx, std::vector<Prepared *> &passes, int p
   if (st == SDD_OK)
     check(launch_walk_persist(precision, sig, reinterpret_cast<const DevReq *>(B.d_reqs), n,
                               reinterpret_cast<const uint32_t *>(B.d_ws), 0u, refill_mask(ctx), blocks, threads,
-                              ctx->stream),
+                              lds_bytes, ctx->stream),
           "walk_persist");
   if (st == SDD_OK) check(hipEventRecord(ctx->ev[1], ctx->stream), "event");
   std::vector<unsigned long long> done(n, 0);
@@ -1130,7 +1312,7 @@ struct Flight {
 // (two per wave).
 static uint64_t pool_bytes(sdd_ctx *ctx, const Prepared &P) {
   uint32_t blocks, threads;
-  launch_shape(ctx, (int)P.dreq.precision, P.dreq.sig, blocks, threads);
+  launch_shape(ctx, (int)P.dreq.precision, P.dreq.sig, 0, blocks, threads);
   const uint64_t lanes = (uint64_t)blocks * threads, waves = lanes / 64;
   return 2 * Arena::round(2 * lanes * sizeof(SuspRec)) + 2 * Arena::round(2 * waves * sizeof(DevTile));
 }
@@ -1189,9 +1371,9 @@ static sdd_status ensure_pools(sdd_ctx *ctx, Flight &F, uint32_t lanes, uint32_t
 static sdd_status run_slice(sdd_ctx *ctx, std::vector<Flight *> &fl, int precision) {
   const uint32_t n = (uint32_t)fl.size();
   if (n == 0) return SDD_OK;
-  uint32_t blocks, threads;
-  const int sig = common_sig(fl.begin(), fl.end(), [](const Flight *F) { return F->P->dreq.sig; });
-  launch_shape(ctx, precision, sig, blocks, threads);
+  uint32_t blocks, threads, lds_bytes;
+  const int sig = launch_sig(fl.begin(), fl.end(), [](const Flight *F) { return F->P; }, lds_bytes);
+  launch_shape(ctx, precision, sig, lds_bytes, blocks, threads);
   const uint32_t lanes = blocks * threads, waves = blocks * (threads / 64);
   for (auto *F : fl) {
     sdd_status st = ensure_pools(ctx, *F, lanes, waves);
@@ -1235,6 +1417,7 @@ static sdd_status run_slice(sdd_ctx *ctx, std::vector<Flight *> &fl, int precisi
     FlightCtl *dc = reinterpret_cast<FlightCtl *>(d_ctl) + i;
     DevReq &q = dq[i];
     q = F.P->dreq;
+    if (sig == kSigGenericLds) q.sig = kSigGenericLds;
     q.tile_counter = &dc->tile_counter;
     q.done_counter = &dc->done;
     q.slice_ctl = dc->slice;
@@ -1260,7 +1443,7 @@ static sdd_status run_slice(sdd_ctx *ctx, std::vector<Flight *> &fl, int precisi
       e = launch_walk_persist(precision, sig, reinterpret_cast<const DevReq *>(d_reqs), n,
                               reinterpret_cast<const uint32_t *>(d_ws),
                               ctx->tuning.slice_iters ? ctx->tuning.slice_iters : 4096u, refill_mask(ctx), blocks, threads,
-                              ctx->stream);
+                              lds_bytes, ctx->stream);
     if (e == hipSuccess) e = hipEventRecord(ctx->ev[1], ctx->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(ctl.data(), d_ctl, n * sizeof(FlightCtl), hipMemcpyDeviceToHost, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
@@ -1626,6 +1809,7 @@ sdd_status sdd_create(int device, void *workspace_dev, size_t workspace_bytes, v
   ctx->device = device;
   ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
   ctx->cus = prop.multiProcessorCount;
+  ctx->lds_per_block = prop.sharedMemPerBlock;
   const char *dbg = std::getenv("SDD_DEBUG");
   ctx->debug = dbg && dbg[0] == '1';
   ctx->arena.init(reinterpret_cast<char *>(workspace_dev), workspace_bytes);
@@ -2202,7 +2386,8 @@ sdd_status sdd_solve_noalloc(sdd_ctx_t ctx, const sdd_request *req, sdd_result *
   const size_t o_req = take(sizeof(DevReq)), o_ctr = take(sizeof(uint32_t)),
                o_done = take(sizeof(unsigned long long)), o_ws = take(2 * sizeof(uint32_t)),
                o_g = take(P->g.size() * sizeof(double)), o_nodes = take(P->nodes.size() * sizeof(double)),
-               o_grid = take(P->grid.size() * sizeof(SigmaCell)), o_tiles = take(P->tiles.size() * sizeof(DevTile)),
+               o_grid = take(P->grid.size() * sizeof(SigmaCell)), o_ext = take(P->grid_ext.size() * sizeof(SigmaCell)),
+               o_tiles = take(P->tiles.size() * sizeof(DevTile)),
                o_recs = take(P->n_paths * sizeof(PathRec)), o_jobs = take((size_t)n * sizeof(NodeJob)),
                o_out = take((size_t)n * sizeof(NodeOut));
   if (off > scratch_bytes())
@@ -2222,11 +2407,12 @@ sdd_status sdd_solve_noalloc(sdd_ctx_t ctx, const sdd_request *req, sdd_result *
   q.tiles = reinterpret_cast<const DevTile *>(base + o_tiles);
   q.recs = reinterpret_cast<PathRec *>(base + o_recs);
   q.grid = P->grid.empty() ? nullptr : reinterpret_cast<const SigmaCell *>(base + o_grid);
+  q.grid_ext = P->grid_ext.empty() ? nullptr : reinterpret_cast<const SigmaCell *>(base + o_ext);
   q.n_tiles = (uint32_t)P->tiles.size();
   q.tile_counter = reinterpret_cast<uint32_t *>(base + o_ctr);
   q.done_counter = reinterpret_cast<unsigned long long *>(base + o_done);
   uint32_t blocks, threads;
-  launch_shape(ctx, (int)q.precision, q.sig, blocks, threads);
+  launch_shape(ctx, (int)q.precision, q.sig, 0, blocks, threads);
   const uint32_t ws[2] = {0u, blocks * (threads / 64)};
   std::vector<NodeJob> jobs(n);
   for (uint32_t j = 0; j < n; ++j) {
@@ -2243,6 +2429,9 @@ sdd_status sdd_solve_noalloc(sdd_ctx_t ctx, const sdd_request *req, sdd_result *
     e = hipMemcpyAsync(base + o_nodes, P->nodes.data(), P->nodes.size() * sizeof(double), hipMemcpyHostToDevice, s);
   if (e == hipSuccess && !P->grid.empty())
     e = hipMemcpyAsync(base + o_grid, P->grid.data(), P->grid.size() * sizeof(SigmaCell), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !P->grid_ext.empty())
+    e = hipMemcpyAsync(base + o_ext, P->grid_ext.data(), P->grid_ext.size() * sizeof(SigmaCell),
+                       hipMemcpyHostToDevice, s);
   if (e == hipSuccess && !P->tiles.empty())
     e = hipMemcpyAsync(base + o_tiles, P->tiles.data(), P->tiles.size() * sizeof(DevTile), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(base + o_req, &q, sizeof(DevReq), hipMemcpyHostToDevice, s);
@@ -2255,7 +2444,8 @@ sdd_status sdd_solve_noalloc(sdd_ctx_t ctx, const sdd_request *req, sdd_result *
   if (e == hipSuccess) e = hipEventRecord(ctx->ev[0], s);
   if (e == hipSuccess)
     e = launch_walk_persist((int)q.precision, q.sig, reinterpret_cast<const DevReq *>(base + o_req), 1u,
-                            reinterpret_cast<const uint32_t *>(base + o_ws), 0u, refill_mask(ctx), blocks, threads, s);
+                            reinterpret_cast<const uint32_t *>(base + o_ws), 0u, refill_mask(ctx), blocks, threads, 0u,
+                            s);
   if (e == hipSuccess) e = hipEventRecord(ctx->ev[1], s);
   if (e == hipSuccess) e = launch_reduce(reinterpret_cast<const NodeJob *>(base + o_jobs), n, s);
   if (e == hipSuccess) e = hipEventRecord(ctx->ev[2], s);
@@ -2336,7 +2526,7 @@ sdd_status sdd_autotune(sdd_ctx_t ctx, const sdd_request *req, uint32_t sample_p
   s.target_rel_se = 0.0;
   if (!sample_paths) {
     uint32_t b, t;
-    launch_shape(ctx, (int)req->precision, -1, b, t);
+    launch_shape(ctx, (int)req->precision, -1, 0, b, t);
     sample_paths = (uint32_t)std::min<uint64_t>(1u << 24, (4ull * b * t + req->n_nodes - 1) / req->n_nodes);
   }
   std::vector<uint32_t> cnt(req->n_nodes);
@@ -2422,6 +2612,7 @@ struct sdd_batch {
   struct Group {
     int prec;
     int sig = -1;
+    uint32_t lds_bytes = 0;
     std::vector<Prepared *> P;
     char *d_reqs = nullptr, *d_ctr = nullptr, *d_done = nullptr, *d_ws = nullptr;
     uint32_t blocks = 0, threads = 0;
@@ -2501,8 +2692,8 @@ sdd_status sdd_batch_create(sdd_ctx_t ctx, uint32_t n, const sdd_request *reqs, 
       if ((int)b->Ps[i]->dreq.precision == prec) g.P.push_back(b->Ps[i].get());
     if (g.P.empty()) continue;
     const uint32_t m = (uint32_t)g.P.size();
-    g.sig = common_sig(g.P.begin(), g.P.end(), [](const Prepared *P) { return P->dreq.sig; });
-    launch_shape(ctx, prec, g.sig, g.blocks, g.threads);
+    g.sig = launch_sig(g.P.begin(), g.P.end(), [](const Prepared *P) { return P; }, g.lds_bytes);
+    launch_shape(ctx, prec, g.sig, g.lds_bytes, g.blocks, g.threads);
     const uint32_t waves = g.blocks * (g.threads / 64);
     g.d_reqs = ctx->alloc(m * sizeof(DevReq));
     g.d_ctr = ctx->alloc(m * sizeof(uint32_t));
@@ -2518,6 +2709,7 @@ sdd_status sdd_batch_create(sdd_ctx_t ctx, uint32_t n, const sdd_request *reqs, 
     for (auto *P : g.P) total += (double)P->n_paths;
     for (uint32_t i = 0; i < m; ++i) {
       dq[i] = g.P[i]->dreq;
+      if (g.sig == kSigGenericLds) dq[i].sig = kSigGenericLds;
       dq[i].tile_counter = reinterpret_cast<uint32_t *>(g.d_ctr) + i;
       dq[i].done_counter = reinterpret_cast<unsigned long long *>(g.d_done) + i;
       ws[i] = total > 0 ? (uint32_t)std::llround(acc / total * waves) : 0u;
@@ -2570,7 +2762,7 @@ sdd_status sdd_batch_create(sdd_ctx_t ctx, uint32_t n, const sdd_request *reqs, 
     if (e == hipSuccess)
       e = launch_walk_persist(g.prec, g.sig, reinterpret_cast<const DevReq *>(g.d_reqs), (uint32_t)g.P.size(),
                               reinterpret_cast<const uint32_t *>(g.d_ws), 0u, refill_mask(ctx), g.blocks, g.threads,
-                              b->cap);
+                              g.lds_bytes, b->cap);
   if (e == hipSuccess) e = launch_reduce(reinterpret_cast<const NodeJob *>(b->d_jobs), (uint32_t)b->total_nodes, b->cap);
   if (e == hipSuccess && b->total_nodes)
     e = hipMemcpyAsync(b->h_out, b->d_out, b->total_nodes * sizeof(NodeOut), hipMemcpyDeviceToHost, b->cap);

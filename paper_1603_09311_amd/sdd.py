@@ -21,6 +21,7 @@ SDD_E_BUSY, SDD_E_NOTFOUND, SDD_E_TIMEOUT, SDD_E_CANCELLED = -4, -5, -6, -7
 SDD_FP64, SDD_FP32_MIXED = 0, 1
 SDD_FLAG_NO_SIGMA_GRID = 1
 SDD_FLAG_EXIT_NAIVE = 2
+SDD_FLAG_NO_LDS_GRID = 4
 SDD_MAX_REGIONS = 16
 SDD_DIAG_DT_UNRESOLVED = 1
 SDD_NOALLOC_SCRATCH_BYTES = 64 << 20

@@ -360,6 +360,33 @@ def block_in_half_space(freq_hz: float, paths: int = 32768, dt: float = 4e-4, M:
                    name=f"block_f{freq_hz:g}")
 
 
+def multi_body(seed: int = 0, n_boxes: int = 4, n_triangles: int = 2, freq_hz: float = 1.0, paths: int = 16384,
+               dt: float = 4e-4, M: int = 4096, precision: int = FP32_MIXED) -> Problem:
+    """A seeded model of several bodies under air (the walker's generic
+    signature): n_boxes boxes and n_triangles triangles with corners uniform
+    in y in [-5, 5], z in [0.2, 5] skin depths (boxes 0.5-3 wide, 0.3-2 tall),
+    conductivities log-uniform in [0.1, 10] S/m, in a 0.01 S/m half-space; the
+    first body listed wins where bodies overlap.  Nodes: the 128 surface
+    nodes y = -8 + (j + 1/2) / 8, z = 0 (the same as block_in_half_space's
+    surface subset), `paths` paths each."""
+    rng = np.random.default_rng(7_000_003 + seed)
+    regions = [Region(HALF_Z_LT, (0.0,), 0.0)]
+    for _ in range(n_boxes):
+        y0, z0 = rng.uniform(-5, 4), rng.uniform(0.2, 4)
+        regions.append(Region(BOX, (y0, y0 + rng.uniform(0.5, 3), z0, z0 + rng.uniform(0.3, 2)),
+                              float(10 ** rng.uniform(-1, 1))))
+    for _ in range(n_triangles):
+        v = np.stack([rng.uniform(-5, 5, 3), rng.uniform(0.2, 5, 3)], axis=1)
+        regions.append(Region(TRIANGLE, tuple(float(x) for x in v.reshape(-1)), float(10 ** rng.uniform(-1, 1))))
+    g = column_tables(regions, 0.01, QS_WALLS, freq_hz, DELTA1, 0.0, M)
+    j = np.arange(128)
+    nodes = np.stack([-8.0 + (j + 0.5) / 8.0, np.zeros(128)], axis=1)
+    return Problem(*QS_WALLS, regions=regions, sigma_background=0.01, length_unit_m=DELTA1, freq_hz=freq_hz,
+                   alpha_direct=0.0, g=g, nodes=nodes, path_begin=np.zeros(128, np.uint32),
+                   path_count=np.full(128, paths, np.uint32), dt=dt, seed=seed, precision=precision,
+                   name=f"multi_body_{seed}")
+
+
 # COMMEMI 2D-1 geometry of Sec. 4.3, in kilometres: a 2 S/m block 1 km wide
 # and 2 km tall, its top 0.25 km below the surface, in a 0.01 S/m half-space
 # under air; response sites on the surface.

@@ -325,19 +325,33 @@ def multi_body_model(seed, paths=128):
 
 
 def test_sigma_grid_equals_primitive_loop_bitwise(ctx, orc):
-    """FP32-mixed walks on multi-body models: the sigma grid gives every
-    path the record the primitive loop gives, bit for bit; and within 3 SE
-    of the FP64 oracle."""
+    """FP32-mixed walks on multi-body models: the sigma grid staged in LDS
+    (the default for a launch of one grid), the grid read from global memory
+    and the loop over the primitives give every path the same record, bit for
+    bit; a batch of two models with different grids (one launch that cannot
+    stage either in LDS) gives each the same records again; and the results
+    are within 3 SE of the FP64 oracle."""
     for seed in range(6):
         p = multi_body_model(seed)
         log(f"sigma grid: seed {seed}, {len(p.regions)} primitives, {p.n_nodes} nodes")
         a = ctx.solve(p, records=True)
         b = ctx.solve(p, records=True, flags=sdd.SDD_FLAG_NO_SIGMA_GRID)
+        c = ctx.solve(p, records=True, flags=sdd.SDD_FLAG_NO_LDS_GRID)
         assert a["records"].tobytes() == b["records"].tobytes(), seed
-        assert np.array_equal(a["mean"], b["mean"])
+        assert a["records"].tobytes() == c["records"].tobytes(), seed
+        assert np.array_equal(a["mean"], b["mean"]) and np.array_equal(a["mean"], c["mean"])
         if seed < 2:
             o, _ = oracle_solve(orc, p.with_paths(2048))
             assert_within_se(ctx.solve(p.with_paths(2048)), o)
+    p0, p1 = multi_body_model(0), multi_body_model(1)
+    both = ctx.solve_batch([p0, p1], records=True)
+    for p, got in zip((p0, p1), both):
+        assert got["records"].tobytes() == ctx.solve(p, records=True)["records"].tobytes()
+    # the seeded multi-body workload of the benchmark: 6 bodies, 128 surface nodes
+    q = W.multi_body(seed=0, paths=256, M=1024)
+    a = ctx.solve(q, records=True)
+    for fl in (sdd.SDD_FLAG_NO_SIGMA_GRID, sdd.SDD_FLAG_NO_LDS_GRID):
+        assert ctx.solve(q, records=True, flags=fl)["records"].tobytes() == a["records"].tobytes()
 
 
 def test_batch_equals_alone_bitwise(ctx):
@@ -532,8 +546,13 @@ def test_served_time_slices_are_exact(ctx):
         tickets = [ctx.submit(p, records=True) for p in ps[:4]]
         tickets.append(ctx.submit(ps[4], target_rel_se=2e-2))
         got = [ctx.wait(t, timeout_s=100) for t in tickets]
+        # generic-signature walkers (64-bit phase sums) suspended and resumed
+        # in slices of the LDS-grid walker (the flight's launches hold one grid)
+        gen = W.multi_body(seed=3, paths=64, M=1024).subset(np.arange(0, 128, 8))
+        g_served = ctx.wait(ctx.submit(gen, records=True), timeout_s=100)
     finally:
         ctx.set_tuning()
+    assert g_served["records"].tobytes() == ctx.solve(gen, records=True)["records"].tobytes()
     for p, r in zip(ps[:4], got[:4]):
         alone = ctx.solve(p, records=True)
         assert r["records"].tobytes() == alone["records"].tobytes()
