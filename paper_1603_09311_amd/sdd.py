@@ -113,6 +113,9 @@ _PROTOS = [
     ("sdd_mt_te_response", C.c_int, [C.c_uint32, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                      C.POINTER(C.c_double), C.c_double, C.c_double, C.c_double,
                                      C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    ("sdd_mt_te_response_jump", C.c_int, [C.c_uint32, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                          C.POINTER(C.c_double), C.c_double, C.c_double, C.c_double, C.c_double,
+                                          C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     ("sdd_rbffd_solve", C.c_int, [C.c_uint32, C.c_uint32, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                   C.c_double, C.c_double, C.POINTER(C.c_double)]),
     ("sdd_rbffd_weights", C.c_int, [C.c_uint32, C.c_uint32, C.POINTER(C.c_double), C.POINTER(C.c_double),
@@ -148,6 +151,11 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build the HIP library first "
                                "(python -m paper_1603_09311_amd.build)")
+        # torch first: the library then binds to the HIP runtime torch has
+        # loaded (same sonames).  Loaded the other way round, the process
+        # holds two HIP runtimes and the library's sees no device once torch
+        # has opened it.
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         for name, res, args in _PROTOS:
             f = getattr(L, name)
@@ -257,9 +265,13 @@ class _Res:
         return d
 
 
-def mt_te_response(e_minus, e_mid, e_plus, h: float, length_unit_m: float, freq_hz: float):
+def mt_te_response(e_minus, e_mid, e_plus, h: float, length_unit_m: float, freq_hz: float,
+                   sigma_jump: float = 0.0):
     """TE apparent resistivity (ohm m) and phase (degrees) per site from the
-    complex field at z - h, z, z + h (sdd_mt_te_response)."""
+    complex field at z - h, z, z + h (sdd_mt_te_response); with sigma_jump
+    (S/m, the conductivity below the site less the one above) the
+    first-order term of a jump between the points is removed
+    (sdd_mt_te_response_jump)."""
     arrs = [np.ascontiguousarray(np.stack([np.asarray(e).real, np.asarray(e).imag], axis=-1), dtype=np.float64)
             for e in (e_minus, e_mid, e_plus)]
     n = arrs[0].shape[0]
@@ -267,8 +279,13 @@ def mt_te_response(e_minus, e_mid, e_plus, h: float, length_unit_m: float, freq_
         raise ValueError("three arrays of the same length")
     rho = np.zeros(max(n, 1))
     phi = np.zeros(max(n, 1))
-    _check(lib().sdd_mt_te_response(n, *[_ptr(a, C.c_double) for a in arrs], h, length_unit_m, freq_hz,
-                                    _ptr(rho, C.c_double), _ptr(phi, C.c_double)))
+    ptrs = [_ptr(a, C.c_double) for a in arrs]
+    if sigma_jump == 0.0:
+        _check(lib().sdd_mt_te_response(n, *ptrs, h, length_unit_m, freq_hz,
+                                        _ptr(rho, C.c_double), _ptr(phi, C.c_double)))
+    else:
+        _check(lib().sdd_mt_te_response_jump(n, *ptrs, h, length_unit_m, freq_hz, sigma_jump,
+                                             _ptr(rho, C.c_double), _ptr(phi, C.c_double)))
     return rho[:n], phi[:n]
 
 
