@@ -1935,18 +1935,24 @@ sdd_status sdd_solve_batch(sdd_ctx_t ctx, uint32_t n, const sdd_request *reqs, s
   return st;
 }
 
-sdd_status sdd_mt_te_response(uint32_t n, const double *e_minus, const double *e_mid, const double *e_plus, double h,
-                              double length_unit_m, double freq_hz, double *rho_a, double *phase_deg) {
+// H^x from the centred difference, less the first-order term of a jump of
+// sigma between the outer points (zero inside one layer).
+static sdd_status mt_te(uint32_t n, const double *e_minus, const double *e_mid, const double *e_plus, double h,
+                        double length_unit_m, double freq_hz, double sigma_jump, double *rho_a, double *phase_deg) {
   if (n && (!e_minus || !e_mid || !e_plus || !rho_a || !phase_deg)) return fail(SDD_E_INVALID, "NULL array");
   if (!(h > 0.0) || !(length_unit_m > 0.0) || !(freq_hz > 0.0))
     return fail(SDD_E_INVALID, "h, length unit and frequency must be positive");
+  if (!std::isfinite(sigma_jump)) return fail(SDD_E_INVALID, "sigma_jump must be finite");
   const double pi = 3.14159265358979323846;
   const double wmu = 2.0 * pi * freq_hz * (4e-7 * pi);
+  const double hm = h * length_unit_m;
+  const std::complex<double> kink(0.0, 0.25 * hm * wmu * sigma_jump);   // (h L / 4) i omega mu0 sigma_jump
   for (uint32_t j = 0; j < n; ++j) {
     const std::complex<double> em(e_minus[2 * j], e_minus[2 * j + 1]);
     const std::complex<double> e0(e_mid[2 * j], e_mid[2 * j + 1]);
     const std::complex<double> ep(e_plus[2 * j], e_plus[2 * j + 1]);
-    const std::complex<double> dedz = (ep - em) / (2.0 * h * length_unit_m);   // per metre
+    std::complex<double> dedz = (ep - em) / (2.0 * hm);   // per metre
+    if (sigma_jump != 0.0) dedz -= kink * e0;
     const std::complex<double> hx = -dedz / std::complex<double>(0.0, wmu);
     if (hx == std::complex<double>(0.0, 0.0)) {
       rho_a[j] = HUGE_VAL;
@@ -1958,6 +1964,17 @@ sdd_status sdd_mt_te_response(uint32_t n, const double *e_minus, const double *e
     phase_deg[j] = std::arg(z) * (180.0 / pi);
   }
   return SDD_OK;
+}
+
+sdd_status sdd_mt_te_response(uint32_t n, const double *e_minus, const double *e_mid, const double *e_plus, double h,
+                              double length_unit_m, double freq_hz, double *rho_a, double *phase_deg) {
+  return mt_te(n, e_minus, e_mid, e_plus, h, length_unit_m, freq_hz, 0.0, rho_a, phase_deg);
+}
+
+sdd_status sdd_mt_te_response_jump(uint32_t n, const double *e_minus, const double *e_mid, const double *e_plus,
+                                   double h, double length_unit_m, double freq_hz, double sigma_jump, double *rho_a,
+                                   double *phase_deg) {
+  return mt_te(n, e_minus, e_mid, e_plus, h, length_unit_m, freq_hz, sigma_jump, rho_a, phase_deg);
 }
 
 sdd_status sdd_solve_multi_freq(sdd_ctx_t ctx, const sdd_request *req, uint32_t n_freq, const double *freqs,

@@ -392,24 +392,29 @@ def multi_body(seed: int = 0, n_boxes: int = 4, n_triangles: int = 2, freq_hz: f
 # under air; response sites on the surface.
 COMMEMI_SITES_KM = (0.0, 0.5, 1.0, 2.0, 4.0)
 COMMEMI_WALLS = (-10.0, 10.0, -5.0, 10.0)
+# point spacing h per site for the surface-jump-corrected difference: below
+# the block's top (0.25 km) over the block, wider away from it
+COMMEMI_H_KM = (0.1, 0.1, 0.2, 0.4, 0.4)
 
 
-def commemi_te_points(freq_hz: float = 10.0, paths: int = 65536, h: float = 0.01, dt: float = 1e-4,
+def commemi_te_points(freq_hz: float = 10.0, paths: int = 65536, h=0.01, dt: float = 1e-4,
                       sites=COMMEMI_SITES_KM, walls=COMMEMI_WALLS, M: int = 16384, seed: int = 0,
                       precision: int = FP32_MIXED, block: bool = True) -> List[Problem]:
-    """Three problems whose node j is site j at depth -h, 0 and +h (z down):
-    the field there gives the TE response of the site by a centred
-    difference.  The three share seed, stream and node order, so the three
-    points of a site walk on the same random numbers.  block=False gives the
-    plain half-space (apparent resistivity 100 ohm m, phase 45 degrees)."""
+    """Three problems whose node j is site j at depth -h_j, 0 and +h_j (z
+    down; h one spacing for all sites or one per site): the field there gives
+    the TE response of the site by a centred difference.  The three share
+    seed, stream and node order, so the three points of a site walk on the
+    same random numbers.  block=False gives the plain half-space (apparent
+    resistivity 100 ohm m, phase 45 degrees)."""
     regions = [Region(HALF_Z_LT, (0.0,), 0.0)]
     if block:
         regions.append(Region(BOX, (-0.5, 0.5, 0.25, 2.25), 2.0))
     g = column_tables(regions, 0.01, walls, freq_hz, 1000.0, 0.0, M)
     ys = np.asarray(sites, dtype=np.float64)
+    hs = np.broadcast_to(np.asarray(h, dtype=np.float64), ys.shape)
     out = []
-    for dz, tag in ((-h, "minus"), (0.0, "mid"), (h, "plus")):
-        nodes = np.stack([ys, np.full(ys.size, dz)], axis=1)
+    for sgn, tag in ((-1.0, "minus"), (0.0, "mid"), (1.0, "plus")):
+        nodes = np.stack([ys, sgn * hs], axis=1)
         n = nodes.shape[0]
         out.append(Problem(*walls, regions=regions, sigma_background=0.01, length_unit_m=1000.0,
                            freq_hz=freq_hz, alpha_direct=0.0, g=g, nodes=nodes,

@@ -104,6 +104,20 @@ def mt_te_response(e_minus, e_mid, e_plus, h, length_unit_m, freq_hz):
     return np.abs(z) ** 2 / (w * MU0), np.degrees(np.angle(z))
 
 
+def mt_te_response_jump(e_minus, e_mid, e_plus, h, length_unit_m, freq_hz, sigma_jump):
+    """mt_te_response across a horizontal jump of sigma (below minus above)
+    between the outer points: d2E/dz2 jumps by i omega mu0 sigma_jump E
+    there, which puts (h L / 4) i omega mu0 sigma_jump E(z) into the centred
+    difference; that term is taken out of dE/dz."""
+    w = 2.0 * np.pi * freq_hz
+    hm = h * length_unit_m
+    e0 = np.asarray(e_mid)
+    dedz = (np.asarray(e_plus) - np.asarray(e_minus)) / (2.0 * hm) - 0.25 * hm * 1j * w * MU0 * sigma_jump * e0
+    hx = -dedz / (1j * w * MU0)
+    z = e0 / hx
+    return np.abs(z) ** 2 / (w * MU0), np.degrees(np.angle(z))
+
+
 def kappa_two_sided(lam, kappa, y, z, y_if=0.0):
     """(1/2) div(kappa grad u) - lam_i u = 0 with kappa_i, lam_i constant on
     the sides y < y_if (i = 0) and y >= y_if (i = 1): u = (z + 1) f(y) with

@@ -767,24 +767,45 @@ def test_mt_response_half_space_physics(ctx):
     assert np.all(np.abs(rho - 100.0) < 12.0) and np.all(np.abs(phi - 45.0) < 2.5)
 
 
+def _surface_jump_bias(h_km):
+    """|rho_a / 100 - 1| of the jump-corrected difference on the exact
+    half-space (0.01 S/m under air, 10 Hz) at spacing h: its own bias."""
+    al = W._alpha_of(np.array([0.0, 0.01]), 10.0, 1000.0, 0.0)
+    e = W.layered_1d(np.array([W.COMMEMI_WALLS[2], 0.0]), al, np.array([-h_km, 0.0, h_km]))
+    rho, _ = sdd.mt_te_response(*[np.atleast_1d(x) for x in e], h_km, 1000.0, 10.0, sigma_jump=0.01)
+    return abs(rho[0] / 100.0 - 1.0)
+
+
 def test_mt_response_commemi_within_table2(ctx):
     """TE apparent resistivity of COMMEMI 2D-1 at 10 Hz at the five sites of
-    Sec. 4.3 from the FP32 walk (four independent seeds of 2^20 paths per
-    point, h = 50 m) lies inside the COMMEMI spread of Table 2 widened by the
-    Monte-Carlo error of the four-seed mean (99% two-sided Student t with
-    three degrees of freedom times the seed spread over 2)."""
+    Sec. 4.3 (Table 2) from the FP32 walk: 16 independent seeds of 2^19 paths
+    per point, the points h = 100 m above and below the surface at the two
+    sites over the block (its top is 250 m down), 200 m at 1 km and 400 m at
+    2 and 4 km, and the surface jump's first-order term removed from the
+    difference (sdd_mt_te_response_jump).  The 16-seed mean lies inside the
+    COMMEMI spread widened by its Monte-Carlo error (99% two-sided Student t,
+    15 degrees of freedom, times the seed spread over 4) and by the
+    difference's own bias on the exact half-space at the same h (at most
+    0.13%).  At 2 and 4 km the Monte-Carlo part alone is narrower than the
+    COMMEMI spread."""
     tab = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "commemi_te_table2.txt"))
     assert np.allclose(tab[:, 0], 1000.0 * np.asarray(W.COMMEMI_SITES_KM))
+    H = np.asarray(W.COMMEMI_H_KM)
+    n_seeds = 16
     rhos = []
-    for seed in range(4):
-        ps = W.commemi_te_points(paths=1 << 20, seed=seed, dt=4e-4, h=0.05)
-        got = ctx.solve_batch(ps)
-        rho, _ = sdd.mt_te_response(*[g["mean"] for g in got], 0.05, 1000.0, 10.0)
-        rhos.append(rho)
+    for seed in range(n_seeds):
+        em, e0, ep = [g["mean"] for g in ctx.solve_batch(W.commemi_te_points(paths=1 << 19, seed=seed, dt=4e-4,
+                                                                                h=H))]
+        rhos.append([sdd.mt_te_response(em[j:j + 1], e0[j:j + 1], ep[j:j + 1], H[j], 1000.0, 10.0,
+                                        sigma_jump=0.01)[0][0] for j in range(H.size)])
     rhos = np.array(rhos)
     mean, sd = rhos.mean(0), rhos.std(0, ddof=1)
-    allow = tab[:, 2] + stats.t.ppf(0.995, 3) * sd / 2.0
-    log(f"COMMEMI rho_a {mean.round(2)} sd {sd.round(2)}; Table 2 {tab[:, 1]} +- {tab[:, 2]}")
+    mc = stats.t.ppf(0.995, n_seeds - 1) * sd / math.sqrt(n_seeds)
+    bias = np.array([_surface_jump_bias(h) for h in H]) * tab[:, 1]
+    allow = tab[:, 2] + mc + bias
+    log(f"COMMEMI rho_a {mean.round(2)} sd {sd.round(2)} MC allowance {mc.round(2)} bias {bias.round(3)}; "
+        f"Table 2 {tab[:, 1]} +- {tab[:, 2]}")
+    assert np.all(mc[3:] <= tab[3:, 2]), mc
     assert np.all(np.abs(mean - tab[:, 1]) <= allow), (mean - tab[:, 1]) / allow
 
 
