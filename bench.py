@@ -140,13 +140,23 @@ def fp32_vs_fp64(r32, r64):
 
 
 def cpu_model() -> str:
+    """The host CPU's model name with its family and model numbers (which
+    name the generation where the name alone does not)."""
+    info = {}
     try:
         for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
+            if ":" in line:
+                k, v = (x.strip() for x in line.split(":", 1))
+                if k in ("model name", "cpu family", "model") and k not in info:
+                    info[k] = v
+            elif info:
+                break
     except OSError:
         pass
-    return "unknown"
+    name = info.get("model name", "unknown")
+    if "cpu family" in info and "model" in info:
+        name += f" (family {info['cpu family']}, model {info['model']})"
+    return name
 
 
 def cpu_baseline(p, budget_s: float = 15.0):
