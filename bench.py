@@ -299,6 +299,14 @@ def _served_run(ctx, trace, target, deadline_s, tag=""):
     return [done_at[i] for i in range(len(trace))], [res[i] for i in range(len(trace))], wall
 
 
+def _busy(s0, s1, wall):
+    """GPU-busy share of a served run: the walk kernels' summed time (HIP
+    events around each slice) over the run's wall time."""
+    ms = s1["served_walk_ms"] - s0["served_walk_ms"]
+    n = s1["served_slices"] - s0["served_slices"]
+    return {"slices": int(n), "slice_ms_mean": ms / n if n else None, "gpu_busy_fraction": ms * 1e-3 / wall}
+
+
 def _fifo_run(ctx, trace, solve, budget=None, tag=""):
     """Blocking solves in arrival order (one launch sequence per request);
     stops starting requests once `budget` seconds have passed."""
@@ -338,14 +346,18 @@ def served_leg(ctx, n_requests: int = 200, warm: int = 40, target: float = 1e-3,
     from paper_1603_09311_amd import workloads as W
     base = W.served_trace(n_requests, 1.0, seed=1, node_range=node_range)
     warm_trace = W.served_trace(warm, 1.0, seed=2, node_range=node_range)
+    s0 = ctx.stats()
     t0 = time.perf_counter()
     tks = [ctx.submit(p, target_rel_se=target) for _, p in warm_trace]
+    res_w = []
     for i, tk in enumerate(tks):
-        ctx.wait(tk, timeout_s=120)
+        res_w.append(ctx.wait(tk, timeout_s=120))
         if i % 10 == 9:
             _progress(f"saturation run: {i + 1} of {warm} done, {time.perf_counter() - t0:.1f} s")
     sat_wall = time.perf_counter() - t0
     sat = warm / sat_wall
+    sat_busy = _busy(s0, ctx.stats(), sat_wall)
+    sat_busy["walk_steps_per_s"] = float(sum(r["steps"].sum() for r in res_w)) / sat_wall
     _progress(f"closed-loop saturation {sat:.2f} requests/s ({warm} requests, {sat_wall:.1f} s)")
     kinds = {}
     for _, p in base:
@@ -353,11 +365,13 @@ def served_leg(ctx, n_requests: int = 200, warm: int = 40, target: float = 1e-3,
         kinds[k] = kinds.get(k, 0) + 1
     out = {"requests": n_requests, "target_se_over_gnorm": target, "node_range_quarter_space_block": list(node_range),
            "families": kinds, "nodes": int(sum(p.n_nodes for _, p in base)),
-           "saturation": {"requests": warm, "wall_s": sat_wall, "requests_per_s": sat}}
+           "saturation": {"requests": warm, "wall_s": sat_wall, "requests_per_s": sat, **sat_busy}}
     for frac in (0.5, 0.8):
         rate = frac * sat
         trace = [(t / rate, p) for t, p in base]
+        s0 = ctx.stats()
         got = _served_run(ctx, trace, target, deadline_s=2.5 * n_requests / rate + 30.0, tag=f"{frac:g}")
+        s1 = ctx.stats()
         if got is None:
             out[f"rate_{frac:g}_of_saturation"] = {"rate_hz": rate, "incomplete": True}
             continue
@@ -368,7 +382,7 @@ def served_leg(ctx, n_requests: int = 200, warm: int = 40, target: float = 1e-3,
         served.update({"nodes_per_s": out["nodes"] / wall, "walk_steps": steps, "walk_steps_per_s": steps / wall,
                        "paths_per_node_median": float(np.median(np.concatenate([r["paths_done"] for r in res]))),
                        "se_over_gnorm_max": float(max(r["diag"]["se_over_gnorm"] for r in res)),
-                       "time_step": diag_of(res)})
+                       "time_step": diag_of(res), **_busy(s0, s1, wall)})
         flat, fres, fwall = _fifo_run(ctx, trace, lambda p: ctx.solve(p, target_rel_se=target),
                                       budget=2.5 * n_requests / rate + 30.0, tag=f"{frac:g}")
         _progress(f"fifo at {frac:g} of saturation: {fwall:.1f} s, {len(flat)} requests")

@@ -283,6 +283,9 @@ typedef struct {
                                        others: they gave their workspace back and were walked again
                                        in one pass, all paths, once admitted (same results) */
     uint32_t reserved;
+    double served_walk_ms;          /* walk kernel time of every served slice so far (HIP events),
+                                       for the GPU-busy fraction of a served stream */
+    uint64_t served_slices;         /* served slices launched so far */
 } sdd_stats;
 
 sdd_status sdd_get_stats(sdd_ctx_t ctx, sdd_stats *out);

@@ -227,6 +227,8 @@ struct sdd_ctx {
   uint64_t held_long = 0;          // workspace held by resident models and prepared batches
   uint64_t reserved = 0;           // workspace promised to served flights
   uint32_t served_in_flight_max = 0, served_waits = 0, served_requeues = 0;
+  double served_walk_ms = 0.0;     // summed slice times (worker thread only)
+  uint64_t served_slices = 0;
   std::unordered_map<uint32_t, std::unique_ptr<HostModel>> models;
   uint32_t next_model = 1;
   // served mode
@@ -1456,6 +1458,11 @@ static sdd_status run_slice(sdd_ctx *ctx, std::vector<Flight *> &fl, int precisi
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]) == hipSuccess) ctx->stats.last_walk_ms = ms;
   ctx->stats.launches += 1;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->served_walk_ms += ms;
+    ctx->served_slices += 1;
+  }
   for (uint32_t i = 0; i < n; ++i) {
     Flight &F = *fl[i];
     const FlightCtl &c = ctl[i];
@@ -2523,6 +2530,8 @@ sdd_status sdd_get_stats(sdd_ctx_t ctx, sdd_stats *out) {
   out->served_in_flight_max = ctx->served_in_flight_max;
   out->served_waits = ctx->served_waits;
   out->served_requeues = ctx->served_requeues;
+  out->served_walk_ms = ctx->served_walk_ms;
+  out->served_slices = ctx->served_slices;
   return SDD_OK;
 }
 

@@ -97,7 +97,8 @@ class sdd_stats(C.Structure):
     _fields_ = [("last_walk_ms", C.c_double), ("last_reduce_ms", C.c_double), ("last_walk_steps", C.c_uint64),
                 ("last_walk_paths", C.c_uint64), ("last_blocks", C.c_uint32), ("last_threads", C.c_uint32),
                 ("launches", C.c_uint64), ("served_in_flight_max", C.c_uint32), ("served_waits", C.c_uint32),
-                ("served_requeues", C.c_uint32), ("reserved", C.c_uint32)]
+                ("served_requeues", C.c_uint32), ("reserved", C.c_uint32), ("served_walk_ms", C.c_double),
+                ("served_slices", C.c_uint64)]
 
 
 # (name, restype, argtypes) of every entry point in include/sdd.h
