@@ -61,6 +61,7 @@ METRIC = "walk-steps/s + interface nodes/s at 1e-3 rel. MC error; p50/p99 reques
 # lane-operations per second (the issue peak of a VALU-bound kernel).
 CUS, SIMDS, LANES, CLOCK = 256, 4, 16, 2.4e9
 VALU_PEAK = CUS * SIMDS * LANES * CLOCK
+FP32_VECTOR_PEAK_TF = 157.3   # MI355X FP32 vector peak (packed FMA), TFLOP/s
 
 # Algorithmic VALU work of one FP32-mixed walk step on the quarter-space
 # model: every operation the method needs, each in its cheapest gfx950
@@ -97,17 +98,23 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload: str):
-    """HBM bytes per walk launch from the committed rocprofv3 counter runs,
-    valid only for the kernel source they were taken with."""
+def load_counters(workload: str) -> dict:
+    """The committed rocprofv3 counter figures of the walker (HBM bytes per
+    launch, FP32 operations per walk-step), valid only for the kernel source
+    they were taken with: empty otherwise."""
     path = os.path.join(ROOT, "profiles", f"walk_persist_{workload}_counters.json")
     if not os.path.exists(path):
-        return None
+        return {}
     with open(path) as fh:
         d = json.load(fh)
     if d.get("kernel_source_sha") != kernel_source_hash():
-        return None
-    return d.get("traffic_bytes_per_launch")
+        return {}
+    return d
+
+
+def load_traffic(workload: str):
+    """HBM bytes per walk launch (load_counters), or None."""
+    return load_counters(workload).get("traffic_bytes_per_launch")
 
 
 def diag_of(results):
@@ -784,6 +791,13 @@ def main():
     out["launch"] = {"blocks": st["last_blocks"], "threads": st["last_threads"]}
     if out["roofline"]["traffic"] is not None:
         out["hbm_gb_per_s"] = out["roofline"]["traffic"] / (walk_ms * 1e-3) / 1e9
+    fl = load_counters("quarter_space").get("fp32_flops_per_walk_step")
+    if fl is not None:
+        # the FP32 vector peak's own measure: FP32 operations per walk-step
+        # counted by rocprofv3 (2 per FMA, 1 per add, multiply, transcendental)
+        tf = fl * steps_per_solve / (walk_ms * 1e-3) / 1e12
+        out["fp32_vector"] = {"flops_per_walk_step": fl, "achieved_tflops": tf, "peak_tflops": FP32_VECTOR_PEAK_TF,
+                              "frac": tf / FP32_VECTOR_PEAK_TF}
 
     if not args.no_fp64 and prec == W.FP32_MIXED:
         out["fp64_full_size"] = fp64_full_leg(ctx, args.paths, res)
