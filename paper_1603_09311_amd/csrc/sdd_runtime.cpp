@@ -2478,7 +2478,12 @@ sdd_status sdd_solve_noalloc(sdd_ctx_t ctx, const sdd_request *req, sdd_result *
   if (e == hipSuccess && res->path_records && P->n_paths)
     e = hipMemcpyAsync(res->path_records, base + o_recs, P->n_paths * sizeof(PathRec), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return fail(SDD_E_DEVICE, "sdd_solve_noalloc: %s", hipGetErrorString(e));
+  if (e != hipSuccess) {
+    // work queued before the failing call may still use the scratch: let it
+    // drain before the lock is released
+    (void)hipStreamSynchronize(s);
+    return fail(SDD_E_DEVICE, "sdd_solve_noalloc: %s", hipGetErrorString(e));
+  }
   if (done != P->n_paths)
     return fail(SDD_E_DEVICE, "%llu of %llu paths completed", done, (unsigned long long)P->n_paths);
   float ms = 0.f, rms = 0.f;
