@@ -11,6 +11,7 @@ namespace sdd {
 
 constexpr int kMaxPrims = 16;                 // conductivity primitives per model
 constexpr int kMaxRegions = kMaxPrims + 1;    // + background
+constexpr int kPfStride = 12;                 // FP32 parameters per primitive (DevReq::pf)
 constexpr uint32_t kNoRequest = 0xFFFFFFFFu;
 
 enum PrimKind : int32_t { kHalfZ = 0, kHalfY = 1, kBox = 2, kTriangle = 3 };
@@ -97,26 +98,30 @@ struct FanJob {
 // One cell of the sigma grid of the FP32 walk's generic signature (32 B):
 // the phase increment of a full step ending at a point (a, b) of the cell
 // (fixed point: units of 2^-phase_shift) is inc_ge if the edge function
-//   e = dy (b - v1) - dz (a - v0)
-// is >= 0, else inc_lt.  e is evaluated in FP32 in the primitive loop's own
-// expression, or negated (dy, dz negated: the FP32 result is exactly -e), so
-// that each of the loop's tests (e < 0, e >= 0, e <= 0) reads "e >= 0" with
-// the two increments in the right order.  A pure cell has a zero line (e is
-// +-0) and equal increments.  A cell whose primitives test two lines has bit
-// 30 of inc_ge set (kCellTwo; increments are below 2^30): its increment is
-// inc_ge or inc_lt when e2 < 0 and the extension entry's inc_ge (e >= 0) or
-// inc_lt (e < 0) when e2 >= 0, e2 the extension entry's line; pad[0] is the
-// extension's index.  A cell with more lines has bit 31 set (kCellLoop): its
-// points take the primitive loop.  The LDS form of a grid stores each
-// distinct cell once (a class table of at most 255 SigmaCells, then the
-// extension entries) and one class byte per cell.
+//   e = fma(A, a, fma(B, b, C))   (FP32)
+// is >= 0, else inc_lt.  Lines are the primitive loop's own: a box side or
+// half-plane a < y0 reads A = 1, B = 0, C = -y0 (e = a - y0 rounded once, so
+// its sign is the compare's), a triangle edge its (A, B, C) from DevReq::pf.
+// A line is negated (A, B, C negated: the FP32 result is exactly -e) or its
+// increments swapped so that each of the loop's tests (e < 0, e >= 0,
+// e <= 0) reads "e >= 0" with the two increments in the right order.  A pure
+// cell has A = B = C = 0 (e = +0) and equal increments.  A cell whose
+// primitives test two lines has bit 30 of inc_ge set (kCellTwo; increments
+// are below 2^30): its increment is inc_ge or inc_lt when e2 < 0 and the
+// extension entry's inc_ge (e >= 0) or inc_lt (e < 0) when e2 >= 0, e2 the
+// extension entry's line; xi is the extension's index.  A cell with more
+// lines has bit 31 set (kCellLoop): its points take the primitive loop.  The
+// LDS form of a grid stores one class byte per cell, then each distinct cell
+// once (a class table of at most 255 SigmaCells, then the extension
+// entries).
 constexpr uint32_t kCellLoop = 0x80000000u;
 constexpr uint32_t kCellTwo = 0x40000000u;
 constexpr uint32_t kCellFlags = kCellLoop | kCellTwo;
 constexpr uint32_t kMaxLdsClasses = 255;
 struct SigmaCell {
   uint32_t inc_ge, inc_lt;
-  float v0, v1, dy, dz;
+  float A, B, C;
+  uint32_t xi;
   uint32_t pad[2];
 };
 
@@ -173,7 +178,10 @@ struct DevReq {
   uint32_t nprims;
   int32_t kind[kMaxPrims];
   double pd[kMaxPrims][6];    // FP64 geometry of the model's primitives
-  float pf[kMaxPrims][8];     // FP32 geometry relative to the centre, padded to 8
+  // FP32 geometry relative to the centre in units of K: half-plane [c], box
+  // [y0, y1, z0, z1], triangle its three edges as (A, B, C), edge k from
+  // vertex k to vertex k + 1: e = fma(A, a, fma(B, b, C))
+  float pf[kMaxPrims][kPfStride];
   const DevModel *model;      // resident model the primitives were taken from
   // sigma grid of the FP32 generic signature (null: the primitive loop); cell
   // (i, j) = (trunc(a gsy + goy), trunc(b gsz + goz)) clamped, at grid[j gy + i]
@@ -182,10 +190,11 @@ struct DevReq {
   uint32_t gy, gz;
   float gsy, goy, gsz, goz;
   float gmy, gmz;       // gy - 1, gz - 1: the cell index clamped in FP32
-  // the grid's LDS form (kSigGenericLds): lds_classes SigmaCells, then gy gz
-  // class bytes, lds_bytes in all (a multiple of 16)
+  // the grid's LDS form (kSigGenericLds): gy gz class bytes, then from byte
+  // lds_table (a multiple of 16) the class table of SigmaCells; lds_bytes in
+  // all (a multiple of 16)
   const uint8_t *lds_src;
-  uint32_t lds_bytes, lds_classes;
+  uint32_t lds_bytes, lds_table;
   const double *nodes;  // n x (y, z)
   const double *g;      // 4 x (M + 1) x (re, im)
   const DevTile *tiles;

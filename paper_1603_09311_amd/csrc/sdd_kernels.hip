@@ -92,6 +92,25 @@ template <class R> struct ExitInfo {
 // Primitives in list order, the first match wins, else the background.
 // ---------------------------------------------------------------------------
 
+// Closed triangle: every edge function >= 0 or every one <= 0 (either
+// orientation).  FP64: the edge functions from the vertices (the plain
+// definition); FP32: edge k from its (A, B, C), e = fma(A, y, fma(B, z, C)),
+// the expression the sigma grid's lines use.
+template <class R>
+__device__ __forceinline__ bool tri_in(const R *v, R y, R z) {
+  R e0, e1, e2;
+  if constexpr (sizeof(R) == 8) {
+    e0 = (v[2] - v[0]) * (z - v[1]) - (v[3] - v[1]) * (y - v[0]);
+    e1 = (v[4] - v[2]) * (z - v[3]) - (v[5] - v[3]) * (y - v[2]);
+    e2 = (v[0] - v[4]) * (z - v[5]) - (v[1] - v[5]) * (y - v[4]);
+  } else {
+    e0 = __builtin_fmaf(v[0], y, __builtin_fmaf(v[1], z, v[2]));
+    e1 = __builtin_fmaf(v[3], y, __builtin_fmaf(v[4], z, v[5]));
+    e2 = __builtin_fmaf(v[6], y, __builtin_fmaf(v[7], z, v[8]));
+  }
+  return ((e0 >= R(0)) & (e1 >= R(0)) & (e2 >= R(0))) | ((e0 <= R(0)) & (e1 <= R(0)) & (e2 <= R(0)));
+}
+
 // Generic: loop over the primitives (kinds and parameters wave-uniform);
 // cv[k] is the value of region k (an FP64 rate, or a fixed-point increment).
 template <class R, int STRIDE, class V>
@@ -108,10 +127,7 @@ __device__ __forceinline__ V region_c_generic(int np, const int32_t *kind, const
     } else if (kd == kBox) {
       in = (y >= v[0]) & (y < v[1]) & (z >= v[2]) & (z < v[3]);
     } else {
-      const R e0 = (v[2] - v[0]) * (z - v[1]) - (v[3] - v[1]) * (y - v[0]);
-      const R e1 = (v[4] - v[2]) * (z - v[3]) - (v[5] - v[3]) * (y - v[2]);
-      const R e2 = (v[0] - v[4]) * (z - v[5]) - (v[1] - v[5]) * (y - v[4]);
-      in = ((e0 >= R(0)) & (e1 >= R(0)) & (e2 >= R(0))) | ((e0 <= R(0)) & (e1 <= R(0)) & (e2 <= R(0)));
+      in = tri_in<R>(v, y, z);
     }
     c = in ? cv[k] : c;
   }
@@ -182,20 +198,23 @@ __device__ __forceinline__ int region_index_generic(int np, const int32_t *kind,
     } else if (kd == kBox) {
       in = (y >= v[0]) & (y < v[1]) & (z >= v[2]) & (z < v[3]);
     } else {
-      const R e0 = (v[2] - v[0]) * (z - v[1]) - (v[3] - v[1]) * (y - v[0]);
-      const R e1 = (v[4] - v[2]) * (z - v[3]) - (v[5] - v[3]) * (y - v[2]);
-      const R e2 = (v[0] - v[4]) * (z - v[5]) - (v[1] - v[5]) * (y - v[4]);
-      in = ((e0 >= R(0)) & (e1 >= R(0)) & (e2 >= R(0))) | ((e0 <= R(0)) & (e1 <= R(0)) & (e2 <= R(0)));
+      in = tri_in<R>(v, y, z);
     }
     idx = in ? k : idx;
   }
   return idx;
 }
 
-// The LDS form of the sigma grid (kSigGenericLds): the class table (SigmaCells)
-// followed by one class byte per cell, staged by each block at the start of
-// the launch.
+// The LDS form of the sigma grid (kSigGenericLds): one class byte per cell,
+// then the class table (SigmaCells), staged by each block at the start of the
+// launch.
 extern __shared__ __attribute__((aligned(16))) uint8_t g_lds[];
+
+// The primitive loop for the sigma grid's few cells crossed by more than two
+// boundaries, out of line so that its registers stay out of the walker loop.
+__device__ __noinline__ uint32_t loop_fallback(const DevReq &Q, float a, float b) {
+  return region_c_generic<float, kPfStride>((int)Q.nprims, Q.kind, &Q.pf[0][0], Q.cfx, a, b);
+}
 
 // FP32 region tests in centred coordinates; the triangle as three linear
 // forms.  The specialised signatures have at most three regions: primitive 0
@@ -213,7 +232,7 @@ template <int SIG> struct Reg32 {
   float p[10];
   // generic signature: the sigma grid
   const SigmaCell *grid, *grid_ext;
-  uint32_t gy, lds_classes;
+  uint32_t gy, lds_table;
   float gsy, goy, gsz, goz, gmy, gmz;
   __device__ __forceinline__ void load(const DevReq &Q) {
     if constexpr (kGeneric) {
@@ -222,7 +241,7 @@ template <int SIG> struct Reg32 {
       gy = Q.gy;
       gsy = Q.gsy; goy = Q.goy; gsz = Q.gsz; goz = Q.goz;
       gmy = Q.gmy; gmz = Q.gmz;
-      lds_classes = Q.lds_classes;
+      lds_table = Q.lds_table;
     }
     if constexpr (SIG != kSigNone && !kGeneric) p[0] = unif(Q.sigp[0]);
     if constexpr (SIG == kSigZY || SIG == kSigZBox || SIG == kSigZTri) {
@@ -253,7 +272,7 @@ template <int SIG> struct Reg32 {
     if constexpr (SIG == kSigNone) {
       return 2;
     } else if constexpr (kGeneric) {
-      return region_index_generic<float, 8>((int)Q.nprims, Q.kind, &Q.pf[0][0], a, b);
+      return region_index_generic<float, kPfStride>((int)Q.nprims, Q.kind, &Q.pf[0][0], a, b);
     } else {
       if (b < unif(p[0])) return 0;
       return in_prim1(a, b) ? 1 : 2;
@@ -291,15 +310,16 @@ template <int SIG> struct Reg32 {
     }
   }
   // generic signature: the fixed-point increment of the region containing
-  // (a, b).  With the sigma grid: one cell read and one edge function (the
-  // primitive loop only in cells crossed by more than one boundary); the same
+  // (a, b).  With the sigma grid: one cell read and one edge function (a
+  // second line in cells crossed by two boundaries, the primitive loop in
+  // cells crossed by more); the same
   // region as the loop for every point (the host classifies cells with
   // margins for the FP32 rounding of the cell index and of the edge
   // functions).  The cell comes from LDS (kSigGenericLds: a class byte, then
   // the class's SigmaCell) or from the global grid.
   __device__ __forceinline__ uint32_t inc32(const DevReq &Q, float a, float b) const {
     if constexpr (SIG == kSigGeneric) {
-      if (grid == nullptr) return region_c_generic<float, 8>((int)Q.nprims, Q.kind, &Q.pf[0][0], Q.cfx, a, b);
+      if (grid == nullptr) return region_c_generic<float, kPfStride>((int)Q.nprims, Q.kind, &Q.pf[0][0], Q.cfx, a, b);
     }
     // cell (trunc(a gsy + goy), trunc(b gsz + goz)) clamped to the grid:
     // clamping in FP32 before the truncation gives the same cell
@@ -307,37 +327,38 @@ template <int SIG> struct Reg32 {
     const uint32_t j = (uint32_t)__builtin_amdgcn_fmed3f(__builtin_fmaf(b, gsz, goz), 0.f, gmz);
     const uint32_t cell = __umul24(j, gy) + i;
     uint32_t inc_ge, inc_lt, xi;
-    float v0, v1, dy, dz;
+    float A, B, C;
     if constexpr (SIG == kSigGenericLds) {
-      const uint32_t cls = g_lds[(size_t)lds_classes * sizeof(SigmaCell) + cell];
-      const uint4 h0 = *reinterpret_cast<const uint4 *>(g_lds + (size_t)cls * sizeof(SigmaCell));
+      // the class byte sits at the cell's own offset; the class at lds_table
+      const uint32_t cls = g_lds[cell];
+      const uint8_t *ce = g_lds + lds_table + cls * (uint32_t)sizeof(SigmaCell);
+      const uint4 h0 = *reinterpret_cast<const uint4 *>(ce);
+      const uint2 h1 = *reinterpret_cast<const uint2 *>(ce + 16);
       inc_ge = h0.x; inc_lt = h0.y;
-      v0 = __builtin_bit_cast(float, h0.z); v1 = __builtin_bit_cast(float, h0.w);
-      const uint4 h1 = *reinterpret_cast<const uint4 *>(g_lds + (size_t)cls * sizeof(SigmaCell) + 16);
-      dy = __builtin_bit_cast(float, h1.x); dz = __builtin_bit_cast(float, h1.y);
-      xi = h1.z;
+      A = __builtin_bit_cast(float, h0.z); B = __builtin_bit_cast(float, h0.w);
+      C = __builtin_bit_cast(float, h1.x); xi = h1.y;
     } else {
-      // the cell's 28 bytes in flight together, through the global address
+      // the cell's 24 bytes in flight together, through the global address
       // space (one memory latency per step)
       typedef const __attribute__((address_space(1))) uint32_t *gptr;
       const gptr w = (gptr)(grid + cell);
       inc_ge = w[0]; inc_lt = w[1];
-      v0 = __builtin_bit_cast(float, w[2]); v1 = __builtin_bit_cast(float, w[3]);
-      dy = __builtin_bit_cast(float, w[4]); dz = __builtin_bit_cast(float, w[5]);
-      xi = w[6];
+      A = __builtin_bit_cast(float, w[2]); B = __builtin_bit_cast(float, w[3]);
+      C = __builtin_bit_cast(float, w[4]); xi = w[5];
     }
-    const float e = dy * (b - v1) - dz * (a - v0);
+    const float e = __builtin_fmaf(A, a, __builtin_fmaf(B, b, C));
     uint32_t c = e >= 0.f ? inc_ge : inc_lt;
-    if (inc_ge & kCellFlags) {   // a few cells: two lines, or the primitive loop
-      if (inc_ge & kCellTwo) {
+    if (inc_ge >= kCellTwo) {   // a few cells: two lines, or the primitive loop
+      if (inc_ge < kCellLoop) {
         const SigmaCell *X;
-        if constexpr (SIG == kSigGenericLds) X = reinterpret_cast<const SigmaCell *>(g_lds) + xi;
+        if constexpr (SIG == kSigGenericLds)
+          X = reinterpret_cast<const SigmaCell *>(g_lds + lds_table) + xi;
         else X = grid_ext + xi;
-        const float e2 = X->dy * (b - X->v1) - X->dz * (a - X->v0);
+        const float e2 = __builtin_fmaf(X->A, a, __builtin_fmaf(X->B, b, X->C));
         if (e2 >= 0.f) c = e >= 0.f ? X->inc_ge : X->inc_lt;
         else c = e >= 0.f ? (inc_ge & ~kCellFlags) : inc_lt;
       } else {
-        c = region_c_generic<float, 8>((int)Q.nprims, Q.kind, &Q.pf[0][0], Q.cfx, a, b);
+        c = loop_fallback(Q, a, b);
       }
     }
     return c;

@@ -336,44 +336,46 @@ static sdd_status validate(sdd_ctx *ctx, const sdd_request *r, const HostModel *
 // ---------------------------------------------------------------------------
 namespace {
 struct GLine {
-  float v0, v1, dy, dz;
+  float A, B, C;   // e = fma(A, a, fma(B, b, C)) in FP32
   uint32_t mode;   // 0: in iff e < 0, 1: in iff e >= 0 (triangles: decided per cell)
 };
 enum GSign { kGNeg, kGPos, kGCross };
 enum GStat { kGOut, kGIn, kGOne, kGMany };
 
-// The primitive's inequalities as edge functions e = dy (b - v1) - dz (a - v0),
-// in the primitive loop's expressions (FP32 parameters relative to the centre).
+// The primitive's inequalities as lines, in the primitive loop's FP32
+// expressions (parameters relative to the centre): a half-plane or box side
+// a < y0 is e = fl(a - y0) < 0 (A = 1, B = 0, C = -y0: the inner fma gives
+// -y0 exactly), whose sign is the compare's; a triangle edge is its (A, B, C).
 int prim_lines(int kind, const float *v, GLine *L) {
   switch (kind) {
-    case SDD_HALF_Z_LT: L[0] = {0.f, v[0], 1.f, 0.f, 0u}; return 1;   // b < z0: e = b - z0
-    case SDD_HALF_Y_LT: L[0] = {v[0], 0.f, 0.f, -1.f, 0u}; return 1;  // a < y0: e = a - y0
+    case SDD_HALF_Z_LT: L[0] = {0.f, 1.f, -v[0], 0u}; return 1;   // b < z0
+    case SDD_HALF_Y_LT: L[0] = {1.f, 0.f, -v[0], 0u}; return 1;   // a < y0
     case SDD_BOX:
-      L[0] = {v[0], 0.f, 0.f, -1.f, 1u};   // a >= y0
-      L[1] = {v[1], 0.f, 0.f, -1.f, 0u};   // a < y1
-      L[2] = {0.f, v[2], 1.f, 0.f, 1u};    // b >= z0
-      L[3] = {0.f, v[3], 1.f, 0.f, 0u};    // b < z1
+      L[0] = {1.f, 0.f, -v[0], 1u};   // a >= y0
+      L[1] = {1.f, 0.f, -v[1], 0u};   // a < y1
+      L[2] = {0.f, 1.f, -v[2], 1u};   // b >= z0
+      L[3] = {0.f, 1.f, -v[3], 0u};   // b < z1
       return 4;
-    default:   // triangle edge m: (v[2m+2] - v[2m]) (b - v[2m+1]) - (v[2m+3] - v[2m+1]) (a - v[2m])
-      for (int m = 0; m < 3; ++m) {
-        const int i0 = 2 * m, i1 = (2 * m + 2) % 6;
-        L[m] = {v[i0], v[i0 + 1], (float)((double)v[i1] - (double)v[i0]),
-                (float)((double)v[i1 + 1] - (double)v[i0 + 1]), 0u};
-      }
+    default:   // triangle edge m
+      for (int m = 0; m < 3; ++m) L[m] = {v[3 * m], v[3 * m + 1], v[3 * m + 2], 0u};
       return 3;
   }
 }
 
+// Sign of the line over a cell (its corners: e is linear).  The FP32 value
+// fma(A, a, fma(B, b, C)) is within 2u (|A a| + |B b| + |C|)(1 + u) of
+// A a + B b + C (two roundings, u = 2^-24), so a sign is certain beyond
+// 4u times that magnitude.
 GSign classify(const GLine &L, double a0, double a1, double b0, double b1) {
   double emin = HUGE_VAL, emax = -HUGE_VAL, mag = 0.0;
   const double as[2] = {a0, a1}, bs[2] = {b0, b1};
+  const double A = L.A, B = L.B, C = L.C;
   for (double a : as)
     for (double b : bs) {
-      const double e = (double)L.dy * (b - (double)L.v1) - (double)L.dz * (a - (double)L.v0);
+      const double e = A * a + B * b + C;
       emin = std::min(emin, e);
       emax = std::max(emax, e);
-      mag = std::max(mag, std::fabs((double)L.dy) * std::fabs(b - (double)L.v1) +
-                              std::fabs((double)L.dz) * std::fabs(a - (double)L.v0));
+      mag = std::max(mag, std::fabs(A * a) + std::fabs(B * b) + std::fabs(C));
     }
   const double m = 4.0 * 0x1p-24 * mag;
   if (emin > m) return kGPos;
@@ -428,8 +430,7 @@ PrimCell prim_cell(int kind, const GLine *L, int nl, double a0, double a1, doubl
 }
 
 bool same_line(const LineTest &x, const LineTest &y) {
-  return x.neg == y.neg && x.line.v0 == y.line.v0 && x.line.v1 == y.line.v1 && x.line.dy == y.line.dy &&
-         x.line.dz == y.line.dz;
+  return x.neg == y.neg && x.line.A == y.line.A && x.line.B == y.line.B && x.line.C == y.line.C;
 }
 }  // namespace
 
@@ -437,10 +438,9 @@ static constexpr uint32_t kGridCells = 65536;
 
 // The cell's line in SigmaCell form (negated when the test needs it).
 static void put_line(SigmaCell &C, const LineTest &t) {
-  C.v0 = t.line.v0;
-  C.v1 = t.line.v1;
-  C.dy = t.neg ? -t.line.dy : t.line.dy;
-  C.dz = t.neg ? -t.line.dz : t.line.dz;
+  C.A = t.neg ? -t.line.A : t.line.A;
+  C.B = t.neg ? -t.line.B : t.line.B;
+  C.C = t.neg ? -t.line.C : t.line.C;
 }
 
 // Sigma grid of the FP32 walk's generic signature.  Per cell: the primitives
@@ -531,7 +531,7 @@ static void build_sigma_grid(DevReq &q, std::vector<SigmaCell> &grid, std::vecto
         T[combo] = q.cfx[region];
       }
       if (nlines == 0) {
-        C.v0 = C.v1 = C.dy = C.dz = 0.f;   // e = +-0 >= 0
+        C.A = C.B = C.C = 0.f;   // e = +0 >= 0
         C.inc_ge = C.inc_lt = T[0];
       } else if (nlines == 1 || (T[0] == T[2] && T[1] == T[3])) {
         put_line(C, L[0]);
@@ -552,22 +552,22 @@ static void build_sigma_grid(DevReq &q, std::vector<SigmaCell> &grid, std::vecto
           it = ext_index.emplace(key, (uint32_t)ext.size()).first;
           ext.push_back(E);
         }
-        C.pad[0] = it->second;
+        C.xi = it->second;
       }
     }
   }
 }
 
-// The LDS form of a sigma grid: its distinct cells once (a class table),
-// then the two-line cells' extension entries (each cell's pad[0] renumbered
-// to its entry's place in this table), then one class byte per cell; empty
-// when the grid has more than kMaxLdsClasses distinct cells or the form
-// would not fit in max_bytes of LDS.  n_table is the number of 32-byte
-// entries before the class bytes.  Padded to a multiple of 16 bytes.
+// The LDS form of a sigma grid: one class byte per cell (padded to 16 bytes),
+// then from byte `table` the grid's distinct cells once (a class table) and
+// the two-line cells' extension entries (each cell's xi renumbered to its
+// entry's place in this table); empty when the grid has more than
+// kMaxLdsClasses distinct cells or the form would not fit in max_bytes of
+// LDS.  Padded to a multiple of 16 bytes.
 static void build_lds_form(const std::vector<SigmaCell> &grid, const std::vector<SigmaCell> &ext, size_t max_bytes,
-                           std::vector<uint8_t> &out, uint32_t &n_table) {
+                           std::vector<uint8_t> &out, uint32_t &table) {
   out.clear();
-  n_table = 0;
+  table = 0;
   std::vector<SigmaCell> classes;
   std::map<std::vector<uint8_t>, uint32_t> index;
   std::vector<uint8_t> ids(grid.size());
@@ -583,16 +583,16 @@ static void build_lds_form(const std::vector<SigmaCell> &grid, const std::vector
     ids[c] = (uint8_t)it->second;
   }
   for (SigmaCell &C : classes)
-    if ((C.inc_ge & kCellFlags) == kCellTwo) C.pad[0] += (uint32_t)classes.size();
+    if ((C.inc_ge & kCellFlags) == kCellTwo) C.xi += (uint32_t)classes.size();
+  const size_t off = (ids.size() + 15) / 16 * 16;
   const size_t n = classes.size() + ext.size();
-  const size_t bytes = (n * sizeof(SigmaCell) + ids.size() + 15) / 16 * 16;
+  const size_t bytes = off + n * sizeof(SigmaCell);
   if (bytes > max_bytes) return;
-  n_table = (uint32_t)n;
-  out.resize(n * sizeof(SigmaCell) + ids.size());
-  std::memcpy(out.data(), classes.data(), classes.size() * sizeof(SigmaCell));
-  if (!ext.empty()) std::memcpy(out.data() + classes.size() * sizeof(SigmaCell), ext.data(), ext.size() * sizeof(SigmaCell));
-  std::memcpy(out.data() + n * sizeof(SigmaCell), ids.data(), ids.size());
-  out.resize(bytes, 0);
+  table = (uint32_t)off;
+  out.assign(bytes, 0);
+  std::memcpy(out.data(), ids.data(), ids.size());
+  std::memcpy(out.data() + off, classes.data(), classes.size() * sizeof(SigmaCell));
+  if (!ext.empty()) std::memcpy(out.data() + off + classes.size() * sizeof(SigmaCell), ext.data(), ext.size() * sizeof(SigmaCell));
 }
 
 static void fill_devreq(Prepared &P) {
@@ -626,11 +626,20 @@ static void fill_devreq(Prepared &P) {
         q.pf[k][0] = (float)((v[0] - q.ymid) * ki); q.pf[k][1] = (float)((v[1] - q.ymid) * ki);
         q.pf[k][2] = (float)((v[2] - q.zmid) * ki); q.pf[k][3] = (float)((v[3] - q.zmid) * ki);
         break;
-      default:
-        for (int i = 0; i < 6; i += 2) {
-          q.pf[k][i] = (float)((v[i] - q.ymid) * ki);
-          q.pf[k][i + 1] = (float)((v[i + 1] - q.zmid) * ki);
+      default: {
+        // edge e from vertex e to vertex e + 1 as A a + B b + C
+        double vy[3], vz[3];
+        for (int i = 0; i < 3; ++i) {
+          vy[i] = (v[2 * i] - q.ymid) * ki;
+          vz[i] = (v[2 * i + 1] - q.zmid) * ki;
         }
+        for (int e = 0; e < 3; ++e) {
+          const int l = (e + 1) % 3;
+          q.pf[k][3 * e] = (float)(-(vz[l] - vz[e]));
+          q.pf[k][3 * e + 1] = (float)(vy[l] - vy[e]);
+          q.pf[k][3 * e + 2] = (float)((vz[l] - vz[e]) * vy[e] - (vy[l] - vy[e]) * vz[e]);
+        }
+      }
     }
   }
   q.c[np] = alpha_of(r, m, m.desc.sigma_background) * r.dt / 2.0;
@@ -710,11 +719,11 @@ static void fill_devreq(Prepared &P) {
   q.grid = nullptr;
   q.grid_ext = nullptr;
   q.lds_src = nullptr;
-  q.lds_bytes = q.lds_classes = 0;
+  q.lds_bytes = q.lds_table = 0;
   if (q.sig == kSigGeneric && r.precision == SDD_FP32_MIXED && !(r.flags & SDD_FLAG_NO_SIGMA_GRID) && np > 0) {
     build_sigma_grid(q, P.grid, P.grid_ext);
     if (!(r.flags & SDD_FLAG_NO_LDS_GRID))
-      build_lds_form(P.grid, P.grid_ext, P.owner->lds_per_block, P.lds, q.lds_classes);
+      build_lds_form(P.grid, P.grid_ext, P.owner->lds_per_block, P.lds, q.lds_table);
     q.lds_bytes = (uint32_t)P.lds.size();
   }
 }
@@ -940,7 +949,7 @@ static int common_sig(It begin, It end, Get get) {
 // lds_bytes is the size of that form.
 static bool same_lds_grid(const Prepared &a, const Prepared &b) {
   const DevReq &x = a.dreq, &y = b.dreq;
-  return a.lds == b.lds && x.lds_classes == y.lds_classes && x.gy == y.gy && x.gz == y.gz && x.gsy == y.gsy &&
+  return a.lds == b.lds && x.lds_table == y.lds_table && x.gy == y.gy && x.gz == y.gz && x.gsy == y.gsy &&
          x.goy == y.goy && x.gsz == y.gsz && x.goz == y.goz;
 }
 
