@@ -1054,6 +1054,15 @@ __device__ __forceinline__ bool run_request(const DevReq &Q, uint32_t budget, ui
   return suspended;
 }
 
+// A launch mixing signatures runs each request's walker loop inlined in one
+// dispatching kernel, except the generic signature's, whose registers (the
+// sigma grid's parameters, the primitive list) would otherwise push the
+// others' loop-invariant values into spill slots: it is called out of line.
+template <class T>
+__device__ __noinline__ bool run_request_outline(const DevReq &Q, uint32_t budget, uint32_t refill_mask, uint32_t &iters) {
+  return run_request<T>(Q, budget, refill_mask, iters);
+}
+
 template <template <int> class T>
 __device__ __forceinline__ bool run_dispatch(const DevReq &Q, uint32_t budget, uint32_t refill_mask, uint32_t &iters) {
   switch (uni((uint32_t)Q.sig)) {
@@ -1062,7 +1071,7 @@ __device__ __forceinline__ bool run_dispatch(const DevReq &Q, uint32_t budget, u
     case kSigZY: return run_request<T<kSigZY>>(Q, budget, refill_mask, iters);
     case kSigZBox: return run_request<T<kSigZBox>>(Q, budget, refill_mask, iters);
     case kSigZTri: return run_request<T<kSigZTri>>(Q, budget, refill_mask, iters);
-    default: return run_request<T<kSigGeneric>>(Q, budget, refill_mask, iters);
+    default: return run_request_outline<T<kSigGeneric>>(Q, budget, refill_mask, iters);
   }
 }
 
