@@ -539,13 +539,13 @@ int orc_solve(const orc_problem *P, int n_threads, orc_node *out_nodes,
  * a disc point outside the rectangle ends the walk at the nearest boundary
  * point with f = 1; equal kappa: the proposal is kept and the step's time
  * goes to the side of the proposal.
- * Parity unpinned: how a step that reaches the interface splits its time
- * between the two sides (the (1/2)(dt - t_gamma) p terms) is pinned only
- * through the sum (exact time conservation), the bounds of each share and
- * the convergence of the whole scheme to the two-sided closed form with
- * kappa and lambda both unequal; any split of an interface step's time
- * changes only the constant of the scheme's O(sqrt(dt)) bias (an interface
- * is visited O(1/sqrt(dt)) times per path), so no closed form separates it.
+ * The split of an interface step's time between the two sides (the
+ * (1/2)(dt - t_gamma) p terms) changes only the constant of the scheme's
+ * O(sqrt(dt)) bias (an interface is visited O(1/sqrt(dt)) times per path),
+ * so no continuum closed form separates it; it is pinned against the exact
+ * expectation of this discrete scheme at a finite dt on a strip, where the
+ * walk is a one-dimensional Markov chain evaluated without sampling
+ * (tests/kappa_chain.py).
  * Random numbers: counter (n/2, p, j, 4s) -> the normals of steps n, n+1
  * (words 0,1 / 2,3); (n, p, j, 4s+1) -> outer bridge uniforms (words 0, 1),
  * the interface bridge uniform (word 2), the side uniform (word 3);

@@ -15,6 +15,12 @@ PINS = "test_oracle_pins.py"
 KPINS = "test_kappa_pins.py"
 KAPPA_SECTION = "Discontinuous kappa: the interface scheme"
 
+# the two branches of an interface step's time split (resume on side i, on side j)
+KAPPA_SPLIT = ("            T[si] += dt - 0.5 * (dt - tg) * pi_;\n            T[sj] += 0.5 * (dt - tg) * pi_;\n"
+               "        } else {                                         /* resume on side j */\n"
+               "            cy = P->y_if + towards * h;\n"
+               "            T[si] += tg + 0.5 * (dt - tg) * pj;\n            T[sj] += 0.5 * (dt - tg) * (2.0 - pj);")
+
 # (name, original text, mutated text, pins expected to fail[, pin file])
 MUTANTS = [
     ("no_bridge", "if (q <= P->dt * L) {", "if (0) {", ["test_mean_exit_time_series"]),
@@ -55,6 +61,26 @@ MUTANTS = [
     ("kappa_step_scale", "double s = sqrt(ki * dt);", "double s = sqrt(dt);",
      ["test_equal_kappa_is_the_constant_coefficient_walk"], KPINS),
     ("kappa_exit_share", "T[si] += fr * dt;", "T[si] += dt;", ["test_occupation_shares_sum_to_the_step"], KPINS),
+    # the split of an interface step's time between the sides (ways that keep
+    # the sum and converge to the same continuum limit)
+    ("kappa_split_all_to_start", KAPPA_SPLIT,
+     KAPPA_SPLIT.replace("T[si] += dt - 0.5 * (dt - tg) * pi_;\n            T[sj] += 0.5 * (dt - tg) * pi_;",
+                         "T[si] += dt;").replace(
+         "T[si] += tg + 0.5 * (dt - tg) * pj;\n            T[sj] += 0.5 * (dt - tg) * (2.0 - pj);", "T[si] += dt;"),
+     ["test_interface_split_matches_the_exact_scheme"], KPINS),
+    ("kappa_split_all_to_resume", KAPPA_SPLIT,
+     KAPPA_SPLIT.replace("T[si] += dt - 0.5 * (dt - tg) * pi_;\n            T[sj] += 0.5 * (dt - tg) * pi_;",
+                         "T[si] += dt;").replace(
+         "T[si] += tg + 0.5 * (dt - tg) * pj;\n            T[sj] += 0.5 * (dt - tg) * (2.0 - pj);", "T[sj] += dt;"),
+     ["test_interface_split_matches_the_exact_scheme"], KPINS),
+    ("kappa_split_p_swapped",
+     "T[si] += dt - 0.5 * (dt - tg) * pi_;\n            T[sj] += 0.5 * (dt - tg) * pi_;",
+     "T[si] += dt - 0.5 * (dt - tg) * pj;\n            T[sj] += 0.5 * (dt - tg) * pj;",
+     ["test_interface_split_matches_the_exact_scheme"], KPINS),
+    ("kappa_split_tg_to_other",
+     "T[si] += tg + 0.5 * (dt - tg) * pj;\n            T[sj] += 0.5 * (dt - tg) * (2.0 - pj);",
+     "T[sj] += tg + 0.5 * (dt - tg) * (2.0 - pj);\n            T[si] += 0.5 * (dt - tg) * pj;",
+     ["test_interface_split_matches_the_exact_scheme"], KPINS),
 ]
 
 
