@@ -238,3 +238,33 @@ def test_kappa_fp32_analytic_grid_full_size(ctx):
     err = np.abs(g32["mean"] - exact)
     assert np.all(g32["unfinished"] == 0)
     assert np.all(err <= 5.0 * g32["se"] + 0.03)
+
+
+def test_kappa_both_precisions_match_the_exact_scheme_on_a_strip(ctx):
+    """The HIP kappa walks, FP64 and FP32-mixed (each with its own code for
+    the interface time split), against the exact expectation of the discrete
+    scheme on a strip (kappa_chain: the walk's one-dimensional Markov chain
+    evaluated without sampling): kappa (1, 4), lambda (20, 0), dt = 1e-2,
+    |y| < 1.5 with the z-walls out of reach, 8e6 paths per node; within 4 SE
+    plus the chain's quadrature error.  Splits of an interface step's time
+    that converge to the same continuum limit differ from it by 0.015 or more
+    at y = -0.05 (about 100 SE here)."""
+    from kappa_chain import StripChain
+    a, kappa, lam, dt = 1.5, (1.0, 4.0), (20.0, 0.0), 1e-2
+    chain = StripChain(a, kappa, lam, 1.0, 1.0, dt, n_side=300).solve()
+    ys = np.array([-0.3, -0.05, 0.05, 0.3])
+    exact = np.array([chain.value(y) for y in ys])
+    walls = (-a, a, -40.0, 40.0)
+    g = W.tables_from_function(lambda y, z: np.ones_like(y, dtype=np.complex128), walls, 4096)
+    nodes = np.stack([ys, np.zeros_like(ys)], axis=1)
+    n = nodes.shape[0]
+    p = W.KappaProblem(*walls, y_if=0.0, kappa=kappa, lam=lam, g=g, nodes=nodes,
+                       path_begin=np.zeros(n, np.uint32), path_count=np.full(n, 8_000_000, np.uint32), dt=dt,
+                       seed=12, stream=1)
+    for prec in (0, FP32):
+        r = ctx.solve_kappa(p, precision=prec)
+        d = (r["mean"] - exact).real
+        log(f"kappa strip precision {prec}: mean {r['mean'].real} exact {exact.real} diff/se {d / r['se_re']}")
+        assert np.all(np.abs(r["mean"].imag) == 0.0)
+        assert np.all(np.abs(d) <= 4.0 * r["se_re"] + 1e-4), (d, r["se_re"])
+        assert np.all(r["unfinished"] == 0)
