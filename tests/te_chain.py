@@ -1,0 +1,125 @@
+"""The exact expectation of the TE walk's discrete scheme on a strip in z, by
+a deterministic evaluation of its Markov chain (no Monte Carlo).
+
+Geometry: z_lo < z < z_hi, the walls y = +-Y far enough that a walk never
+reaches them, the conductivity a function of z (layers), Dirichlet data
+g_top at z = z_lo and g_bottom at z = z_hi.  The walk's z-coordinate is then
+a Markov chain of its own and exp(-i S) is a product of one factor per step,
+so the scheme's expectation u (a function of the starting z) solves the
+linear equation u = K u + b.  One step from z, as Secs. 2.2 and 3.1 prescribe
+in the reading this build takes:
+
+* the proposal z' = z + sqrt(dt) N;
+* the wall nearer to z (a tie goes to the lower one, z_lo) is left if z' lies
+  beyond it, at the fraction d0 / (d0 - d1) of the step, or else with the
+  Brownian bridge's probability exp(-2 d0 d1 / dt), at the fraction e / E,
+  E ~ e + Exp(1), e = 2 d0 d1 / dt (Eq. 14); the exit's factor is
+  exp(-i c(z) fr) g_wall, the partial step charged to the region of the last
+  point inside;
+* otherwise the walk moves to z' with the factor exp(-i c(z')): the full
+  step's phase goes to the region of its end point;
+
+where c(z) = alpha(z) dt / 2 is the phase of a full step in the layer of z
+(Eqs. 7-8 with the rate alpha = omega mu0 sigma L^2).  u is piecewise linear on a
+grid with nodes at the layer boundaries; the one-step expectations are
+Gauss-Legendre sums over the proposal and Gauss-Laguerre sums over the
+bridge's exponential variable.  Test infrastructure: it computes no part of
+the walk the library runs."""
+import math
+
+import numpy as np
+
+_XL, _WL = np.polynomial.laguerre.laggauss(40)
+_XG, _WG = np.polynomial.legendre.leggauss(6)
+
+
+class ZStripChain:
+    def __init__(self, z_lo, z_hi, tops, rates, g_top, g_bottom, dt, n=1200, charge_end_point=True):
+        """tops: ascending layer tops (the first <= z_lo); rates: the phase
+        per full step c of each layer.  charge_end_point=False charges each
+        full step to the layer of its start point instead (for comparison)."""
+        self.zl, self.zh, self.dt = float(z_lo), float(z_hi), float(dt)
+        self.tops, self.rates = np.asarray(tops, dtype=np.float64), np.asarray(rates, dtype=np.float64)
+        self.gt, self.gb = complex(g_top), complex(g_bottom)
+        self.end_point = charge_end_point
+        grid = np.linspace(self.zl, self.zh, n + 1)
+        inner = self.tops[(self.tops > self.zl) & (self.tops < self.zh)]
+        self.z = np.unique(np.concatenate([grid, inner]))
+
+    def rate(self, z):
+        k = np.searchsorted(self.tops, np.asarray(z, dtype=np.float64), side="right") - 1
+        return self.rates[np.clip(k, 0, self.rates.size - 1)]
+
+    def _interp(self, x, w):
+        m = self.z.size
+        k = np.clip(np.searchsorted(self.z, x, side="right") - 1, 0, m - 2)
+        t = (x - self.z[k]) / (self.z[k + 1] - self.z[k])
+        row = np.zeros(m, dtype=np.complex128)
+        for part, wt in ((k, w * (1.0 - t)), (k + 1, w * t)):
+            row += np.bincount(part, weights=wt.real, minlength=m) + 1j * np.bincount(part, weights=wt.imag,
+                                                                                      minlength=m)
+        return row
+
+    def _row(self, z):
+        dt = self.dt
+        s = math.sqrt(dt)
+        dlo, dhi = z - self.zl, self.zh - z
+        upper = not (dlo <= dhi)
+        d0 = dhi if upper else dlo
+        gw = self.gb if upper else self.gt
+        lo, hi = z - 9.0 * s, z + 9.0 * s
+        cuts = [lo, hi, self.zl, self.zh] + list(np.linspace(lo, hi, 73)) + list(self.tops)
+        cuts.extend(self.z[(self.z > lo) & (self.z < hi)])
+        cuts = np.unique(np.clip(np.asarray(cuts), lo, hi))
+        L, R = cuts[:-1], cuts[1:]
+        zn = ((0.5 * (R - L))[:, None] * _XG[None, :] + (0.5 * (R + L))[:, None]).ravel()
+        wq = ((0.5 * (R - L))[:, None] * _WG[None, :]).ravel()
+        wq = wq * np.exp(-0.5 * ((zn - z) / s) ** 2) / (s * math.sqrt(2.0 * math.pi))
+        c0 = float(self.rate(z))
+        d1 = (self.zh - zn) if upper else (zn - self.zl)
+        cross = d1 <= 0.0
+        b = np.sum(wq[cross] * np.exp(-1j * c0 * d0 / (d0 - d1[cross]))) * gw
+        zn, wq, d1 = zn[~cross], wq[~cross], d1[~cross]
+        e = 2.0 * d0 * d1 / dt
+        pb = np.exp(-e)
+        fr = e[:, None] / (e[:, None] + _XL[None, :])
+        b += np.sum(wq * pb * (np.exp(-1j * c0 * fr) @ _WL)) * gw
+        cstep = self.rate(zn) if self.end_point else c0
+        row = self._interp(zn, wq * (1.0 - pb) * np.exp(-1j * cstep))
+        return row, b
+
+    def solve(self):
+        m = self.z.size
+        K = np.zeros((m, m), dtype=np.complex128)
+        bvec = np.zeros(m, dtype=np.complex128)
+        bvec[0], bvec[-1] = self.gt, self.gb      # the walls themselves
+        for k in range(1, m - 1):
+            K[k], bvec[k] = self._row(self.z[k])
+        self.u = np.linalg.solve(np.eye(m) - K, bvec)
+        return self
+
+    def value(self, z):
+        return complex(self._interp(np.array([float(z)]), np.array([1.0 + 0.0j])) @ self.u)
+
+
+def z_strip_problem(alpha, dt, zs, paths, precision=0, seed=21, g_top=1.0, g_bottom=0.3 + 0.2j, M=4096):
+    """The strip of ZStripChain as a request: air (z < 0) over ground of rate
+    alpha, z in [-1, 1], the walls y = +-40 out of reach; g_top at z = -1,
+    g_bottom at z = 1 (linear in z on the side walls, which no walk reaches);
+    nodes at (0, z) for z in zs."""
+    from paper_1603_09311_amd import workloads as W
+    walls = (-40.0, 40.0, -1.0, 1.0)
+    gt, gb = complex(g_top), complex(g_bottom)
+    g = W.tables_from_function(lambda y, z: gt + (gb - gt) * (np.asarray(z) + 1.0) / 2.0 + 0.0 * np.asarray(y),
+                               walls, M)
+    zs = np.asarray(zs, dtype=np.float64)
+    nodes = np.stack([np.zeros_like(zs), zs], axis=1)
+    n = nodes.shape[0]
+    return W.Problem(*walls, regions=[W.Region(W.HALF_Z_LT, (0.0,), 0.0)], sigma_background=1.0,
+                     length_unit_m=1.0, freq_hz=0.0, alpha_direct=float(alpha), g=g, nodes=nodes,
+                     path_begin=np.zeros(n, np.uint32), path_count=np.full(n, paths, np.uint32), dt=dt,
+                     seed=seed, precision=precision, name="z_strip")
+
+
+def z_strip_chain(alpha, dt, g_top=1.0, g_bottom=0.3 + 0.2j, n=1200):
+    return ZStripChain(-1.0, 1.0, [-1.0, 0.0], [0.0, alpha * dt / 2.0], g_top, g_bottom, dt, n=n).solve()

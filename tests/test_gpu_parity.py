@@ -832,3 +832,23 @@ def test_domain_decomposition_layered_model(ctx):
     err = np.abs(F - ex).max()
     log(f"decomposition: max error {err:.3e}, max interface SE {r['se'].max():.3e}")
     assert err <= 1.7e-4 + 5.0 * r["se"].max()
+
+
+def test_both_precisions_match_the_exact_scheme_on_a_strip(ctx):
+    """The walkers as discrete schemes, at a finite dt with no bias
+    allowance: on the strip -1 < z < 1 (air over ground of rate 20, the side
+    walls out of reach) the scheme's exact expectation (te_chain, its Markov
+    chain evaluated with no sampling) against the FP64 and the FP32-mixed
+    persistent walkers at dt = 1e-2 and 10^7 paths per node: within 4 SE per
+    component plus 3e-5 (the chain's quadrature error is about 1e-5)."""
+    import te_chain as TC
+    zs = (-0.5, -0.05, 0.05, 0.5)
+    chain = TC.z_strip_chain(20.0, 1e-2)
+    exact = np.array([chain.value(z) for z in zs])
+    for prec in (W.FP64, W.FP32_MIXED):
+        r = ctx.solve(TC.z_strip_problem(20.0, 1e-2, zs, 10_000_000, precision=prec))
+        d = r["mean"] - exact
+        log(f"z strip precision {prec}: diff/se re {d.real / r['se_re']} im {d.imag / r['se_im']}")
+        assert np.all(np.abs(d.real) <= 4.0 * r["se_re"] + 3e-5), (d, r["se_re"])
+        assert np.all(np.abs(d.imag) <= 4.0 * r["se_im"] + 3e-5), (d, r["se_im"])
+        assert np.all(r["unfinished"] == 0)

@@ -35,6 +35,8 @@ MUTANTS = [
      "orc_box_muller(orc_u01(w[0]), orc_u01(w[1]), out);", ["test_mean_exit_time_series"]),
     ("partial_phase_dropped", "S += c[orc_region(P, y, z)] * fr;", "S += 0.0 * fr;",
      ["test_single_step_crossing_by_hand"]),
+    ("phase_start_point", "S += c[orc_region(P, yn, zn)];", "S += c[orc_region(P, y, z)];",
+     ["test_discrete_scheme_exact_on_a_strip"]),
     ("table_index_shift", "out[0] = (1.0 - lam) * gw[2 * i] + lam * gw[2 * i + 2];",
      "out[0] = (1.0 - lam) * gw[2 * i + 2] + lam * gw[2 * i + 4];", ["test_table_interpolation_linear_exact"]),
     ("air_phase", "if (P->freq_hz > 0.0) {", "if (sigma == 0.0) return P->alpha_direct;\n    if (P->freq_hz > 0.0) {",

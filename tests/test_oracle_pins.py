@@ -335,6 +335,30 @@ def test_layered_halfspace_is_1d(orc):
     _check(res, exact, bias=2e-3)
 
 
+def test_discrete_scheme_exact_on_a_strip(orc):
+    """The walk as a discrete scheme, at a finite dt and with no bias
+    allowance: on the strip -1 < z < 1 (air over ground of rate alpha = 20,
+    the side walls out of reach) the walk's z-coordinate is a Markov chain
+    and exp(-i S) a product of one factor per step, so the scheme's exact
+    expectation solves a linear equation, which te_chain evaluates with no
+    sampling (it reproduces the linear harmonic solution to 1e-13, and its
+    quadrature converges to about 1e-5 at this grid).  The oracle at
+    dt = 1e-2, 10^6 paths per node, within 4 standard errors per component
+    plus 3e-5.  Charging each full step to the layer of its start point
+    instead of its end point moves the value at z = 0.05 by 0.017 (30 SE)."""
+    import te_chain as TC
+    lin = TC.ZStripChain(-1.0, 1.0, [-1.0, 0.0], [0.0, 0.0], 1.0, 0.3 + 0.2j, 1e-2, n=300).solve()
+    for z in (-0.5, 0.05, 0.7):
+        assert abs(lin.value(z) - (1.0 + (0.3 + 0.2j - 1.0) * (z + 1.0) / 2.0)) < 1e-12
+    zs = (-0.5, -0.05, 0.05, 0.5)
+    chain = TC.z_strip_chain(20.0, 1e-2)
+    exact = np.array([chain.value(z) for z in zs])
+    res, _ = orc.solve(TC.z_strip_problem(20.0, 1e-2, zs, 1_000_000))
+    d_re, d_im = res["mean_re"] - exact.real, res["mean_im"] - exact.imag
+    assert np.all(np.abs(d_re) <= 4.0 * res["se_re"] + 3e-5), (d_re, res["se_re"])
+    assert np.all(np.abs(d_im) <= 4.0 * res["se_im"] + 3e-5), (d_im, res["se_im"])
+
+
 def test_frequency_branch_skin_depth(orc):
     """A model entered by frequency, conductivity and a length unit in metres
     (the TE equation of Sec. 2.1 as measured): air over a 100 ohm m
