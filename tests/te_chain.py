@@ -102,24 +102,36 @@ class ZStripChain:
         return complex(self._interp(np.array([float(z)]), np.array([1.0 + 0.0j])) @ self.u)
 
 
-def z_strip_problem(alpha, dt, zs, paths, precision=0, seed=21, g_top=1.0, g_bottom=0.3 + 0.2j, M=4096):
+def z_strip_problem(alpha, dt, zs, paths, precision=0, seed=21, g_top=1.0, g_bottom=0.3 + 0.2j, M=4096,
+                    layers=()):
     """The strip of ZStripChain as a request: air (z < 0) over ground of rate
     alpha, z in [-1, 1], the walls y = +-40 out of reach; g_top at z = -1,
     g_bottom at z = 1 (linear in z on the side walls, which no walk reaches);
-    nodes at (0, z) for z in zs."""
+    nodes at (0, z) for z in zs.  layers: (z0, z1, sigma) boxes across the
+    whole strip below the air, first match first (the background has sigma 1)."""
     from paper_1603_09311_amd import workloads as W
     walls = (-40.0, 40.0, -1.0, 1.0)
+    regions = [W.Region(W.HALF_Z_LT, (0.0,), 0.0)]
+    regions += [W.Region(W.BOX, (-50.0, 50.0, float(z0), float(z1)), float(sg)) for z0, z1, sg in layers]
     gt, gb = complex(g_top), complex(g_bottom)
     g = W.tables_from_function(lambda y, z: gt + (gb - gt) * (np.asarray(z) + 1.0) / 2.0 + 0.0 * np.asarray(y),
                                walls, M)
     zs = np.asarray(zs, dtype=np.float64)
     nodes = np.stack([np.zeros_like(zs), zs], axis=1)
     n = nodes.shape[0]
-    return W.Problem(*walls, regions=[W.Region(W.HALF_Z_LT, (0.0,), 0.0)], sigma_background=1.0,
+    return W.Problem(*walls, regions=regions, sigma_background=1.0,
                      length_unit_m=1.0, freq_hz=0.0, alpha_direct=float(alpha), g=g, nodes=nodes,
                      path_begin=np.zeros(n, np.uint32), path_count=np.full(n, paths, np.uint32), dt=dt,
                      seed=seed, precision=precision, name="z_strip")
 
 
-def z_strip_chain(alpha, dt, g_top=1.0, g_bottom=0.3 + 0.2j, n=1200):
-    return ZStripChain(-1.0, 1.0, [-1.0, 0.0], [0.0, alpha * dt / 2.0], g_top, g_bottom, dt, n=n).solve()
+def z_strip_chain(alpha, dt, g_top=1.0, g_bottom=0.3 + 0.2j, n=1200, layers=()):
+    """The chain of z_strip_problem (layers contiguous from z = 0 down, in
+    list order)."""
+    tops, rates = [-1.0, 0.0], [0.0]
+    for z0, z1, sg in layers:
+        assert abs(z0 - tops[-1]) < 1e-15
+        rates.append(alpha * sg * dt / 2.0)
+        tops.append(z1)
+    rates.append(alpha * dt / 2.0)
+    return ZStripChain(-1.0, 1.0, tops, rates, g_top, g_bottom, dt, n=n).solve()

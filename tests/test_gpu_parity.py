@@ -852,3 +852,32 @@ def test_both_precisions_match_the_exact_scheme_on_a_strip(ctx):
         assert np.all(np.abs(d.real) <= 4.0 * r["se_re"] + 3e-5), (d, r["se_re"])
         assert np.all(np.abs(d.imag) <= 4.0 * r["se_im"] + 3e-5), (d, r["se_im"])
         assert np.all(r["unfinished"] == 0)
+
+
+def test_generic_signature_matches_the_exact_scheme_on_a_strip(ctx):
+    """The generic signature's walkers as discrete schemes: air over two
+    full-width layers (sigma 3 on 0 <= z < 0.3, 0.5 on 0.3 <= z < 0.6) over
+    the background, three primitives, so the FP32-mixed walk looks regions up
+    in the sigma grid (in LDS, in global memory, or by the primitive loop) and
+    sums fixed-point phases; the FP64 walk loops over the primitives.  Each
+    against the scheme's exact expectation (te_chain) at dt = 1e-2 and 10^7
+    paths per node, within 4 SE per component plus 3e-5; the three FP32
+    lookups give the same records bit for bit."""
+    import te_chain as TC
+    layers = ((0.0, 0.3, 3.0), (0.3, 0.6, 0.5))
+    zs = (-0.5, -0.05, 0.05, 0.32, 0.7)
+    chain = TC.z_strip_chain(20.0, 1e-2, layers=layers)
+    exact = np.array([chain.value(z) for z in zs])
+    p64 = TC.z_strip_problem(20.0, 1e-2, zs, 10_000_000, precision=W.FP64, layers=layers)
+    p32 = TC.z_strip_problem(20.0, 1e-2, zs, 10_000_000, precision=W.FP32_MIXED, layers=layers)
+    runs = [("fp64", ctx.solve(p64)), ("fp32 lds grid", ctx.solve(p32)),
+            ("fp32 global grid", ctx.solve(p32, flags=sdd.SDD_FLAG_NO_LDS_GRID)),
+            ("fp32 primitive loop", ctx.solve(p32, flags=sdd.SDD_FLAG_NO_SIGMA_GRID))]
+    for name, r in runs:
+        d = r["mean"] - exact
+        log(f"layered strip {name}: diff/se re {d.real / r['se_re']} im {d.imag / r['se_im']}")
+        assert np.all(np.abs(d.real) <= 4.0 * r["se_re"] + 3e-5), (name, d, r["se_re"])
+        assert np.all(np.abs(d.imag) <= 4.0 * r["se_im"] + 3e-5), (name, d, r["se_im"])
+        assert np.all(r["unfinished"] == 0)
+    for name, r in runs[2:]:
+        assert np.array_equal(r["mean"], runs[1][1]["mean"]) and np.array_equal(r["steps"], runs[1][1]["steps"]), name
