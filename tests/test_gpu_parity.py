@@ -881,3 +881,23 @@ def test_generic_signature_matches_the_exact_scheme_on_a_strip(ctx):
         assert np.all(r["unfinished"] == 0)
     for name, r in runs[2:]:
         assert np.array_equal(r["mean"], runs[1][1]["mean"]) and np.array_equal(r["steps"], runs[1][1]["steps"]), name
+
+
+def test_multi_frequency_one_walk_matches_the_exact_scheme_on_a_strip(ctx):
+    """The multi-frequency fan-out as a discrete scheme: one FP32-mixed walk
+    on the strip (air over ground) weighted for rates 5, 20 and 80 (the
+    walk's own rate 20 sets the phase scale), each against the exact
+    expectation of the scheme at that rate (te_chain), dt = 1e-2 and 10^7
+    paths per node: within 4 SE per component plus 3e-5."""
+    import te_chain as TC
+    zs = (-0.5, -0.05, 0.05, 0.5)
+    rates = (5.0, 20.0, 80.0)
+    p = TC.z_strip_problem(20.0, 1e-2, zs, 10_000_000, precision=W.FP32_MIXED)
+    got = ctx.solve_multi_freq(p, list(rates), [p.g] * len(rates))
+    for alpha, r in zip(rates, got):
+        chain = TC.z_strip_chain(alpha, 1e-2)
+        exact = np.array([chain.value(z) for z in zs])
+        d = r["mean"] - exact
+        log(f"strip fan-out rate {alpha}: diff/se re {d.real / r['se_re']} im {d.imag / r['se_im']}")
+        assert np.all(np.abs(d.real) <= 4.0 * r["se_re"] + 3e-5), (alpha, d, r["se_re"])
+        assert np.all(np.abs(d.imag) <= 4.0 * r["se_im"] + 3e-5), (alpha, d, r["se_im"])
