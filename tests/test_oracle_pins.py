@@ -359,6 +359,36 @@ def test_discrete_scheme_exact_on_a_strip(orc):
     assert np.all(np.abs(d_im) <= 4.0 * res["se_im"] + 3e-5), (d_im, res["se_im"])
 
 
+def _strip_continuum(alpha, g_top, g_bottom, z):
+    """Air (z < 0, E linear) over ground (E'' = i alpha E) on -1 < z < 1, E
+    and E' continuous at z = 0, E = g_top at z = -1 and g_bottom at z = 1."""
+    k = np.sqrt(1j * alpha)
+    M = np.array([[1, -1, 0, 0], [0, 0, np.exp(k), np.exp(-k)], [1, 0, -1, -1], [0, 1, -k, k]], dtype=complex)
+    a0, a1, A, B = np.linalg.solve(M, np.array([g_top, g_bottom, 0, 0], dtype=complex))
+    z = np.asarray(z, dtype=np.float64)
+    return np.where(z < 0, a0 + a1 * z, A * np.exp(k * z) + B * np.exp(-k * z))
+
+
+def test_scheme_is_first_order_on_a_strip():
+    """The scheme as this build reads it converges to the PDE (Eq. 1 with
+    the walk's generator, Eqs. 7-8): its exact expectation on the strip
+    (te_chain, no sampling; the oracle matches it, test above) has a bias
+    against the 1-D continuum solution that falls at first order in dt
+    (largest 3.2e-3 at dt = 4e-3 and 8.2e-4 at 1e-3, ratio 3.9), and the
+    first-order extrapolation (4 u(dt/4) - u(dt)) / 3 lands on the continuum
+    solution within a fraction of the smaller bias (1.2e-4, 0.14 of it; the
+    rest is higher order)."""
+    import te_chain as TC
+    zs = np.array([-0.5, -0.05, 0.05, 0.5])
+    ex = _strip_continuum(20.0, 1.0, 0.3 + 0.2j, zs)
+    u1 = np.array([TC.z_strip_chain(20.0, 4e-3).value(z) for z in zs])
+    u4 = np.array([TC.z_strip_chain(20.0, 1e-3).value(z) for z in zs])
+    b1, b4 = np.abs(u1 - ex).max(), np.abs(u4 - ex).max()
+    assert 1e-3 < b1 < 5e-3 and 3.0 < b1 / b4 < 5.0, (b1, b4)
+    extrap = (4.0 * u4 - u1) / 3.0
+    assert np.abs(extrap - ex).max() < 0.25 * b4, (np.abs(extrap - ex).max(), b4)
+
+
 def test_frequency_branch_skin_depth(orc):
     """A model entered by frequency, conductivity and a length unit in metres
     (the TE equation of Sec. 2.1 as measured): air over a 100 ohm m
