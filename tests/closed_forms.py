@@ -118,6 +118,25 @@ def mt_te_response_jump(e_minus, e_mid, e_plus, h, length_unit_m, freq_hz, sigma
     return np.abs(z) ** 2 / (w * MU0), np.degrees(np.angle(z))
 
 
+def kappa_strip(lam, kappa, a, g_left, g_right, y):
+    """(1/2)(kappa u')' - lam u = 0 on -a < y < a with kappa_i, lam_i
+    constant on y < 0 (i = 0) and y >= 0 (i = 1), u(-a) = g_left,
+    u(a) = g_right, u and the flux kappa u' continuous at 0: on each side
+    u = A_i cosh(k_i y) + B_i sinh(k_i y) / k_i, k_i = sqrt(2 lam_i / kappa_i)
+    (B_i y when lam_i = 0)."""
+    k = [np.sqrt(2.0 * complex(lam[i]) / kappa[i]) for i in range(2)]
+
+    def S(kk, yy):
+        return yy if kk == 0 else np.sinh(kk * yy) / kk
+    M = np.array([[np.cosh(-k[0] * a), S(k[0], -a), 0, 0],
+                  [0, 0, np.cosh(k[1] * a), S(k[1], a)],
+                  [1, 0, -1, 0],
+                  [0, kappa[0], 0, -kappa[1]]], dtype=complex)
+    A0, B0, A1, B1 = np.linalg.solve(M, np.array([g_left, g_right, 0, 0], dtype=complex))
+    y = np.asarray(y, dtype=np.float64)
+    return np.where(y < 0, A0 * np.cosh(k[0] * y) + B0 * S(k[0], y), A1 * np.cosh(k[1] * y) + B1 * S(k[1], y))
+
+
 def kappa_two_sided(lam, kappa, y, z, y_if=0.0):
     """(1/2) div(kappa grad u) - lam_i u = 0 with kappa_i, lam_i constant on
     the sides y < y_if (i = 0) and y >= y_if (i = 1): u = (z + 1) f(y) with

@@ -50,10 +50,15 @@ def split_reading(dt, tg, pi_, pj, resume_own):
 
 
 class StripChain:
-    def __init__(self, a, kappa, lam, g_left, g_right, dt, n_side=600, split=split_reading):
+    def __init__(self, a, kappa, lam, g_left, g_right, dt, n_side=600, split=split_reading, swap_p=False,
+                 own_radius_each_side=False):
+        """swap_p and own_radius_each_side evaluate two other readings of
+        Eqs. 11-12 (for comparison): the resume probabilities exchanged, and
+        each disc with the radius sqrt(kappa dt) of its own side."""
         self.a, self.kappa, self.lam, self.dt = float(a), tuple(map(float, kappa)), tuple(map(complex, lam)), float(dt)
         self.gl, self.gr = complex(g_left), complex(g_right)
         self.split = split
+        self.swap_p, self.own_radius = swap_p, own_radius_each_side
         # grid: side 0 nodes in [-a, 0], side 1 in [0, a]; unknowns at every node
         # (the end nodes carry values only through the interpolation)
         self.y0 = np.linspace(-a, 0.0, n_side + 1)
@@ -140,11 +145,12 @@ class StripChain:
         sn = np.where(yn < 0.0, 0, 1)
         di = abs(y)
         h = s
-        pi_ = ki / (ki + kj)
+        hj = math.sqrt(kj * dt) if self.own_radius else h
+        pi_ = (kj if self.swap_p else ki) / (ki + kj)
         pj = 1.0 - pi_
         towards = 1.0 if si == 0 else -1.0
         own_row, own_b = self._disc_rows(-towards * h, h)
-        oth_row, oth_b = self._disc_rows(towards * h, h)
+        oth_row, oth_b = self._disc_rows(towards * hj, hj)
 
         def resume(tg):
             """Expected factor of each resume side for interface times tg (array)."""
