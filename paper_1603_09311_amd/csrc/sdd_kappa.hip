@@ -366,8 +366,51 @@ __device__ __forceinline__ bool kstep32(const KReq &Q, KWalker32 &W, uint32_t wa
   return false;
 }
 
-// Two steps per normal draw (a walker is at an even step at the start of a
-// pair).  pair() returns 0 running, 1 exited (X), 2 step cap.
+// kstep32 for a step that none of its tests flags (no outer crossing or
+// bridge candidate, no interface crossing or bridge candidate): the same
+// proposal and the same tests, then the move and the count of the step's
+// side.  Returns false, leaving W as it was, when the step needs the full
+// logic; kstep32 on the same words then takes it.
+__device__ __forceinline__ bool kstep32_plain(const KReq &Q, KWalker32 &W, uint32_t wa, uint32_t wb) {
+  const bool s1 = !(W.a < Q.fa_if);
+  const float K = s1 ? Q.fK[1] : Q.fK[0];
+  const float thr = s1 ? Q.fthr[1] : Q.fthr[0];
+  const float rk = K * __builtin_amdgcn_sqrtf(-__builtin_amdgcn_logf(u01_k(wa)));
+  const float ang = one_frac_k(wb);
+  const float an = __builtin_fmaf(__builtin_amdgcn_cosf(ang), rk, W.a);
+  const float bn = __builtin_fmaf(__builtin_amdgcn_sinf(ang), rk, W.b);
+  const bool upy = W.a > 0.f, upz = W.b > 0.f;
+  const float d0y = Q.fhy - fabsf(W.a), d0z = Q.fhz - fabsf(W.b);
+  const float d1y = upy ? (Q.fhy - an) : (Q.fhy + an);
+  const float d1z = upz ? (Q.fhz - bn) : (Q.fhz + bn);
+  const bool cy = d1y <= 0.f, cz = d1z <= 0.f;
+  const float qy = (2.f * d0y) * d1y, qz = (2.f * d0z) * d1z;
+  const bool by = !cy && (qy <= thr), bz = !cz && (qz <= thr);
+  const bool sn1 = !(an < Q.fa_if);
+  const bool jump = !Q.equal_kappa;
+  const float e0 = fabsf(W.a - Q.fa_if), e1 = fabsf(an - Q.fa_if);
+  const bool crossed = jump && (sn1 != s1);
+  const bool bridge_if = jump && !crossed && ((2.f * e0) * e1 <= thr);
+  if (cy || cz || by || bz || crossed || bridge_if) return false;
+  // unflagged: the proposal's side is the step's (with a jump in kappa the
+  // proposal stayed on the start's side)
+  if (sn1) W.c1 += 1u; else W.c0 += 1u;
+  W.a = an;
+  W.b = bn;
+  return true;
+}
+
+// Lanes whose step is flagged park it until the wave runs the full step
+// logic for all parked lanes at once: when kParkLanes lanes are parked,
+// kParkIters iterations after a lane first parked, or when no lane is left
+// that can step.  Near the interface a few lanes of a wave are flagged in
+// most steps; run step by step, every flagged step would cost the wave the
+// whole branch (a second Philox call, a bridge, a resume).  A record depends
+// only on its path's random numbers, so parking changes when a step runs,
+// not what it computes.
+constexpr uint32_t kParkLanes = 16;
+constexpr uint32_t kParkIters = 8;
+
 struct K32 {
   using Walker = KWalker32;
   static __device__ __forceinline__ void start(const KReq &Q, Walker &W, double2 xy, uint32_t p, uint32_t node,
@@ -382,16 +425,6 @@ struct K32 {
     W.rec = rec;
     W.pp = philox_path(p, node, k0);
   }
-  static __device__ __forceinline__ int pair(const KReq &Q, Walker &W, KExit &X) {
-    const uint64_t P = (uint64_t)kM0 * (uint64_t)(W.n >> 1);
-    const uint4 w = philox_pp(P, Q.ctr3, W.pp, Q.key0, Q.key1);
-    if (kstep32(Q, W, w.x, w.y, X)) return 1;
-    W.n += 1u;
-    if (W.n >= Q.max_steps) return 2;
-    if (kstep32(Q, W, w.z, w.w, X)) return 1;
-    W.n += 1u;
-    return W.n >= Q.max_steps ? 2 : 0;
-  }
   static __device__ __forceinline__ PathRec finish(const KReq &Q, const Walker &W, const KExit &X) {
     const double T0 = Q.dt * (double)W.c0 + W.f0;
     const double T1 = Q.dt * (double)W.c1 + W.f1;
@@ -399,8 +432,8 @@ struct K32 {
   }
 };
 
-// The two walks keep separate kernels (the same loop), so that each gets the
-// register allocation of its own step.
+// The two walks keep separate kernels, so that each gets the register
+// allocation of its own step; the FP32-mixed one parks flagged steps.
 __global__ void __launch_bounds__(kKappaThreads) walk_kappa32(const KReq *__restrict__ qp) {
   using T = K32;
   const KReq &Q = *qp;
@@ -408,6 +441,10 @@ __global__ void __launch_bounds__(kKappaThreads) walk_kappa32(const KReq *__rest
   typename T::Walker W;
   bool active = false;
   bool exhausted = false;
+  bool parked = false;
+  uint32_t wz = 0, ww = 0;   // words of the odd step of the walker's current pair
+  uint32_t pa = 0, pb = 0;   // words of the parked step
+  uint32_t waited = 0;       // iterations the parked lanes have waited (wave-uniform)
   // wave-uniform tile cursor
   uint32_t t_node = 0, t_p0 = 0, t_next = 0, t_end = 0;
   uint64_t t_rec0 = 0;
@@ -445,24 +482,70 @@ __global__ void __launch_bounds__(kKappaThreads) walk_kappa32(const KReq *__rest
     }
     if (__builtin_amdgcn_ballot_w64(!active) == ~0ull) break;   // no work left for this wave
 
-    if (active) {
-      KExit X;
-      X.wall = -1;
-      const int st = T::pair(Q, W, X);
-      if (st != 0) {
-        PathRec r;
-        if (st == 1) {
-          r = T::finish(Q, W, X);
-        } else {   // step cap: max_steps steps drawn
-          r.w_re = 0.0;
-          r.w_im = 0.0;
-          r.tau = -1.0;
-          r.steps = W.n;
-          r.wall = -1;
+    // flagged steps first, every parked lane at once; a walker whose parked
+    // step was even then takes the odd one below in the same iteration, so
+    // the walkers of a wave stay at one parity
+    int st = 0;   // 0 running, 1 exited (X), 2 step cap
+    KExit X;
+    X.wall = -1;
+    const uint64_t pmask = __builtin_amdgcn_ballot_w64(parked);
+    if (pmask != 0ull) {
+      waited += 1u;
+      const bool stuck = __builtin_amdgcn_ballot_w64(active && !parked) == 0ull;
+      if ((uint32_t)__popcll(pmask) >= kParkLanes || waited >= kParkIters || stuck) {
+        waited = 0;
+        if (parked) {
+          parked = false;
+          if (kstep32(Q, W, pa, pb, X)) {
+            st = 1;
+          } else {
+            W.n += 1u;
+            if (W.n >= Q.max_steps) st = 2;
+          }
         }
-        Q.recs[W.rec] = r;
-        active = false;
       }
+    }
+    // unflagged steps: two per normal draw (steps 2k and 2k + 1 take words
+    // 0, 1 and 2, 3 of the draw at 2k)
+    if (active && !parked && st == 0) {
+      if ((W.n & 1u) == 0u) {
+        const uint64_t P = (uint64_t)kM0 * (uint64_t)(W.n >> 1);
+        const uint4 w = philox_pp(P, Q.ctr3, W.pp, Q.key0, Q.key1);
+        wz = w.z;
+        ww = w.w;
+        if (kstep32_plain(Q, W, w.x, w.y)) {
+          W.n += 1u;
+          if (W.n >= Q.max_steps) st = 2;
+        } else {
+          parked = true;
+          pa = w.x;
+          pb = w.y;
+        }
+      }
+      if (st == 0 && !parked) {
+        if (kstep32_plain(Q, W, wz, ww)) {
+          W.n += 1u;
+          if (W.n >= Q.max_steps) st = 2;
+        } else {
+          parked = true;
+          pa = wz;
+          pb = ww;
+        }
+      }
+    }
+    if (st != 0) {
+      PathRec r;
+      if (st == 1) {
+        r = T::finish(Q, W, X);
+      } else {   // step cap: max_steps steps drawn
+        r.w_re = 0.0;
+        r.w_im = 0.0;
+        r.tau = -1.0;
+        r.steps = W.n;
+        r.wall = -1;
+      }
+      Q.recs[W.rec] = r;
+      active = false;
     }
   }
 }
