@@ -220,6 +220,7 @@ __device__ __forceinline__ bool kstep(const KReq &Q, KWalker &W, double n0, doub
 // ---------------------------------------------------------------------------
 struct KWalker32 {
   float a, b;        // y - ymid, z - zmid
+  float m;           // kdist32 of (a, b)
   uint32_t c0, c1;   // full steps on side 0 / side 1
   double f0, f1;     // the rest of the occupation times (interface shares, exit fraction)
   uint32_t n;
@@ -237,10 +238,37 @@ __device__ __forceinline__ float neglog_k(uint32_t w) {
   return -0.69314718055994531f * __builtin_amdgcn_logf(u01_k(w));
 }
 
-__device__ __forceinline__ bool kstep32(const KReq &Q, KWalker32 &W, uint32_t wa, uint32_t wb, KExit &X) {
+// The per-side FP32 constants of the walk in scalar registers: a choice
+// between two fields of the request by the lane's side is otherwise compiled
+// to a per-lane load from the request.
+__device__ __forceinline__ float uni_f(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
+}
+struct KSide32 {
+  float K[2], thr[2], kdt[2], kappa[2], p[2], s[2], r[2];
+  __device__ __forceinline__ void load(const KReq &Q) {
+    for (int i = 0; i < 2; ++i) {
+      K[i] = uni_f(Q.fK[i]);
+      thr[i] = uni_f(Q.fthr[i]);
+      // the least float r with fl(2 r r) > thr: two distances above r give a
+      // rounded product 2 d0 d1 above thr (rounding is monotone)
+      float rr = __builtin_sqrtf(0.5f * thr[i]);
+      while (rr > 0.f && (2.f * rr) * rr > thr[i]) rr = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, rr) - 1u);
+      while (!((2.f * rr) * rr > thr[i])) rr = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, rr) + 1u);
+      r[i] = uni_f(rr);
+      kdt[i] = uni_f(Q.fkdt[i]);
+      kappa[i] = uni_f(Q.fkappa[i]);
+      p[i] = uni_f(Q.fp[i]);
+      s[i] = uni_f(Q.fs[i]);
+    }
+  }
+};
+
+__device__ __forceinline__ bool kstep32(const KReq &Q, const KSide32 &S, KWalker32 &W, uint32_t wa, uint32_t wb,
+                                        KExit &X) {
   const bool s1 = !(W.a < Q.fa_if);
-  const float K = s1 ? Q.fK[1] : Q.fK[0];
-  const float thr = s1 ? Q.fthr[1] : Q.fthr[0];
+  const float K = s1 ? S.K[1] : S.K[0];
+  const float thr = s1 ? S.thr[1] : S.thr[0];
   const float rk = K * __builtin_amdgcn_sqrtf(-__builtin_amdgcn_logf(u01_k(wa)));
   const float ang = one_frac_k(wb);
   const float an = __builtin_fmaf(__builtin_amdgcn_cosf(ang), rk, W.a);
@@ -267,7 +295,7 @@ __device__ __forceinline__ bool kstep32(const KReq &Q, KWalker32 &W, uint32_t wa
     const uint64_t Pn = (uint64_t)kM0 * (uint64_t)W.n;
     u = philox_pp(Pn, Q.ctr3 + 1u, W.pp, Q.key0, Q.key1);
   }
-  const float kdt = s1 ? Q.fkdt[1] : Q.fkdt[0];
+  const float kdt = s1 ? S.kdt[1] : S.kdt[0];
   bool hy = cy, hz = cz;
   float fy = 0.f, fz = 0.f;
   if (by) {
@@ -310,7 +338,7 @@ __device__ __forceinline__ bool kstep32(const KReq &Q, KWalker32 &W, uint32_t wa
   if (crossed) {
     tg = Q.fdt * (e0 * __builtin_amdgcn_rcpf(fabsf(an - W.a)));
   } else if (bridge_if) {
-    const float ki = s1 ? Q.fkappa[1] : Q.fkappa[0];
+    const float ki = s1 ? S.kappa[1] : S.kappa[0];
     tg = ((2.f * e0) * e1) * __builtin_amdgcn_rcpf(ki * neglog_k(u.z));
     reached = tg <= Q.fdt;
   }
@@ -322,8 +350,8 @@ __device__ __forceinline__ bool kstep32(const KReq &Q, KWalker32 &W, uint32_t wa
   }
 
   // resume inside a disc touching the interface from side i or side j
-  const float pi = s1 ? Q.fp[1] : Q.fp[0];
-  const float h = s1 ? Q.fs[1] : Q.fs[0];
+  const float pi = s1 ? S.p[1] : S.p[0];
+  const float h = s1 ? S.s[1] : S.s[0];
   const float zg = __builtin_fmaf(fminf(tg * Q.frdt, 1.f), bn - W.b, W.b);   // interface point
   const float towards = s1 ? -1.f : 1.f;
   const double half = 0.5 * (Q.dt - (double)tg);
@@ -366,37 +394,37 @@ __device__ __forceinline__ bool kstep32(const KReq &Q, KWalker32 &W, uint32_t wa
   return false;
 }
 
-// kstep32 for a step that none of its tests flags (no outer crossing or
-// bridge candidate, no interface crossing or bridge candidate): the same
-// proposal and the same tests, then the move and the count of the step's
-// side.  Returns false, leaving W as it was, when the step needs the full
-// logic; kstep32 on the same words then takes it.
-__device__ __forceinline__ bool kstep32_plain(const KReq &Q, KWalker32 &W, uint32_t wa, uint32_t wb) {
+// The least distance of (a, b) to the outer boundary and (kappa jumping) to
+// the interface.
+__device__ __forceinline__ float kdist32(const KReq &Q, float a, float b) {
+  const float e = Q.equal_kappa ? __builtin_inff() : fabsf(a - Q.fa_if);
+  return fminf(fminf(Q.fhy - fabsf(a), Q.fhz - fabsf(b)), e);
+}
+
+// kstep32 for a step that none of its tests flags: the same proposal, then
+// a screen that passes only steps kstep32 would not flag (no crossing of the
+// interface, and the start and the proposal both farther than r from the
+// outer boundary and the interface: each distance kstep32 takes is at least
+// the one here, so every product 2 d0 d1 it forms rounds above thr and no
+// distance is <= 0), the move and the count of the step's side (with a jump
+// in kappa the proposal stayed on the start's side).  Returns false, leaving
+// W as it was, for any other step; kstep32 on the same words then takes it.
+__device__ __forceinline__ bool kstep32_plain(const KReq &Q, const KSide32 &S, KWalker32 &W, uint32_t wa, uint32_t wb) {
   const bool s1 = !(W.a < Q.fa_if);
-  const float K = s1 ? Q.fK[1] : Q.fK[0];
-  const float thr = s1 ? Q.fthr[1] : Q.fthr[0];
+  const float K = s1 ? S.K[1] : S.K[0];
+  const float r = s1 ? S.r[1] : S.r[0];
   const float rk = K * __builtin_amdgcn_sqrtf(-__builtin_amdgcn_logf(u01_k(wa)));
   const float ang = one_frac_k(wb);
   const float an = __builtin_fmaf(__builtin_amdgcn_cosf(ang), rk, W.a);
   const float bn = __builtin_fmaf(__builtin_amdgcn_sinf(ang), rk, W.b);
-  const bool upy = W.a > 0.f, upz = W.b > 0.f;
-  const float d0y = Q.fhy - fabsf(W.a), d0z = Q.fhz - fabsf(W.b);
-  const float d1y = upy ? (Q.fhy - an) : (Q.fhy + an);
-  const float d1z = upz ? (Q.fhz - bn) : (Q.fhz + bn);
-  const bool cy = d1y <= 0.f, cz = d1z <= 0.f;
-  const float qy = (2.f * d0y) * d1y, qz = (2.f * d0z) * d1z;
-  const bool by = !cy && (qy <= thr), bz = !cz && (qz <= thr);
+  const float m1 = kdist32(Q, an, bn);
   const bool sn1 = !(an < Q.fa_if);
-  const bool jump = !Q.equal_kappa;
-  const float e0 = fabsf(W.a - Q.fa_if), e1 = fabsf(an - Q.fa_if);
-  const bool crossed = jump && (sn1 != s1);
-  const bool bridge_if = jump && !crossed && ((2.f * e0) * e1 <= thr);
-  if (cy || cz || by || bz || crossed || bridge_if) return false;
-  // unflagged: the proposal's side is the step's (with a jump in kappa the
-  // proposal stayed on the start's side)
+  const bool crossed = !Q.equal_kappa && (sn1 != s1);
+  if (!(fminf(W.m, m1) > r) || crossed) return false;
   if (sn1) W.c1 += 1u; else W.c0 += 1u;
   W.a = an;
   W.b = bn;
+  W.m = m1;
   return true;
 }
 
@@ -408,7 +436,7 @@ __device__ __forceinline__ bool kstep32_plain(const KReq &Q, KWalker32 &W, uint3
 // whole branch (a second Philox call, a bridge, a resume).  A record depends
 // only on its path's random numbers, so parking changes when a step runs,
 // not what it computes.
-constexpr uint32_t kParkLanes = 16;
+constexpr uint32_t kParkLanes = 24;
 constexpr uint32_t kParkIters = 8;
 
 struct K32 {
@@ -417,6 +445,7 @@ struct K32 {
                                                uint64_t rec, uint32_t k0) {
     W.a = (float)(xy.x - Q.ymid);
     W.b = (float)(xy.y - Q.zmid);
+    W.m = kdist32(Q, W.a, W.b);
     W.c0 = 0u;
     W.c1 = 0u;
     W.f0 = 0.0;
@@ -437,6 +466,8 @@ struct K32 {
 __global__ void __launch_bounds__(kKappaThreads) walk_kappa32(const KReq *__restrict__ qp) {
   using T = K32;
   const KReq &Q = *qp;
+  KSide32 S;
+  S.load(Q);
   const uint32_t lane = __lane_id();
   typename T::Walker W;
   bool active = false;
@@ -496,9 +527,10 @@ __global__ void __launch_bounds__(kKappaThreads) walk_kappa32(const KReq *__rest
         waited = 0;
         if (parked) {
           parked = false;
-          if (kstep32(Q, W, pa, pb, X)) {
+          if (kstep32(Q, S, W, pa, pb, X)) {
             st = 1;
           } else {
+            W.m = kdist32(Q, W.a, W.b);
             W.n += 1u;
             if (W.n >= Q.max_steps) st = 2;
           }
@@ -513,7 +545,7 @@ __global__ void __launch_bounds__(kKappaThreads) walk_kappa32(const KReq *__rest
         const uint4 w = philox_pp(P, Q.ctr3, W.pp, Q.key0, Q.key1);
         wz = w.z;
         ww = w.w;
-        if (kstep32_plain(Q, W, w.x, w.y)) {
+        if (kstep32_plain(Q, S, W, w.x, w.y)) {
           W.n += 1u;
           if (W.n >= Q.max_steps) st = 2;
         } else {
@@ -523,7 +555,7 @@ __global__ void __launch_bounds__(kKappaThreads) walk_kappa32(const KReq *__rest
         }
       }
       if (st == 0 && !parked) {
-        if (kstep32_plain(Q, W, wz, ww)) {
+        if (kstep32_plain(Q, S, W, wz, ww)) {
           W.n += 1u;
           if (W.n >= Q.max_steps) st = 2;
         } else {
