@@ -731,6 +731,12 @@ __device__ __forceinline__ PathRec finish32(const DevReq &Q, const X32 &X) {
   return r;
 }
 
+// finish32 called out of line by the generic signatures' walkers: inlined,
+// its FP64 constants and table pointers stay live in scalar registers across
+// the walker loop, where the sigma grid's parameters push loop values into
+// spill slots.
+__device__ __noinline__ PathRec finish32_outline(const DevReq &Q, const X32 &X) { return finish32(Q, X); }
+
 __device__ __forceinline__ int32_t fbits(float x) { return __builtin_bit_cast(int32_t, x); }
 
 // Two steps (one Philox call).  Both proposals are made first; a step needs
@@ -826,7 +832,8 @@ template <int SIG> struct F32 {
     return iterate32<SIG>(Q, U, W, X);
   }
   static __device__ __forceinline__ PathRec finish(const DevReq &Q, const Walker &, const Exit &X) {
-    return finish32(Q, X);
+    if constexpr (Reg32<SIG>::kGeneric) return finish32_outline(Q, X);
+    else return finish32(Q, X);
   }
   // counts and FP32 values all widen to doubles exactly; the generic
   // signature's 64-bit phase sum and increment go to the integer fields
