@@ -116,11 +116,11 @@ __device__ __forceinline__ bool kstep(const KReq &Q, KWalker &W, double n0, doub
   bool hy = cy, hz = cz;
   double fy = 0.0, fz = 0.0;
   if (by) {
-    const double L = -log(u01_64(u.x));
+    const double L = -log_unit64(u01_64(u.x));
     if (qy <= kdt * L) { hy = true; fy = qy / (kdt * L); }
   }
   if (bz) {
-    const double L = -log(u01_64(u.y));
+    const double L = -log_unit64(u01_64(u.y));
     if (qz <= kdt * L) { hz = true; fz = qz / (kdt * L); }
   }
   if (hy || hz) {
@@ -154,7 +154,7 @@ __device__ __forceinline__ bool kstep(const KReq &Q, KWalker &W, double n0, doub
     tg = Q.dt * fabs(e0 / (yn - W.y));
   } else if (bridge_if) {
     const double ki = s1 ? Q.kappa[1] : Q.kappa[0];
-    tg = ((-2.0 * e0) * e1) / (ki * log(u01_64(u.z)));
+    tg = ((-2.0 * e0) * e1) / (ki * log_unit64(u01_64(u.z)));
     reached = tg <= Q.dt;
   }
   if (!reached) {
@@ -184,11 +184,9 @@ __device__ __forceinline__ bool kstep(const KReq &Q, KWalker &W, double n0, doub
   W.T1 = W.T1 + (s1 ? add_i : add_j);
   const uint64_t Pn = (uint64_t)kM0 * (uint64_t)W.n;
   const uint4 d = philox_pp(Pn, Q.ctr3 + 2u, W.pp, Q.key0, Q.key1);
-  const double two_pi = 6.283185307179586476925286766559;
   const double r = s * sqrt(u01_64(d.x));
-  const double th = two_pi * u01_64(d.y);
   double sth, cth;
-  sincos(th, &sth, &cth);
+  sincos_2pi64(u01_64(d.y), sth, cth);   // the angle 2 pi u
   const double y = cyc + r * cth;
   const double z = zg + r * sth;
   if (!(y > Q.y_lo && y < Q.y_hi && z > Q.z_lo && z < Q.z_hi)) {

@@ -392,6 +392,17 @@ __device__ __forceinline__ void finish_weight(const DevReq &Q, int wall, double 
   }
 }
 
+// finish_weight called out of line, for the walkers that hold many values
+// across their loop (the FP64 walks, the generic signatures): inlined, the
+// table lookup and the FP64 sine and cosine of the phase keep their constants
+// and pointers live in scalar registers through the loop, which pushes loop
+// values into spill slots.  Arguments and result by value (no stack copy).
+__device__ __noinline__ double2 finish_weight_outline(const DevReq &Q, int wall, double t, double S) {
+  PathRec r;
+  finish_weight(Q, wall, t, S, r);
+  return make_double2(r.w_re, r.w_im);
+}
+
 __device__ __forceinline__ PathRec unfinished_rec(uint32_t steps) {
   PathRec r;
   r.w_re = 0.0;
@@ -473,11 +484,11 @@ __device__ __forceinline__ bool exit64(const U64<SIG> &U, const W64 &W, double y
     const uint64_t Pn = (W.P << 1) + ((W.n & 1u) ? (uint64_t)kM0 : 0ull);   // M0 * n
     const uint4 b = philox_pp(Pn, U.ctr3 + 1u, W.pp, U.k0, U.k1);
     if (ny) {
-      const double L = -log(u01_64(b.x));
+      const double L = -log_unit64(u01_64(b.x));
       if (qy <= U.dt * L) { hy = true; fy = qy / (U.dt * L); }
     }
     if (nz) {
-      const double L = -log(u01_64(b.y));
+      const double L = -log_unit64(u01_64(b.y));
       if (qz <= U.dt * L) { hz = true; fz = qz / (U.dt * L); }
     }
   }
@@ -529,7 +540,9 @@ __device__ __forceinline__ bool step64(const DevReq &Q, const U64<SIG> &U, W64 &
 __device__ __forceinline__ PathRec finish64(const DevReq &Q, const W64 &W, const ExitInfo<double> &X) {
   const double S = W.S + W.cc * X.f;
   PathRec r;
-  finish_weight(Q, X.wall, X.t, S, r);
+  const double2 w = finish_weight_outline(Q, X.wall, X.t, S);
+  r.w_re = w.x;
+  r.w_im = w.y;
   r.tau = ((double)W.n + X.f) * Q.dt;
   r.steps = W.n + 1u;
   r.wall = X.wall;
@@ -717,6 +730,7 @@ __device__ __forceinline__ void advance32(const DevReq &Q, const U32<SIG> &U, W3
   W.d0z = e1z;
 }
 
+template <bool kOutline>
 __device__ __forceinline__ PathRec finish32(const DevReq &Q, const X32 &X) {
   const double S = X.S;
   const bool along_y = (X.wall == 0) || (X.wall == 2);
@@ -724,18 +738,18 @@ __device__ __forceinline__ PathRec finish32(const DevReq &Q, const X32 &X) {
   const double lo = along_y ? Q.y_lo : Q.z_lo, hi = along_y ? Q.y_hi : Q.z_hi;
   t = t < lo ? lo : (t > hi ? hi : t);
   PathRec r;
-  finish_weight(Q, X.wall, t, S, r);
+  if constexpr (kOutline) {
+    const double2 w = finish_weight_outline(Q, X.wall, t, S);
+    r.w_re = w.x;
+    r.w_im = w.y;
+  } else {
+    finish_weight(Q, X.wall, t, S, r);
+  }
   r.tau = ((double)X.n + (double)X.f) * Q.dt;
   r.steps = X.n + 1u;
   r.wall = X.wall;
   return r;
 }
-
-// finish32 called out of line by the generic signatures' walkers: inlined,
-// its FP64 constants and table pointers stay live in scalar registers across
-// the walker loop, where the sigma grid's parameters push loop values into
-// spill slots.
-__device__ __noinline__ PathRec finish32_outline(const DevReq &Q, const X32 &X) { return finish32(Q, X); }
 
 __device__ __forceinline__ int32_t fbits(float x) { return __builtin_bit_cast(int32_t, x); }
 
@@ -832,8 +846,7 @@ template <int SIG> struct F32 {
     return iterate32<SIG>(Q, U, W, X);
   }
   static __device__ __forceinline__ PathRec finish(const DevReq &Q, const Walker &, const Exit &X) {
-    if constexpr (Reg32<SIG>::kGeneric) return finish32_outline(Q, X);
-    else return finish32(Q, X);
+    return finish32<Reg32<SIG>::kGeneric>(Q, X);
   }
   // counts and FP32 values all widen to doubles exactly; the generic
   // signature's 64-bit phase sum and increment go to the integer fields

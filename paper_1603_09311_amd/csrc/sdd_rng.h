@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "sdd_math64.h"
+
 namespace sdd {
 
 // ---------------------------------------------------------------------------
@@ -89,11 +91,9 @@ __device__ __forceinline__ double unid(double v) {
 __device__ __forceinline__ double u01_64(uint32_t w) { return ((double)w + 0.5) * (1.0 / 4294967296.0); }
 
 __device__ __forceinline__ void normals64(uint32_t a, uint32_t b, double &n0, double &n1) {
-  const double two_pi = 6.283185307179586476925286766559;
-  const double r = sqrt(-2.0 * log(u01_64(a)));
-  const double th = two_pi * u01_64(b);
+  const double r = sqrt(-2.0 * log_unit64(u01_64(a)));
   double sn, cs;
-  sincos(th, &sn, &cs);   // one argument reduction for both
+  sincos_2pi64(u01_64(b), sn, cs);   // the angle 2 pi u, both from one reduction
   n0 = r * cs;
   n1 = r * sn;
 }
