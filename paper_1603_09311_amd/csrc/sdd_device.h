@@ -154,6 +154,7 @@ struct DevReq {
   //   kSigZY:   [z0, y1]                  + half-space y < y1
   //   kSigZBox: [z0, y0, y1, zb0, zb1]    + box
   //   kSigZTri: [z0, A0,B0,C0, A1,B1,C1, A2,B2,C2]  + triangle, edges A a + B b + C
+  //             (oriented: the interior is e >= 0 on all three)
   int32_t sig;
   // 1: finished paths record the phase and the exit point instead of the
   // weight (w_re = S at this request's frequency, w_im = tangential exit
@@ -180,7 +181,8 @@ struct DevReq {
   double pd[kMaxPrims][6];    // FP64 geometry of the model's primitives
   // FP32 geometry relative to the centre in units of K: half-plane [c], box
   // [y0, y1, z0, z1], triangle its three edges as (A, B, C), edge k from
-  // vertex k to vertex k + 1: e = fma(A, a, fma(B, b, C))
+  // vertex k to vertex k + 1: e = fma(A, a, fma(B, b, C)), all three negated
+  // for a clockwise triangle so that the interior is e >= 0
   float pf[kMaxPrims][kPfStride];
   const DevModel *model;      // resident model the primitives were taken from
   // sigma grid of the FP32 generic signature (null: the primitive loop); cell

@@ -92,23 +92,26 @@ template <class R> struct ExitInfo {
 // Primitives in list order, the first match wins, else the background.
 // ---------------------------------------------------------------------------
 
-// Closed triangle: every edge function >= 0 or every one <= 0 (either
-// orientation).  FP64: the edge functions from the vertices (the plain
-// definition); FP32: edge k from its (A, B, C), e = fma(A, y, fma(B, z, C)),
-// the expression the sigma grid's lines use.
+// Closed triangle.  FP64: every edge function from the vertices >= 0 or
+// every one <= 0 (either orientation; the plain definition).  FP32: edge k
+// from its (A, B, C), e = fma(A, y, fma(B, z, C)), the expression the sigma
+// grid's lines use, with the edges oriented by the host so that the interior
+// is e >= 0 on all three (the three edge functions sum to twice the signed
+// area, so no point of a triangle of positive area has all three below zero
+// beyond their rounding).
 template <class R>
 __device__ __forceinline__ bool tri_in(const R *v, R y, R z) {
-  R e0, e1, e2;
   if constexpr (sizeof(R) == 8) {
-    e0 = (v[2] - v[0]) * (z - v[1]) - (v[3] - v[1]) * (y - v[0]);
-    e1 = (v[4] - v[2]) * (z - v[3]) - (v[5] - v[3]) * (y - v[2]);
-    e2 = (v[0] - v[4]) * (z - v[5]) - (v[1] - v[5]) * (y - v[4]);
+    const R e0 = (v[2] - v[0]) * (z - v[1]) - (v[3] - v[1]) * (y - v[0]);
+    const R e1 = (v[4] - v[2]) * (z - v[3]) - (v[5] - v[3]) * (y - v[2]);
+    const R e2 = (v[0] - v[4]) * (z - v[5]) - (v[1] - v[5]) * (y - v[4]);
+    return ((e0 >= R(0)) & (e1 >= R(0)) & (e2 >= R(0))) | ((e0 <= R(0)) & (e1 <= R(0)) & (e2 <= R(0)));
   } else {
-    e0 = __builtin_fmaf(v[0], y, __builtin_fmaf(v[1], z, v[2]));
-    e1 = __builtin_fmaf(v[3], y, __builtin_fmaf(v[4], z, v[5]));
-    e2 = __builtin_fmaf(v[6], y, __builtin_fmaf(v[7], z, v[8]));
+    const R e0 = __builtin_fmaf(v[0], y, __builtin_fmaf(v[1], z, v[2]));
+    const R e1 = __builtin_fmaf(v[3], y, __builtin_fmaf(v[4], z, v[5]));
+    const R e2 = __builtin_fmaf(v[6], y, __builtin_fmaf(v[7], z, v[8]));
+    return fminf(fminf(e0, e1), e2) >= 0.f;
   }
-  return ((e0 >= R(0)) & (e1 >= R(0)) & (e2 >= R(0))) | ((e0 <= R(0)) & (e1 <= R(0)) & (e2 <= R(0)));
 }
 
 // Generic: loop over the primitives (kinds and parameters wave-uniform);
@@ -263,7 +266,7 @@ template <int SIG> struct Reg32 {
       const float e0 = __builtin_fmaf(q[1], a, __builtin_fmaf(q[2], b, q[3]));
       const float e1 = __builtin_fmaf(q[4], a, __builtin_fmaf(q[5], b, q[6]));
       const float e2 = __builtin_fmaf(q[7], a, __builtin_fmaf(q[8], b, q[9]));
-      return (fminf(fminf(e0, e1), e2) >= 0.f) | (fmaxf(fmaxf(e0, e1), e2) <= 0.f);
+      return fminf(fminf(e0, e1), e2) >= 0.f;   // edges oriented: the interior is e >= 0
     } else {
       return false;
     }

@@ -340,7 +340,7 @@ struct GLine {
   uint32_t mode;   // 0: in iff e < 0, 1: in iff e >= 0 (triangles: decided per cell)
 };
 enum GSign { kGNeg, kGPos, kGCross };
-enum GStat { kGOut, kGIn, kGOne, kGMany };
+enum GStat { kGOut, kGIn, kGOne };
 
 // The primitive's inequalities as lines, in the primitive loop's FP32
 // expressions (parameters relative to the centre): a half-plane or box side
@@ -404,19 +404,12 @@ PrimCell prim_cell(int kind, const GLine *L, int nl, double a0, double a1, doubl
   PrimCell P{kGOut, 0, {}};
   GSign c[4];
   for (int i = 0; i < nl; ++i) c[i] = classify(L[i], a0, a1, b0, b1);
-  if (kind == SDD_TRIANGLE) {
-    int pos = 0, neg = 0, cross = 0;
-    for (int i = 0; i < 3; ++i) {
-      if (c[i] == kGPos) ++pos;
-      else if (c[i] == kGNeg) ++neg;
-      else ++cross;
-    }
-    if (pos && neg) return P;                     // no point has all three edge signs equal
-    if (cross == 0) { P.status = kGIn; return P; }
-    if (cross == 3) { P.status = kGMany; return P; }   // inside: all e >= 0 or all e <= 0 (not one conjunction)
-    P.status = kGOne;
+  if (kind == SDD_TRIANGLE) {   // edges oriented: inside iff every e >= 0
     for (int i = 0; i < 3; ++i)
-      if (c[i] == kGCross) P.t[P.n++] = LineTest{L[i], neg > 0, false};   // all e >= 0 (pos) or all e <= 0 (neg)
+      if (c[i] == kGNeg) return P;   // outside on the whole cell
+    for (int i = 0; i < 3; ++i)
+      if (c[i] == kGCross) P.t[P.n++] = LineTest{L[i], false, false};
+    P.status = P.n == 0 ? kGIn : kGOne;
     return P;
   }
   for (int i = 0; i < nl; ++i) {
@@ -495,7 +488,6 @@ static void build_sigma_grid(DevReq &q, std::vector<SigmaCell> &grid, std::vecto
       int nlines = 0;
       for (int k = 0; k < np && !loop; ++k) {
         pc[k] = prim_cell(q.kind[k], lines[k], nl[k], a0 - da, a1 + da, b0 - db, b1 + db);
-        if (pc[k].status == kGMany) { loop = true; break; }
         if (pc[k].status == kGIn) { last = k; break; }
         for (int m = 0; m < pc[k].n && !loop; ++m) {
           int f = -1;
@@ -627,17 +619,22 @@ static void fill_devreq(Prepared &P) {
         q.pf[k][2] = (float)((v[2] - q.zmid) * ki); q.pf[k][3] = (float)((v[3] - q.zmid) * ki);
         break;
       default: {
-        // edge e from vertex e to vertex e + 1 as A a + B b + C
+        // edge e from vertex e to vertex e + 1 as A a + B b + C; at the third
+        // vertex every edge function equals twice the signed area, so with
+        // all three negated for a negative area the interior is e >= 0 on
+        // every edge (negation is exact before and after rounding)
         double vy[3], vz[3];
         for (int i = 0; i < 3; ++i) {
           vy[i] = (v[2 * i] - q.ymid) * ki;
           vz[i] = (v[2 * i + 1] - q.zmid) * ki;
         }
+        const double area2 = (vy[1] - vy[0]) * (vz[2] - vz[0]) - (vz[1] - vz[0]) * (vy[2] - vy[0]);
+        const double o = area2 < 0.0 ? -1.0 : 1.0;
         for (int e = 0; e < 3; ++e) {
           const int l = (e + 1) % 3;
-          q.pf[k][3 * e] = (float)(-(vz[l] - vz[e]));
-          q.pf[k][3 * e + 1] = (float)(vy[l] - vy[e]);
-          q.pf[k][3 * e + 2] = (float)((vz[l] - vz[e]) * vy[e] - (vy[l] - vy[e]) * vz[e]);
+          q.pf[k][3 * e] = (float)(o * -(vz[l] - vz[e]));
+          q.pf[k][3 * e + 1] = (float)(o * (vy[l] - vy[e]));
+          q.pf[k][3 * e + 2] = (float)(o * ((vz[l] - vz[e]) * vy[e] - (vy[l] - vy[e]) * vz[e]));
         }
       }
     }
@@ -663,19 +660,8 @@ static void fill_devreq(Prepared &P) {
       q.sigp[4] = (float)((R[1].v[3] - q.zmid) * ki);
     } else if (R[1].kind == SDD_TRIANGLE) {
       q.sig = kSigZTri;
-      // edge k from vertex k to vertex k+1 as A a + B b + C in centred
-      // coordinates (units of K)
-      double vy[3], vz[3];
-      for (int i = 0; i < 3; ++i) {
-        vy[i] = (R[1].v[2 * i] - q.ymid) * ki;
-        vz[i] = (R[1].v[2 * i + 1] - q.zmid) * ki;
-      }
-      for (int k = 0; k < 3; ++k) {
-        const int l = (k + 1) % 3;
-        q.sigp[1 + 3 * k] = (float)(-(vz[l] - vz[k]));
-        q.sigp[2 + 3 * k] = (float)(vy[l] - vy[k]);
-        q.sigp[3 + 3 * k] = (float)((vz[l] - vz[k]) * vy[k] - (vy[l] - vy[k]) * vz[k]);
-      }
+      // the three oriented edges (A, B, C) of the primitive's FP32 geometry
+      for (int i = 0; i < 9; ++i) q.sigp[1 + i] = q.pf[1][i];
     }
   }
   q.fhy = (float)(0.5 * (q.y_hi - q.y_lo) * ki);
