@@ -24,7 +24,10 @@ enum ModelSig : int32_t {
   kSigNone = 0, kSigZ = 1, kSigZY = 2, kSigZBox = 3, kSigZTri = 4, kSigGeneric = 5, kSigGenericLds = 6
 };
 
-// Resident conductivity model (workspace copy made by sdd_model_create).
+// Resident conductivity model (workspace copy made by sdd_model_create).  The
+// walkers read the primitives from each request's DevReq (converted there to
+// the request's centred FP32 coordinates); this copy is the model's device
+// footprint, counted against the workspace while the model is resident.
 struct DevModel {
   int32_t nprims;
   int32_t pad0[3];
