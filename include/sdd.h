@@ -51,8 +51,9 @@ typedef enum {
     SDD_E_CANCELLED = -7   /* the ticket was cancelled */
 } sdd_status;
 
-/* Arithmetic of the walk.  SDD_FP64: every step in FP64 (the plain form,
- * identical decisions to an FP64 reference on the same streams).
+/* Arithmetic of the walk.  SDD_FP64: every step in FP64 (the plain form:
+ * the decisions of an FP64 reference on the same streams, its logarithm and
+ * sine/cosine of the uniforms within 2 ulp of the exact values).
  * SDD_FP32_MIXED: positions, normals, exit test and region lookup in FP32,
  * the phase integral as exact per-region step counts formed in FP64 (models
  * of air plus at most one half-space, box or triangle) or as an exact 64-bit
