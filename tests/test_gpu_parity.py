@@ -354,6 +354,40 @@ def test_sigma_grid_equals_primitive_loop_bitwise(ctx, orc):
         assert ctx.solve(q, records=True, flags=fl)["records"].tobytes() == a["records"].tobytes()
 
 
+def _reversed_triangle(p, k):
+    """p with primitive k (a triangle) entered in the other vertex order."""
+    r = p.regions[k]
+    v = np.asarray(r.params, dtype=np.float64).reshape(3, 2)[::-1].reshape(-1)
+    regions = list(p.regions)
+    regions[k] = W.Region(W.TRIANGLE, tuple(float(x) for x in v), r.sigma)
+    return p.replace(regions=regions)
+
+
+def test_triangle_either_vertex_order(ctx, orc):
+    """A triangle entered clockwise and counter-clockwise is one region: the
+    FP32 walkers (the specialised air + triangle signature, and the generic
+    signature's sigma grid in LDS, in global memory and by the loop) give the
+    two orders the same estimates to far below the Monte-Carlo error (the
+    host orients the edges; the two orders' edge coefficients differ by
+    rounding only), and both orders stay within 3 SE of the FP64 oracle."""
+    tri = W.triangle_request(5, precision=W.FP32_MIXED, M=1024)
+    tri = tri.subset(np.arange(0, tri.n_nodes, max(1, tri.n_nodes // 8))[:8]).with_paths(2048)
+    rev = _reversed_triangle(tri, 1)
+    a, b = ctx.solve(tri), ctx.solve(rev)
+    se = np.hypot(a["se_re"], a["se_im"])
+    assert np.all(np.abs(a["mean"] - b["mean"]) <= 0.05 * se), (np.abs(a["mean"] - b["mean"]) / se).max()
+    o, _ = oracle_solve(orc, tri)
+    assert_within_se(b, o)
+    gen = W.multi_body(seed=1, paths=512, M=1024)
+    k = next(i for i, r in enumerate(gen.regions) if r.kind == W.TRIANGLE)
+    grev = _reversed_triangle(gen, k)
+    for fl in (0, sdd.SDD_FLAG_NO_LDS_GRID, sdd.SDD_FLAG_NO_SIGMA_GRID):
+        log(f"triangle vertex order, generic signature, flags {fl}")
+        x, y = ctx.solve(gen, flags=fl), ctx.solve(grev, flags=fl)
+        se = np.hypot(x["se_re"], x["se_im"])
+        assert np.all(np.abs(x["mean"] - y["mean"]) <= 0.05 * se), fl
+
+
 def test_batch_equals_alone_bitwise(ctx):
     """Uneven node counts, path counts, frequencies, models and precisions in
     one persistent launch: each result is bitwise the one it gets alone."""
