@@ -104,10 +104,10 @@ struct FanJob {
 //   e = fma(A, a, fma(B, b, C))   (FP32)
 // is >= 0, else inc_lt.  Lines are the primitive loop's own: a box side or
 // half-plane a < y0 reads A = 1, B = 0, C = -y0 (e = a - y0 rounded once, so
-// its sign is the compare's), a triangle edge its (A, B, C) from DevReq::pf.
-// A line is negated (A, B, C negated: the FP32 result is exactly -e) or its
-// increments swapped so that each of the loop's tests (e < 0, e >= 0,
-// e <= 0) reads "e >= 0" with the two increments in the right order.  A pure
+// its sign is the compare's), a triangle edge its oriented (A, B, C) from
+// DevReq::pf.  A line's increments are swapped where the loop's test is
+// e < 0, so that every test reads "e >= 0" with the two increments in the
+// right order.  A pure
 // cell has A = B = C = 0 (e = +0) and equal increments.  A cell whose
 // primitives test two lines has bit 30 of inc_ge set (kCellTwo; increments
 // are below 2^30): its increment is inc_ge or inc_lt when e2 < 0 and the

@@ -337,7 +337,7 @@ static sdd_status validate(sdd_ctx *ctx, const sdd_request *r, const HostModel *
 namespace {
 struct GLine {
   float A, B, C;   // e = fma(A, a, fma(B, b, C)) in FP32
-  uint32_t mode;   // 0: in iff e < 0, 1: in iff e >= 0 (triangles: decided per cell)
+  uint32_t mode;   // 0: in iff e < 0, 1: in iff e >= 0
 };
 enum GSign { kGNeg, kGPos, kGCross };
 enum GStat { kGOut, kGIn, kGOne };
@@ -345,7 +345,8 @@ enum GStat { kGOut, kGIn, kGOne };
 // The primitive's inequalities as lines, in the primitive loop's FP32
 // expressions (parameters relative to the centre): a half-plane or box side
 // a < y0 is e = fl(a - y0) < 0 (A = 1, B = 0, C = -y0: the inner fma gives
-// -y0 exactly), whose sign is the compare's; a triangle edge is its (A, B, C).
+// -y0 exactly), whose sign is the compare's; a triangle edge is its oriented
+// (A, B, C).
 int prim_lines(int kind, const float *v, GLine *L) {
   switch (kind) {
     case SDD_HALF_Z_LT: L[0] = {0.f, 1.f, -v[0], 0u}; return 1;   // b < z0
@@ -356,8 +357,8 @@ int prim_lines(int kind, const float *v, GLine *L) {
       L[2] = {0.f, 1.f, -v[2], 1u};   // b >= z0
       L[3] = {0.f, 1.f, -v[3], 0u};   // b < z1
       return 4;
-    default:   // triangle edge m
-      for (int m = 0; m < 3; ++m) L[m] = {v[3 * m], v[3 * m + 1], v[3 * m + 2], 0u};
+    default:   // triangle edge m, oriented: the interior is e >= 0 on all three
+      for (int m = 0; m < 3; ++m) L[m] = {v[3 * m], v[3 * m + 1], v[3 * m + 2], 1u};
       return 3;
   }
 }
@@ -383,13 +384,13 @@ GSign classify(const GLine &L, double a0, double a1, double b0, double b1) {
   return kGCross;
 }
 
-// One test of a point against a line: t = (e' >= 0), e' the edge function
-// (negated when neg: exactly -e in FP32), and the primitive's condition is t
-// (inv = false) or not t (inv = true).  The loop's three tests read:
-// e >= 0 (t), e < 0 (not t), e <= 0 (t on the negated line).
+// One test of a point against a line: t = (e >= 0), e the edge function, and
+// the primitive's condition is t (inv = false) or not t (inv = true).  The
+// loop's two tests read: e >= 0 (t: a box's lower sides, a triangle's oriented
+// edges), e < 0 (not t: half-planes, a box's upper sides).
 struct LineTest {
   GLine line;
-  bool neg, inv;
+  bool inv;
 };
 
 // A primitive over a cell: outside everywhere, inside everywhere, or inside
@@ -400,40 +401,32 @@ struct PrimCell {
   LineTest t[4];
 };
 
-PrimCell prim_cell(int kind, const GLine *L, int nl, double a0, double a1, double b0, double b1) {
+PrimCell prim_cell(const GLine *L, int nl, double a0, double a1, double b0, double b1) {
   PrimCell P{kGOut, 0, {}};
   GSign c[4];
   for (int i = 0; i < nl; ++i) c[i] = classify(L[i], a0, a1, b0, b1);
-  if (kind == SDD_TRIANGLE) {   // edges oriented: inside iff every e >= 0
-    for (int i = 0; i < 3; ++i)
-      if (c[i] == kGNeg) return P;   // outside on the whole cell
-    for (int i = 0; i < 3; ++i)
-      if (c[i] == kGCross) P.t[P.n++] = LineTest{L[i], false, false};
-    P.status = P.n == 0 ? kGIn : kGOne;
-    return P;
-  }
   for (int i = 0; i < nl; ++i) {
     const bool holds = L[i].mode == 0u ? c[i] == kGNeg : c[i] == kGPos;
     const bool fails = L[i].mode == 0u ? c[i] == kGPos : c[i] == kGNeg;
     if (fails) return P;
-    if (!holds) P.t[P.n++] = LineTest{L[i], false, L[i].mode == 0u};
+    if (!holds) P.t[P.n++] = LineTest{L[i], L[i].mode == 0u};
   }
   P.status = P.n == 0 ? kGIn : kGOne;
   return P;
 }
 
 bool same_line(const LineTest &x, const LineTest &y) {
-  return x.neg == y.neg && x.line.A == y.line.A && x.line.B == y.line.B && x.line.C == y.line.C;
+  return x.line.A == y.line.A && x.line.B == y.line.B && x.line.C == y.line.C;
 }
 }  // namespace
 
 static constexpr uint32_t kGridCells = 65536;
 
-// The cell's line in SigmaCell form (negated when the test needs it).
+// The cell's line in SigmaCell form.
 static void put_line(SigmaCell &C, const LineTest &t) {
-  C.A = t.neg ? -t.line.A : t.line.A;
-  C.B = t.neg ? -t.line.B : t.line.B;
-  C.C = t.neg ? -t.line.C : t.line.C;
+  C.A = t.line.A;
+  C.B = t.line.B;
+  C.C = t.line.C;
 }
 
 // Sigma grid of the FP32 walk's generic signature.  Per cell: the primitives
@@ -487,7 +480,7 @@ static void build_sigma_grid(DevReq &q, std::vector<SigmaCell> &grid, std::vecto
       LineTest L[2];
       int nlines = 0;
       for (int k = 0; k < np && !loop; ++k) {
-        pc[k] = prim_cell(q.kind[k], lines[k], nl[k], a0 - da, a1 + da, b0 - db, b1 + db);
+        pc[k] = prim_cell(lines[k], nl[k], a0 - da, a1 + da, b0 - db, b1 + db);
         if (pc[k].status == kGIn) { last = k; break; }
         for (int m = 0; m < pc[k].n && !loop; ++m) {
           int f = -1;
