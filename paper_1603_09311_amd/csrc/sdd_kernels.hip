@@ -3,12 +3,15 @@
 //
 //   walk_plain        FP64, one thread per path, one launch per node (the
 //                     plain form): a wave waits for its longest path.
-//   walk_persist_f64  persistent walker, FP64: identical arithmetic to a
-//                     plain FP64 reference on the same streams.
+//   walk_persist_f64  persistent walker, FP64: the arithmetic of a plain
+//                     FP64 reference on the same streams (the uniforms' log
+//                     and full-turn sine/cosine from sdd_math64.h, within
+//                     2 ulp of the exact values).
 //   walk_persist_f32  persistent walker, FP32-mixed: coordinates relative to
 //                     the domain centre, a conservative exit screen per
 //                     pair of steps (the least distance of three points
-//                     to the walls), compensated FP32 phase; weight and
+//                     to the walls), the phase as exact per-region step
+//                     counts or a 64-bit fixed-point sum; weight and
 //                     reduction in FP64.
 //   reduce_nodes      deterministic FP64 reduction of each node's path records
 //                     to the MC estimate, variance, covariance and SE.
